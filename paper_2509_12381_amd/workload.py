@@ -1,0 +1,231 @@
+"""Seeded synthetic workloads: system constants and initial conditions.
+
+This module is the only code shared by the HIP path and the CPU oracle.  It
+builds the *inputs* of an integration (physical constants in atomic units and
+the 12-component initial states) and holds none of the integrator's or the
+force's arithmetic.
+
+State layout (paper Sec. 2.1, definition of y): components 0-2 are the ion's
+Cartesian coordinates, 3-5 the ion's velocity, 6-8 the atom's coordinates and
+9-11 the atom's velocity.  Ensembles are returned as a float64 array of shape
+(12, n): twelve planes of n trajectories, plane c holding component c.
+
+The trap term follows the paper's Hamiltonian (Sec. 2.1): the ion's
+acceleration along axis k contains -(a_k + 2 q_k cos(Omega t)) Omega^2/4 x_k.
+A trap written as x'' + (Omega^2/4)(a - 2 q cos(Omega t)) x = 0 with
+(a, a, -2a) and (q, q, -2q) on (x, y, z) is the same equation with the
+paper-form q taken as (-q, -q, +2q); ``paul_trap`` does that conversion.
+
+Initial-condition recipe for the thermal, impact-parameter ensembles
+(``thermal_ensemble``), per trajectory i, from one PCG64 stream:
+  * 12 uniforms u[i, 0:12] = (raw64 >> 11) * 2**-53 (numpy ``Generator.random``),
+    drawn row by row, so trajectory i depends only on the seed and i;
+  * five Box-Muller pairs from (u0,u1) ... (u8,u9) give 10 normals, of which the
+    first 9 are the ion position, the ion velocity and the atom velocity (3 each);
+  * u10 gives the impact parameter b = b_max sqrt(u10), u11 the azimuth
+    psi = 2 pi u11 around the atom's direction of flight;
+  * ion position ~ N(0, kT_ion / (m_ion w^2)) per axis with the secular frequency
+    of the x axis, w = (Omega/2) sqrt(a_x + q_x^2 / 2) (paper Sec. 4.1);
+    ion velocity ~ N(0, kT_ion / m_ion); atom velocity ~ N(0, kT_atom / m_atom);
+  * the atom starts on the sphere of radius R0 centred on the ion's initial
+    position, on the straight line along its own velocity that passes the ion at
+    distance b: x_atom = x_ion - sqrt(R0^2 - b^2) v_hat + b (cos psi e1 + sin psi e2).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# CODATA 2018 values used to express SI inputs in atomic units.
+AMU = 1822.888486209            # unified atomic mass unit in electron masses
+KB = 3.166811563e-6             # Boltzmann constant in Hartree per kelvin
+T_AU = 2.4188843265857e-17      # atomic unit of time in seconds
+
+NSTATE = 12
+
+# Observable planes written by both integrators (one float64 plane each).
+OBS_NAMES = (
+    "tend", "status", "nsteps", "nfailed", "bounces", "lifetime", "angle",
+    "transfer", "position", "dist", "ke", "rmin", "hnext",
+)
+NOBS = len(OBS_NAMES)
+OBS = {name: i for i, name in enumerate(OBS_NAMES)}
+
+STATUS_NAMES = {0: "running", 1: "escaped", 2: "tmax", 3: "maxsteps", 4: "hmin", 5: "nonfinite"}
+ST_ESCAPED, ST_TMAX, ST_MAXSTEPS, ST_HMIN, ST_NONFINITE = 1, 2, 3, 4, 5
+
+
+@dataclasses.dataclass
+class System:
+    """Constants of one atom + trapped-ion system, atomic units (paper Sec. 2.1).
+
+    V(r) = -Cn / r^n + Cm / r^m; trap acceleration on the ion along axis k is
+    -(a_k + 2 q_k cos(omega_rf t)) omega_rf^2 / 4 x_k.  ``r_exit`` ends a
+    trajectory once the atom-ion distance exceeds it after the first closest
+    approach (0 disables that exit), ``r_bounce`` is the distance below which an
+    inner turning point counts as a short-range collision ("bounce"),
+    ``max_steps`` caps accepted steps and ``hmax`` the step size (0 means one
+    tenth of the integration span).
+    """
+
+    m_ion: float
+    m_atom: float
+    n: int = 4
+    m: int = 8
+    Cn: float = 0.0
+    Cm: float = 0.0
+    a: tuple = (0.0, 0.0, 0.0)
+    q: tuple = (0.0, 0.0, 0.0)
+    omega_rf: float = 0.0
+    r_exit: float = 0.0
+    r_bounce: float = 20.0
+    max_steps: int = 1_000_000
+    hmax: float = 0.0
+
+    def as_dict(self) -> dict:
+        return dataclasses.asdict(self)
+
+
+@dataclasses.dataclass
+class Workload:
+    """A complete integration request: system, ensemble recipe and tolerances."""
+
+    name: str
+    system: System
+    n: int
+    seed: int
+    t0: float
+    tmax: float
+    rtol: float
+    atol: float
+    T_ion: float
+    T_atom: float
+    R0: float
+    b_max: float
+
+    def initial_states(self, n: int | None = None) -> np.ndarray:
+        """The (12, n) float64 SoA initial states of this workload's ensemble."""
+        return thermal_ensemble(self.system, self.n if n is None else n, self.seed,
+                                self.T_ion, self.T_atom, self.R0, self.b_max)
+
+
+def rf_omega(freq_hz: float) -> float:
+    """Angular radio frequency 2 pi f in inverse atomic time units."""
+    return 2.0 * math.pi * freq_hz * T_AU
+
+
+def paul_trap(a: float, q: float) -> tuple[tuple, tuple]:
+    """Paper-form (a_k, q_k) for the trap x'' + (Omega^2/4)(a - 2q cos Omega t) x = 0
+    on x and y with a_z = -2a, q_z = -2q."""
+    return (a, a, -2.0 * a), (-q, -q, 2.0 * q)
+
+
+def secular_omega_x(system: System) -> float:
+    """Secular frequency of the x axis, (Omega/2) sqrt(a_x + q_x^2/2) (paper Sec. 4.1)."""
+    return 0.5 * system.omega_rf * math.sqrt(system.a[0] + 0.5 * system.q[0] ** 2)
+
+
+def liyb_system(q: float = 0.1, a: float = 0.0, r_exit: float = 1e5) -> System:
+    """6-amu atom and 171-amu ion, C4 = 82, C8 = 4.1e5 (minimum at r = 10 a0), in a
+    2 MHz Paul trap; bounce radius 2 R_e = 20 a0."""
+    ta, tq = paul_trap(a, q)
+    return System(m_ion=171.0 * AMU, m_atom=6.0 * AMU, n=4, m=8, Cn=82.0, Cm=4.1e5,
+                  a=ta, q=tq, omega_rf=rf_omega(2.0e6), r_exit=r_exit, r_bounce=20.0,
+                  max_steps=1_000_000, hmax=0.0)
+
+
+def rf_periods(system: System, k: float) -> float:
+    return k * 2.0 * math.pi / system.omega_rf
+
+
+def thermal_workload(n: int, seed: int = 0, rtol: float = 1e-8, atol: float = 1e-10,
+                     T_atom: float = 1e-3, q: float = 0.1, name: str | None = None) -> Workload:
+    """Thermal ion (0.5 mK) + Maxwell-Boltzmann atom aimed with impact parameter
+    b = b_max sqrt(U) from a sphere of R0 = 1e5 a0 (b_max = 2e4 a0); exit at r > R0
+    after closest approach or after 200 RF periods."""
+    system = liyb_system(q=q)
+    return Workload(name=name or f"thermal-liyb-n{n}", system=system, n=n, seed=seed,
+                    t0=0.0, tmax=rf_periods(system, 200.0), rtol=rtol, atol=atol,
+                    T_ion=0.5e-3, T_atom=T_atom, R0=1e5, b_max=2e4)
+
+
+def small_ensemble() -> Workload:
+    """1,024 trajectories, seed 0, RelTol 1e-8, AbsTol 1e-10."""
+    return thermal_workload(1024, 0, name="liyb-thermal-1k")
+
+
+def full_ensemble() -> Workload:
+    """2^20 trajectories, seed 0, RelTol 1e-8, AbsTol 1e-10."""
+    return thermal_workload(1 << 20, 0, name="liyb-thermal-1M")
+
+
+def _uniform_rows(n: int, seed: int, ncols: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.random((n, ncols))
+
+
+def _box_muller(u1: np.ndarray, u2: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    rad = np.sqrt(-2.0 * np.log1p(-u1))      # 1 - u1 lies in (0, 1]
+    ang = 2.0 * math.pi * u2
+    return rad * np.cos(ang), rad * np.sin(ang)
+
+
+def _perpendicular_basis(vhat: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Two unit vectors completing vhat (rows) to a right-handed orthonormal frame."""
+    ref = np.zeros_like(vhat)
+    use_x = np.abs(vhat[:, 2]) > 0.9
+    ref[~use_x, 2] = 1.0
+    ref[use_x, 0] = 1.0
+    e1 = np.cross(vhat, ref)
+    e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+    e2 = np.cross(vhat, e1)
+    return e1, e2
+
+
+def thermal_ensemble(system: System, n: int, seed: int, T_ion: float, T_atom: float,
+                     R0: float, b_max: float) -> np.ndarray:
+    """(12, n) float64 initial states; the recipe is in the module docstring."""
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    if b_max > R0:
+        raise ValueError("b_max must not exceed R0")
+    u = _uniform_rows(n, seed, 12)
+    normals = np.empty((n, 10))
+    for p in range(5):
+        z0, z1 = _box_muller(u[:, 2 * p], u[:, 2 * p + 1])
+        normals[:, 2 * p] = z0
+        normals[:, 2 * p + 1] = z1
+    w = secular_omega_x(system)
+    sx = math.sqrt(KB * T_ion / system.m_ion) / w if w > 0 else 0.0
+    svi = math.sqrt(KB * T_ion / system.m_ion)
+    sva = math.sqrt(KB * T_atom / system.m_atom)
+    xi = normals[:, 0:3] * sx
+    vi = normals[:, 3:6] * svi
+    va = normals[:, 6:9] * sva
+    b = b_max * np.sqrt(u[:, 10])
+    psi = 2.0 * math.pi * u[:, 11]
+    speed = np.linalg.norm(va, axis=1, keepdims=True)
+    vhat = va / np.where(speed > 0, speed, 1.0)
+    vhat[speed[:, 0] == 0] = (0.0, 0.0, 1.0)
+    e1, e2 = _perpendicular_basis(vhat)
+    along = np.sqrt(R0 * R0 - b * b)[:, None]
+    xa = xi - along * vhat + b[:, None] * (np.cos(psi)[:, None] * e1 + np.sin(psi)[:, None] * e2)
+    y0 = np.empty((NSTATE, n))
+    y0[0:3] = xi.T
+    y0[3:6] = vi.T
+    y0[6:9] = xa.T
+    y0[9:12] = va.T
+    return y0
+
+
+def head_on_state(system: System, r0: float, T_atom: float, theta: float, phi: float) -> np.ndarray:
+    """Ion at rest at the origin, atom at r0 (sin t cos p, sin t sin p, cos t) moving
+    towards it with speed sqrt(3 kT / m_atom) (paper Sec. 2.1, initial conditions)."""
+    v0 = math.sqrt(3.0 * KB * T_atom / system.m_atom)
+    u = np.array([math.sin(theta) * math.cos(phi), math.sin(theta) * math.sin(phi), math.cos(theta)])
+    y = np.zeros(NSTATE)
+    y[6:9] = r0 * u
+    y[9:12] = -v0 * u
+    return y

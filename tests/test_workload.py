@@ -1,0 +1,69 @@
+"""The seeded synthetic ensembles: shapes, determinism and the distributions
+the recipe promises (thermal ion, Maxwell-Boltzmann atom aimed with an impact
+parameter b = b_max sqrt(U) from a sphere of radius R0 around the ion)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2509_12381_amd import workload as W
+
+
+@pytest.fixture(scope="module")
+def ens():
+    wl = W.thermal_workload(20000, seed=11)
+    return wl, wl.initial_states()
+
+
+def test_shape_and_determinism(ens):
+    wl, y0 = ens
+    assert y0.shape == (12, 20000) and y0.dtype == np.float64
+    np.testing.assert_array_equal(y0, wl.initial_states())
+    # trajectory i depends only on the seed and i
+    np.testing.assert_array_equal(y0[:, :500], W.thermal_workload(500, seed=11).initial_states())
+    assert not np.array_equal(y0[:, :500], W.thermal_workload(500, seed=12).initial_states())
+
+
+def test_atom_starts_on_sphere_aimed_with_impact_parameter(ens):
+    wl, y0 = ens
+    d = y0[6:9] - y0[0:3]
+    np.testing.assert_allclose(np.linalg.norm(d, axis=0), wl.R0, rtol=1e-12)
+    vhat = y0[9:12] / np.linalg.norm(y0[9:12], axis=0)
+    along = np.sum(d * vhat, axis=0)
+    assert np.all(along < 0)                         # moving towards the ion
+    b = np.linalg.norm(d - along * vhat, axis=0)
+    assert b.max() <= wl.b_max * (1 + 1e-12)
+    # b^2 / b_max^2 is uniform on [0, 1]
+    assert stats.kstest((b / wl.b_max) ** 2, "uniform").pvalue > 1e-3
+
+
+def test_thermal_widths(ens):
+    wl, y0 = ens
+    s = wl.system
+    w = 0.5 * s.omega_rf * math.sqrt(s.a[0] + 0.5 * s.q[0] ** 2)
+    sig = {
+        "xi": math.sqrt(W.KB * wl.T_ion / s.m_ion) / w,
+        "vi": math.sqrt(W.KB * wl.T_ion / s.m_ion),
+        "va": math.sqrt(W.KB * wl.T_atom / s.m_atom),
+    }
+    for name, rows in (("xi", slice(0, 3)), ("vi", slice(3, 6)), ("va", slice(9, 12))):
+        z = (y0[rows] / sig[name]).ravel()
+        assert stats.kstest(z, "norm").pvalue > 1e-3, name
+    assert sig["xi"] == pytest.approx(6632, rel=1e-3)
+    assert sig["va"] == pytest.approx(5.381e-7, rel=1e-3)
+
+
+def test_paul_trap_form():
+    a, q = W.paul_trap(0.01, 0.1)
+    # paper form -(a_k + 2 q_k cos) equals the trap -(a - 2q cos) on x, y and
+    # -(a_z - 2 q_z cos) with a_z = -2a, q_z = -2q on z
+    for c in (-1.0, 0.3, 1.0):
+        assert a[0] + 2 * q[0] * c == pytest.approx(0.01 - 2 * 0.1 * c)
+        assert a[2] + 2 * q[2] * c == pytest.approx(-0.02 - 2 * (-0.2) * c)
+
+
+def test_units():
+    s = W.liyb_system()
+    assert W.rf_periods(s, 200.0) * W.T_AU == pytest.approx(100e-6, rel=1e-12)
+    assert (2 * s.Cm / s.Cn) ** 0.25 == pytest.approx(10.0)
