@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Throughput of the ensemble integrator on one MI355X.
+
+One step = one call of the C ABI (ai_integrate_async) integrating the whole
+2^20-trajectory thermal Li + Yb+ ensemble (seed 0, RelTol 1e-8, AbsTol 1e-10,
+exit at r > R0 after closest approach or after 200 RF periods) with the
+persistent kernel, inputs already resident in device memory.  W untimed
+warm-up steps, then K timed steps bracketed by device synchronisation; prints
+one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--kernel persistent|plain]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "accepted RK45 steps/s and trajectories/s per MI355X at RelTol 1e-8; p50/p99 latency"
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SYMBOL = {"persistent": "ai_persistent_kernel", "plain": "ai_plain_kernel"}
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for p in ("paper_2509_12381_amd/csrc/ai.hip", "include/ai.h"):
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(KERNEL_SYMBOL[kernel])
+    if not k or rec.get("source_digest") != source_digest():
+        return None
+    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+
+
+def cpu_baseline(wl, y0_host, sample: int):
+    """The oracle as it stands, on the first `sample` trajectories of the same
+    ensemble, with the host threads of this process's CPU share."""
+    import oracle
+    import numpy as np
+    threads = min(16, os.cpu_count() or 1)
+    ys = np.ascontiguousarray(y0_host[:, :sample])
+    t = time.perf_counter()
+    _, ob, _ = oracle.integrate(wl.system, ys, wl.t0, wl.tmax, wl.rtol, wl.atol, nthreads=threads)
+    wall = time.perf_counter() - t
+    steps = float(ob[2].sum())
+    return {"value": steps / wall, "unit": "accepted steps/s", "cores": threads,
+            "kind": "oracle", "sample": f"first {sample} trajectories of the {wl.n}-trajectory "
+            f"ensemble, {wall:.1f} s wall", "trajectories_per_s": sample / wall}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--kernel", choices=("persistent", "plain"), default="persistent")
+    ap.add_argument("--n", type=int, default=None, help="ensemble size (default 2^20)")
+    ap.add_argument("--no-compare", action="store_true", help="skip timing the other kernel")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (HBM counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {max(args.gpus, world)}): the "
+              "trajectories are independent and this build measures one GPU's share",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2509_12381_amd import binding, flops
+    from paper_2509_12381_amd import workload as W
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 3
+    binding.load()
+    dev = torch.device("cuda:0")
+
+    wl = W.full_ensemble()
+    if args.n is not None:
+        wl = W.thermal_workload(args.n, 0, name=f"liyb-thermal-{args.n}")
+    y0_host = wl.initial_states()
+    y0 = torch.from_numpy(y0_host).to(dev)
+    fin = torch.empty_like(y0)
+    obs = torch.empty((W.NOBS, wl.n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_calibration_mib:
+        nel = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def call(kernel):
+        return binding.ai_integrate_async(wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, fin,
+                                          obs, kernel=kernel, stream=stream)
+
+    def timed(kernel, steps, warmup):
+        for _ in range(warmup):
+            call(kernel)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        t_start.record(stream)
+        for a, b in ev:
+            a.record(stream)
+            call(kernel)
+            b.record(stream)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        per = [a.elapsed_time(b) for a, b in ev]
+        return t_start.elapsed_time(t_end), per, wall
+
+    total_ms, per_ms, wall = timed(args.kernel, args.steps, args.warmup)
+    ob = obs.cpu().numpy()
+    nsteps = float(ob[W.OBS["nsteps"]].sum())
+    nfailed = float(ob[W.OBS["nfailed"]].sum())
+    flop = flops.algorithmic_flops(ob)
+    ms_per_step = total_ms / args.steps
+    value = nsteps * args.steps / (total_ms / 1e3)
+    launch_ms = float(np.mean(per_ms))
+    achieved = flop / (launch_ms / 1e3) / 1e12
+    status = np.bincount(ob[W.OBS["status"]].astype(int), minlength=6)[1:].tolist()
+
+    info = binding.ai_get_kernel_info(args.kernel)
+    other = None
+    if not args.no_compare:
+        okernel = "plain" if args.kernel == "persistent" else "persistent"
+        o_total, o_per, _ = timed(okernel, max(1, min(args.steps, 5)), 1)
+        o_ms = o_total / max(1, min(args.steps, 5))
+        other = {"kernel": okernel, "ms_per_step": o_ms,
+                 "steps_per_s": nsteps / (o_ms / 1e3),
+                 "speedup_of_timed_kernel": o_ms / ms_per_step,
+                 "kernel_info": binding.ai_get_kernel_info(okernel)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, y0_host, min(args.cpu_sample, wl.n))
+
+    traffic = measured_traffic(args.kernel)
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "accepted steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: seeded thermal Li(6 amu) + Yb+(171 amu) ensemble, impact-parameter "
+                "sampling, generated on the host",
+        "config": {"workload": wl.name, "trajectories": wl.n, "seed": wl.seed,
+                   "rtol": wl.rtol, "atol": wl.atol, "kernel": args.kernel,
+                   "tmax_rf_periods": 200, "R0_a0": wl.R0, "b_max_a0": wl.b_max},
+        "trajectories_per_s": wl.n * args.steps / (total_ms / 1e3),
+        "latency_ms": {"p50": float(np.percentile(per_ms, 50)),
+                       "p99": float(np.percentile(per_ms, 99)),
+                       "what": "one ensemble call, enqueue to completion on the stream"},
+        "accepted_steps_per_call": nsteps,
+        "rejected_attempts_per_call": nfailed,
+        "status_counts": dict(zip(("escaped", "tmax", "maxsteps", "hmin", "nonfinite"), status)),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": traffic, "kernel": KERNEL_SYMBOL[args.kernel],
+                     "flop_per_launch": flop, "launch_ms": launch_ms},
+        "kernel_info": info,
+        "other_kernel": other,
+        "cpu_baseline": cpu,
+        "wall_s_timed_region": wall,
+    }
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,143 @@
+/*
+ * ai.h -- C ABI of libai.so: ensemble Dormand-Prince 5(4) integration of
+ * atom + trapped-ion trajectories on an AMD Instinct MI355X (gfx950).
+ *
+ * Method (arXiv 2509.12381):
+ *   - state y = (x_ion, v_ion, x_atom, v_atom), 12 components (Sec. 2.1,
+ *     definition of y);
+ *   - y' = f(t, y) with the atom-ion force of V(r) = -Cn/r^n + Cm/r^m and the
+ *     Paul-trap term -(a_k + 2 q_k cos(omega_rf t)) omega_rf^2/4 x_k on the ion
+ *     (Sec. 2.1, equation for f; general n, m in Sec. 4.1);
+ *   - the ode45 algorithm (Fig. 2: Dormand-Prince 5(4) pair, initial step,
+ *     weighted infinity-norm error test against RelTol/AbsTol, step-size
+ *     control), one call integrating many independent trajectories, each from
+ *     t0 to its own exit (Sec. 3.2 and 3.3: the arrayfun launch over arrays
+ *     of initial conditions, outputs the end time, the final state and scalar
+ *     observables);
+ *   - the observables of Sec. 4.1 (angle, bounces, lifetime, position,
+ *     transfer, dist, nsteps, KE) accumulated on the fly.
+ *
+ * Units are atomic units throughout.  All entry points are thread-safe; calls
+ * on different streams are independent.
+ */
+#ifndef AI_H
+#define AI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AI_NSTATE 12 /* state components per trajectory */
+#define AI_NOBS 13   /* observable planes per trajectory */
+
+/* Constants of the atom + trapped-ion system (Sec. 2.1 Hamiltonian; Sec. 4.1
+ * inputs).  Exit rule: a trajectory ends once the atom-ion distance exceeds
+ * r_exit after its first closest approach (a sign change of
+ * (x_ion - x_atom) . (v_ion - v_atom) from negative to non-negative between
+ * accepted steps, or a non-negative value at t0); r_exit = 0 disables it. */
+typedef struct ai_params {
+  double m_ion, m_atom;  /* masses (electron masses), > 0 */
+  int32_t n, m;          /* exponents of V(r) = -Cn/r^n + Cm/r^m; this build runs n=4, m=8 */
+  double Cn, Cm;         /* coefficients (C4 and C8 for n=4, m=8) */
+  double a[3], q[3];     /* Paul-trap parameters per axis, paper form */
+  double omega_rf;       /* trap radio frequency (inverse atomic time) */
+  double r_exit;         /* exit radius after closest approach, >= 0; 0 = off */
+  double r_bounce;       /* a closest approach inside this radius is a bounce */
+  int64_t max_steps;     /* cap on accepted steps per trajectory, >= 1 (paper: 10^6) */
+  double hmax;           /* step-size cap; 0 selects 0.1 (tmax - t0) */
+} ai_params;
+
+/* Observable planes of obs (index c of obs[c * ld + i]).  Counts are stored
+ * as exact doubles. */
+enum ai_obs {
+  AI_OBS_TEND = 0,     /* end time of the trajectory */
+  AI_OBS_STATUS = 1,   /* enum ai_status */
+  AI_OBS_NSTEPS = 2,   /* accepted steps */
+  AI_OBS_NFAILED = 3,  /* rejected attempts */
+  AI_OBS_BOUNCES = 4,  /* closest approaches inside r_bounce */
+  AI_OBS_LIFETIME = 5, /* time from first to last bounce if bounces >= 2, else 0 */
+  AI_OBS_ANGLE = 6,    /* angle between the atom's initial and final velocity */
+  AI_OBS_TRANSFER = 7, /* m_atom |v_atom(end) - v_atom(t0)| */
+  AI_OBS_POSITION = 8, /* |x_ion| at the first bounce, 0 if none */
+  AI_OBS_DIST = 9,     /* final atom-ion distance */
+  AI_OBS_KE = 10,      /* final ion kinetic energy */
+  AI_OBS_RMIN = 11,    /* smallest atom-ion distance seen at t0 and accepted steps */
+  AI_OBS_HNEXT = 12    /* step size the controller proposes next */
+};
+
+/* Per-trajectory end status (never an error return). */
+enum ai_status {
+  AI_ST_ESCAPED = 1,   /* r > r_exit after closest approach */
+  AI_ST_TMAX = 2,      /* reached tmax exactly */
+  AI_ST_MAXSTEPS = 3,  /* max_steps accepted steps */
+  AI_ST_HMIN = 4,      /* rejected at the smallest step 16 eps(t) */
+  AI_ST_NONFINITE = 5  /* non-finite initial state, force or error estimate */
+};
+
+enum ai_kernel {
+  AI_KERNEL_PLAIN = 0,     /* one trajectory per lane, grid covers n */
+  AI_KERNEL_PERSISTENT = 1 /* resident waves refill exited lanes from a device queue */
+};
+
+enum ai_rc {
+  AI_OK = 0,
+  AI_WRTOL = 1,          /* warning: rtol below 100 eps was raised to 100 eps (as ode45 does) */
+  AI_EINVAL = -1,        /* invalid argument; nothing was launched */
+  AI_EHIP = -2,          /* HIP runtime error; text in ai_last_error() */
+  AI_ENOMEM = -3,        /* device allocation failed */
+  AI_EUNSUPPORTED = -4   /* valid request this build does not run (exponents other than 4, 8) */
+};
+
+/* Integrate trajectories i = 0 .. n-1 and wait for the result.
+ *
+ * y0, final_state: device pointers to 12 planes, element (i, c) at ptr[c * ld + i];
+ *   y0 is read only; final_state may equal y0 (in place) but must not overlap
+ *   it otherwise.  final_state receives the state at the end time.
+ * obs: device pointer to AI_NOBS planes with the same leading dimension ld;
+ *   must not overlap y0 or final_state.
+ * n >= 0 trajectories, ld >= n; n = 0 returns AI_OK without launching.
+ * t0 < tmax, both finite: every trajectory starts at t0 and stops at tmax at
+ *   the latest.  rtol > 0 and atol > 0 are ode45's RelTol and scalar AbsTol.
+ * kernel: enum ai_kernel; both give bitwise-identical per-trajectory results.
+ * The caller owns every buffer.  Returns AI_OK, AI_WRTOL or a negative
+ * ai_rc; a failing call leaves the outputs unspecified. */
+int ai_integrate(const ai_params *p, const double *y0, int64_t n, int64_t ld, double t0,
+                 double tmax, double rtol, double atol, double *final_state, double *obs,
+                 int32_t kernel);
+
+/* As ai_integrate, but enqueued on `stream` (a hipStream_t; NULL is the null
+ * stream) and returning at once.  Buffers must stay allocated until the work
+ * on the stream has completed; the library keeps no pointer after that.
+ * The persistent kernel takes an 8-byte queue counter from the stream-ordered
+ * allocator for the duration of the call. */
+int ai_integrate_async(const ai_params *p, const double *y0, int64_t n, int64_t ld, double t0,
+                       double tmax, double rtol, double atol, double *final_state, double *obs,
+                       int32_t kernel, void *stream);
+
+/* Launch facts of one kernel on the current device. */
+typedef struct ai_kernel_info {
+  int32_t block_threads;      /* threads per workgroup */
+  int32_t vgprs;              /* vector registers per lane */
+  int32_t spill_bytes;        /* private (scratch) bytes per lane; 0 = no spills */
+  int32_t blocks_per_cu;      /* resident workgroups per CU at this register use */
+  int32_t waves_per_simd;     /* resident waves per SIMD */
+  int32_t compute_units;      /* CUs of the device */
+  int64_t persistent_blocks;  /* grid of the persistent kernel */
+} ai_kernel_info;
+
+/* Fill *info for enum ai_kernel `kernel`.  Returns AI_OK or a negative ai_rc. */
+int ai_get_kernel_info(int32_t kernel, ai_kernel_info *info);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *ai_last_error(void);
+
+int ai_nobs(void);    /* AI_NOBS */
+int ai_version(void); /* library version, > 0 */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AI_H */

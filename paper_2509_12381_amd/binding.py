@@ -1,0 +1,177 @@
+"""Python binding of libai.so (the C ABI in include/ai.h): argument
+marshalling only.  Every step of the integration runs in the HIP kernels.
+
+The entry points keep the C names.  Buffers are torch CUDA (HIP) float64
+tensors laid out as planes: y0 and final_state of shape (12, ld), obs of
+shape (13, ld), contiguous, so plane c starts at c * ld.  If the library has
+not been built, or does not load, every call raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libai.so")
+
+NSTATE = 12
+NOBS = 13
+KERNELS = {"plain": 0, "persistent": 1}
+OK, WRTOL, EINVAL, EHIP, ENOMEM, EUNSUPPORTED = 0, 1, -1, -2, -3, -4
+
+# exported symbols of the C ABI, in declaration order
+SYMBOLS = ("ai_integrate", "ai_integrate_async", "ai_get_kernel_info", "ai_last_error",
+           "ai_nobs", "ai_version")
+
+
+class AiParams(C.Structure):
+    _fields_ = [
+        ("m_ion", C.c_double), ("m_atom", C.c_double),
+        ("n", C.c_int32), ("m", C.c_int32),
+        ("Cn", C.c_double), ("Cm", C.c_double),
+        ("a", C.c_double * 3), ("q", C.c_double * 3),
+        ("omega_rf", C.c_double), ("r_exit", C.c_double), ("r_bounce", C.c_double),
+        ("max_steps", C.c_int64), ("hmax", C.c_double),
+    ]
+
+
+class AiKernelInfo(C.Structure):
+    _fields_ = [
+        ("block_threads", C.c_int32), ("vgprs", C.c_int32), ("spill_bytes", C.c_int32),
+        ("blocks_per_cu", C.c_int32), ("waves_per_simd", C.c_int32),
+        ("compute_units", C.c_int32), ("persistent_blocks", C.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class AiError(RuntimeError):
+    def __init__(self, rc: int, msg: str):
+        super().__init__(f"libai error {rc}: {msg}")
+        self.rc = rc
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Open libai.so; raises if it is missing (build it with
+    ``python -m paper_2509_12381_amd.build``)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise FileNotFoundError(f"{path} is not built; run python -m paper_2509_12381_amd.build")
+        lib = C.CDLL(path)
+        _P = C.POINTER(AiParams)
+        _D = C.c_void_p
+        args = [_P, _D, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double,
+                _D, _D, C.c_int32]
+        lib.ai_integrate.argtypes = args
+        lib.ai_integrate.restype = C.c_int
+        lib.ai_integrate_async.argtypes = args + [C.c_void_p]
+        lib.ai_integrate_async.restype = C.c_int
+        lib.ai_get_kernel_info.argtypes = [C.c_int32, C.POINTER(AiKernelInfo)]
+        lib.ai_get_kernel_info.restype = C.c_int
+        lib.ai_last_error.restype = C.c_char_p
+        lib.ai_nobs.restype = C.c_int
+        lib.ai_version.restype = C.c_int
+        _lib = lib
+        return lib
+
+
+def params(system) -> AiParams:
+    """ai_params from any object (or mapping) with the System fields."""
+    get = (lambda k: system[k]) if isinstance(system, dict) else (lambda k: getattr(system, k))
+    p = AiParams()
+    p.m_ion, p.m_atom = float(get("m_ion")), float(get("m_atom"))
+    p.n, p.m = int(get("n")), int(get("m"))
+    p.Cn, p.Cm = float(get("Cn")), float(get("Cm"))
+    for k in range(3):
+        p.a[k] = float(get("a")[k])
+        p.q[k] = float(get("q")[k])
+    p.omega_rf = float(get("omega_rf"))
+    p.r_exit, p.r_bounce = float(get("r_exit")), float(get("r_bounce"))
+    p.max_steps = int(get("max_steps"))
+    p.hmax = float(get("hmax"))
+    return p
+
+
+def _planes(t, rows: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or t.dim() != 2 or t.shape[0] != rows or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 tensor of shape ({rows}, ld)")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    return t.data_ptr(), t.shape[1]
+
+
+def _args(system, y0, n, t0, tmax, rtol, atol, final_state, obs, kernel):
+    p0, ld = _planes(y0, NSTATE, "y0")
+    p1, ld1 = _planes(final_state, NSTATE, "final_state")
+    p2, ld2 = _planes(obs, NOBS, "obs")
+    if not (ld == ld1 == ld2):
+        raise ValueError("y0, final_state and obs must share the leading dimension")
+    n = ld if n is None else int(n)
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    p = system if isinstance(system, AiParams) else params(system)
+    return (C.byref(p), p0, n, ld, float(t0), float(tmax), float(rtol), float(atol), p1, p2, k)
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise AiError(rc, load().ai_last_error().decode())
+    return rc
+
+
+def ai_integrate(system, y0, t0, tmax, rtol, atol, final_state, obs, kernel="plain", n=None):
+    """Blocking ai_integrate.  Returns AI_OK or AI_WRTOL; raises on errors."""
+    return _check(load().ai_integrate(*_args(system, y0, n, t0, tmax, rtol, atol, final_state,
+                                             obs, kernel)))
+
+
+def ai_integrate_async(system, y0, t0, tmax, rtol, atol, final_state, obs, kernel="plain",
+                       n=None, stream=None):
+    """ai_integrate_async on `stream` (a torch.cuda.Stream; default: torch's
+    current stream)."""
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _check(load().ai_integrate_async(*_args(system, y0, n, t0, tmax, rtol, atol,
+                                                   final_state, obs, kernel),
+                                            C.c_void_p(s.cuda_stream)))
+
+
+def ai_get_kernel_info(kernel="plain") -> dict:
+    info = AiKernelInfo()
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    _check(load().ai_get_kernel_info(k, C.byref(info)))
+    return info.as_dict()
+
+
+def ai_last_error() -> str:
+    return load().ai_last_error().decode()
+
+
+def ai_nobs() -> int:
+    return load().ai_nobs()
+
+
+def ai_version() -> int:
+    return load().ai_version()
+
+
+def integrate(system, y0, t0, tmax, rtol, atol, kernel="plain", stream=None):
+    """Allocate outputs next to y0 (a (12, n) GPU tensor), enqueue the
+    integration on the current stream and return (final_state, obs, rc)."""
+    import torch
+    final_state = torch.empty_like(y0)
+    obs = torch.empty((NOBS, y0.shape[1]), dtype=torch.float64, device=y0.device)
+    rc = ai_integrate_async(system, y0, t0, tmax, rtol, atol, final_state, obs, kernel,
+                            stream=stream)
+    return final_state, obs, rc

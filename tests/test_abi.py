@@ -1,0 +1,72 @@
+"""The C ABI library loads on a host without a GPU and exports every entry
+point include/ai.h declares (no compute calls are made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ai.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(ai_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2509_12381_amd import binding, build
+    if build.stale():
+        build.build()
+    return ctypes.CDLL(binding.LIB_PATH)
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    assert names == sorted(["ai_integrate", "ai_integrate_async", "ai_get_kernel_info",
+                            "ai_last_error", "ai_nobs", "ai_version"])
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header():
+    from paper_2509_12381_amd import binding
+    assert sorted(binding.SYMBOLS) == declared_functions()
+    for name in declared_functions():
+        assert callable(getattr(binding, name))
+
+
+def test_struct_layout_matches_header():
+    from paper_2509_12381_amd import binding
+    # ai_params: 2 doubles, 2 int32, 2 doubles, 2 x 3 doubles, 3 doubles, int64, double
+    assert ctypes.sizeof(binding.AiParams) == 8 * 2 + 4 * 2 + 8 * 2 + 8 * 6 + 8 * 3 + 8 + 8
+    assert binding.AiParams.max_steps.offset == 8 * 2 + 4 * 2 + 8 * 2 + 8 * 6 + 8 * 3
+    assert ctypes.sizeof(binding.AiKernelInfo) == 6 * 4 + 8
+
+
+def test_constants_without_gpu(lib):
+    lib.ai_nobs.restype = ctypes.c_int
+    lib.ai_version.restype = ctypes.c_int
+    assert lib.ai_nobs() == 13
+    assert lib.ai_version() >= 1
+
+
+def test_invalid_arguments_are_refused_before_any_device_call(lib):
+    from paper_2509_12381_amd import binding
+    from paper_2509_12381_amd import workload as W
+    b = binding.load()
+    p = binding.params(W.liyb_system())
+    # tmax <= t0 is refused during validation, before any HIP call
+    rc = b.ai_integrate(ctypes.byref(p), None, 0, 0, 1.0, 0.0, 1e-8, 1e-10, None, None, 0)
+    assert rc == binding.EINVAL
+    assert "t0 < tmax" in binding.ai_last_error()
+    rc = b.ai_integrate(ctypes.byref(p), None, -1, 0, 0.0, 1.0, 1e-8, 1e-10, None, None, 0)
+    assert rc == binding.EINVAL
+    rc = b.ai_integrate(ctypes.byref(p), None, 0, 0, 0.0, 1.0, 1e-8, 1e-10, None, None, 7)
+    assert rc == binding.EINVAL
