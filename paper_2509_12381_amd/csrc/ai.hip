@@ -38,53 +38,64 @@
 namespace {
 
 // ---------------------------------------------------------------------------
-// Dormand-Prince 5(4) coefficients (Dormand and Prince 1980; the pair ode45
-// uses, Sec. 1 and Fig. 2 caption).  Row 7 of a equals the fifth-order
-// weights b, so stage 7 is f at the new solution (first same as last); the
-// error weights are e = b - bhat.
+// Dormand-Prince 5(4) pair (Dormand and Prince 1980; the pair ode45 uses,
+// Sec. 1 and Fig. 2 caption).  Nodes c, weights b of the propagated
+// fifth-order solution and error weights e = b - bhat.
 constexpr double C2 = 1.0 / 5.0, C3 = 3.0 / 10.0, C4 = 4.0 / 5.0, C5 = 8.0 / 9.0;
-constexpr double A21 = 1.0 / 5.0;
-constexpr double A31 = 3.0 / 40.0, A32 = 9.0 / 40.0;
-constexpr double A41 = 44.0 / 45.0, A42 = -56.0 / 15.0, A43 = 32.0 / 9.0;
-constexpr double A51 = 19372.0 / 6561.0, A52 = -25360.0 / 2187.0, A53 = 64448.0 / 6561.0,
-                 A54 = -212.0 / 729.0;
-constexpr double A61 = 9017.0 / 3168.0, A62 = -355.0 / 33.0, A63 = 46732.0 / 5247.0,
-                 A64 = 49.0 / 176.0, A65 = -5103.0 / 18656.0;
-constexpr double A71 = 35.0 / 384.0, A73 = 500.0 / 1113.0, A74 = 125.0 / 192.0,
-                 A75 = -2187.0 / 6784.0, A76 = 11.0 / 84.0;
+constexpr double B1 = 35.0 / 384.0, B3 = 500.0 / 1113.0, B4 = 125.0 / 192.0,
+                 B5 = -2187.0 / 6784.0, B6 = 11.0 / 84.0;
 constexpr double E1 = 71.0 / 57600.0, E3 = -71.0 / 16695.0, E4 = 71.0 / 1920.0,
                  E5 = -17253.0 / 339200.0, E6 = 22.0 / 525.0, E7 = -1.0 / 40.0;
+
+// The force depends on positions and time only (Sec. 2.1), so the stage
+// velocities of the 12-component system never need to be formed: with A the
+// pair's stage matrix, the stage positions are
+//   X_s = x + c_s h v + h^2 sum_l (A^2)_sl F_l,
+// the new position x + h v + h^2 sum_l (bA)_l F_l (stage 7's position), the
+// new velocity v + h sum_l b_l F_l, and the error vector's position part
+// sum_j e_j V_j = h sum_l (eA)_l F_l (the e_j sum to zero).  These equal the
+// 12-component stage formulas exactly in exact arithmetic; the entries
+// below are the exact rationals of A^2, bA and eA.
+constexpr double Q31 = 9.0 / 200.0;
+constexpr double Q41 = -12.0 / 25.0, Q42 = 4.0 / 5.0;
+constexpr double Q51 = -12248.0 / 6561.0, Q52 = 7208.0 / 2187.0, Q53 = -6784.0 / 6561.0;
+constexpr double Q61 = -533.0 / 264.0, Q62 = 91.0 / 22.0, Q63 = -56.0 / 33.0, Q64 = 7.0 / 88.0;
+constexpr double Q71 = 35.0 / 384.0, Q73 = 50.0 / 159.0, Q74 = 25.0 / 192.0,
+                 Q75 = -243.0 / 6784.0;  // (bA)_2 = (bA)_6 = 0
+constexpr double P1 = 611.0 / 230400.0, P3 = -514.0 / 83475.0, P4 = 391.0 / 38400.0,
+                 P5 = -4617.0 / 1356800.0, P6 = -11.0 / 3360.0;  // (eA)_l, (eA)_2 = 0
 
 constexpr int WAVE = 64;
 constexpr int BLOCK = 64;  // one wave per workgroup: a finished wave frees its slot at once
 
 // Launch constants: the system constants folded into the forms the force and
-// the controller use, computed once per call on the host.  Passed by value, so
-// they sit in scalar registers, uniform across the wave.
+// the controller use, computed once per call on the host.  Passed by value,
+// so they sit in scalar registers, uniform across the wave.
 struct Launch {
   double inv_mi, inv_ma;     // 1/m_ion, 1/m_atom
   double nCn, mCm;           // 4 C4 and 8 C8: (dV/dr)/r = s^3 (4 C4 - 8 C8 s^2), s = 1/r^2
-  double ka[3], kq[3];       // trap: kappa_k(t) = ka_k + kq_k cos(omega t) = (a_k + 2 q_k cos) omega^2/4
+  double ka[3], kq[3];       // kappa_k(t) = ka_k + kq_k cos(omega t) = (a_k + 2 q_k cos) omega^2/4
   double omega;
   double r_exit2, r_bounce2;
   double half_mi, m_atom;    // for the observables
-  double t0, tf, hmax, rtol, thr;
+  double t0, tf, hmax, rtol, inv_rtol, thr;
   double hinit_den;          // 0.8 rtol^(1/5)
-  long long max_steps;
   long long n, ld;
   long long first_dynamic;   // persistent kernel: first index handed out by the queue
+  int max_steps;
   int exit_on;               // r_exit > 0
 };
 
-// Per-lane integration state.
+// Per-lane integration state.  x and v hold (ion, atom) positions and
+// velocities, F1 the accelerations at (t, x): the first stage of the next
+// attempt (first same as last).  The step size h always equals absh here
+// (integration runs forward), and the step floor 16 eps(t) is recomputed.
 struct Lane {
-  double y[12];
-  double k1[12];
-  double t, h, absh, hmin;
-  double va0[3];
-  double w_prev, t_first, t_last, position, rmin2, r2;
-  long long nsteps, nfailed, bounces;
-  int status;
+  double x[6], v[6], F1[6];
+  double t, absh;
+  double w_prev, t_first, t_last, position, rmin2;
+  long long nfailed;
+  int nsteps, bounces, status;
   bool done, nofailed, fresh, approached;
 };
 
@@ -94,53 +105,126 @@ __device__ __forceinline__ double spacing(double t) {
   return __longlong_as_double(__double_as_longlong(at) + 1) - at;
 }
 
-// f(t, y) of Sec. 2.1 for V(r) = -C4/r^4 + C8/r^8.  cosrf = cos(omega t).
-// Returns r^2 of the input state.
-__device__ __forceinline__ double force(const Launch& P, double cosrf, const double* y,
-                                        double* f) {
-  const double dx = y[0] - y[6], dy = y[1] - y[7], dz = y[2] - y[8];
+// 1/a: hardware reciprocal estimate refined by two Newton steps.
+__device__ __forceinline__ double recip(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-a, r, 1.0);
+  return fma(r, e, r);
+}
+
+// cos(x) for |x| < 2^31 pi/2 (checked on the host).  Cody-Waite reduction
+// x = n pi/2 + r with pi/2 split into two doubles (the first product is exact
+// under the fused multiply-add, the split error is 1.5e-33 per unit of n),
+// then the Taylor series of cos and sin on |r| <= pi/4, truncated after
+// r^16 and r^17 (remainders below 3e-18).
+__device__ __forceinline__ double cos_rf(double x) {
+  constexpr double TWO_OVER_PI = 0.63661977236758134;  // 2/pi rounded
+  constexpr double PIO2_HI = 1.5707963267948966;       // pi/2 rounded
+  constexpr double PIO2_LO = 6.123233995736766e-17;    // pi/2 - PIO2_HI rounded
+  const double n = rint(x * TWO_OVER_PI);
+  double r = fma(-n, PIO2_HI, x);
+  r = fma(-n, PIO2_LO, r);
+  const int q = (int)n;
+  const double r2 = r * r;
+  double c = 1.0 / 20922789888000.0;                     // 1/16!
+  c = fma(c, r2, -1.0 / 87178291200.0);                  // -1/14!
+  c = fma(c, r2, 1.0 / 479001600.0);                     // 1/12!
+  c = fma(c, r2, -1.0 / 3628800.0);                      // -1/10!
+  c = fma(c, r2, 1.0 / 40320.0);                         // 1/8!
+  c = fma(c, r2, -1.0 / 720.0);                          // -1/6!
+  c = fma(c, r2, 1.0 / 24.0);                            // 1/4!
+  c = fma(c, r2, -0.5);                                  // -1/2!
+  c = fma(c, r2, 1.0);
+  double s = 1.0 / 355687428096000.0;                    // 1/17!
+  s = fma(s, r2, -1.0 / 1307674368000.0);                // -1/15!
+  s = fma(s, r2, 1.0 / 6227020800.0);                    // 1/13!
+  s = fma(s, r2, -1.0 / 39916800.0);                     // -1/11!
+  s = fma(s, r2, 1.0 / 362880.0);                        // 1/9!
+  s = fma(s, r2, -1.0 / 5040.0);                         // -1/7!
+  s = fma(s, r2, 1.0 / 120.0);                           // 1/5!
+  s = fma(s, r2, -1.0 / 6.0);                            // -1/3!
+  s = s * r2;
+  s = fma(s, r, r);
+  // cos(q pi/2 + r) = cos r, -sin r, -cos r, sin r for q = 0, 1, 2, 3 (mod 4)
+  const double v = (q & 1) ? s : c;
+  return ((q + 1) & 2) ? -v : v;
+}
+
+// (err/rtol)^(-1/5) for the step-size controller.  Arguments are clamped to
+// [1e-30, 1e30]: outside it the controller's own limits (growth at most 5x,
+// shrink at least 0.1x) decide.  A single-precision estimate is refined by
+// two Newton steps of w <- w (6 - q w^5) / 5 (quadratic convergence from
+// ~1e-7 relative error).
+__device__ __forceinline__ double inv_fifth_root(double q) {
+  q = fmin(fmax(q, 1e-30), 1e30);
+  double w = (double)__builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf((float)q));
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double w2 = w * w;
+    const double w5 = w2 * w2 * w;
+    w = w * fma(-q, w5, 6.0) * 0.2;
+  }
+  return w;
+}
+
+// Accelerations F(t, X) of Sec. 2.1 for V(r) = -C4/r^4 + C8/r^8:
+// F_ion = -(g/m_ion) d - kappa(t) x_ion, F_atom = (g/m_atom) d with
+// d = x_ion - x_atom and g = (dV/dr)/r.  cosrf = cos(omega t).  Returns r^2
+// and d.
+__device__ __forceinline__ double accel(const Launch& P, double cosrf, const double* X,
+                                        double* F, double& dx, double& dy, double& dz) {
+  dx = X[0] - X[3];
+  dy = X[1] - X[4];
+  dz = X[2] - X[5];
   const double r2 = dx * dx + dy * dy + dz * dz;
-  const double s = 1.0 / r2;
+  const double s = recip(r2);
   const double s2 = s * s;
-  const double g = s2 * s * (P.nCn - P.mCm * s2);  // (dV/dr) / r
+  const double g = s2 * s * (P.nCn - P.mCm * s2);
   const double gi = g * P.inv_mi, ga = g * P.inv_ma;
-  f[0] = y[3];
-  f[1] = y[4];
-  f[2] = y[5];
-  f[3] = -gi * dx - (P.ka[0] + P.kq[0] * cosrf) * y[0];
-  f[4] = -gi * dy - (P.ka[1] + P.kq[1] * cosrf) * y[1];
-  f[5] = -gi * dz - (P.ka[2] + P.kq[2] * cosrf) * y[2];
-  f[6] = y[9];
-  f[7] = y[10];
-  f[8] = y[11];
-  f[9] = ga * dx;
-  f[10] = ga * dy;
-  f[11] = ga * dz;
+  F[0] = -gi * dx - (P.ka[0] + P.kq[0] * cosrf) * X[0];
+  F[1] = -gi * dy - (P.ka[1] + P.kq[1] * cosrf) * X[1];
+  F[2] = -gi * dz - (P.ka[2] + P.kq[2] * cosrf) * X[2];
+  F[3] = ga * dx;
+  F[4] = ga * dy;
+  F[5] = ga * dz;
   return r2;
 }
 
 // Start of trajectory idx: load its y0 column, f(t0, y0), ode45's initial
 // step and the observables' initial values.
-__device__ __forceinline__ void start(const Launch& P, const double* __restrict__ y0,
-                                      long long idx, Lane& L) {
+__device__ __forceinline__ void start(const Launch& P, const double* y0, long long idx,
+                                      Lane& L) {
+  double y[12];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) L.y[c] = y0[c * P.ld + idx];
+  for (int c = 0; c < 12; ++c) y[c] = y0[c * P.ld + idx];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    L.x[k] = y[k];
+    L.v[k] = y[3 + k];
+    L.x[3 + k] = y[6 + k];
+    L.v[3 + k] = y[9 + k];
+  }
+  double dx, dy, dz;
+  const double r2 = accel(P, cos_rf(P.omega * P.t0), L.x, L.F1, dx, dy, dz);
   L.t = P.t0;
-  L.r2 = force(P, cos(P.omega * P.t0), L.y, L.k1);
-  L.nsteps = L.nfailed = L.bounces = 0;
+  L.nsteps = L.bounces = 0;
+  L.nfailed = 0;
   L.status = 0;
   L.fresh = true;
   L.done = false;
   L.nofailed = true;
-  L.h = 0.0;
-  L.hmin = 0.0;
 
+  // initial step: the weighted first-order increment h f(t0, y0) equals
+  // 0.8 rtol^(1/5); position derivatives are the velocities
   bool finite = true;
   double rh = 0.0;
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    finite = finite && isfinite(L.y[c]) && isfinite(L.k1[c]);
-    rh = fmax(rh, fabs(L.k1[c]) / fmax(fabs(L.y[c]), P.thr));
+  for (int c = 0; c < 6; ++c) {
+    finite = finite && isfinite(L.x[c]) && isfinite(L.v[c]) && isfinite(L.F1[c]);
+    rh = fmax(rh, fabs(L.v[c]) / fmax(fabs(L.x[c]), P.thr));
+    rh = fmax(rh, fabs(L.F1[c]) / fmax(fabs(L.v[c]), P.thr));
   }
   rh = rh / P.hinit_den;
   double absh = fmin(P.hmax, P.tf - P.t0);
@@ -148,102 +232,122 @@ __device__ __forceinline__ void start(const Launch& P, const double* __restrict_
   L.absh = fmax(absh, 16.0 * spacing(P.t0));
   if (!finite) L.status = AI_ST_NONFINITE;
 
-  const double dx = L.y[0] - L.y[6], dy = L.y[1] - L.y[7], dz = L.y[2] - L.y[8];
-  const double w = dx * (L.y[3] - L.y[9]) + dy * (L.y[4] - L.y[10]) + dz * (L.y[5] - L.y[11]);
-  L.va0[0] = L.y[9];
-  L.va0[1] = L.y[10];
-  L.va0[2] = L.y[11];
+  const double w = dx * (L.v[0] - L.v[3]) + dy * (L.v[1] - L.v[4]) + dz * (L.v[2] - L.v[5]);
   L.approached = (w >= 0.0);
   L.w_prev = w;
   L.t_first = L.t_last = L.position = 0.0;
-  L.rmin2 = L.r2;
+  L.rmin2 = r2;
 }
 
 // Step set-up of ode45: floor and cap the step, stretch it onto tf when within
 // 10% of the remaining span.
 __device__ __forceinline__ void begin_step(const Launch& P, Lane& L) {
-  L.hmin = 16.0 * spacing(L.t);
-  L.absh = fmin(P.hmax, fmax(L.hmin, L.absh));
-  L.h = L.absh;
+  const double hmin = 16.0 * spacing(L.t);
+  L.absh = fmin(P.hmax, fmax(hmin, L.absh));
   L.done = false;
   if (1.1 * L.absh >= P.tf - L.t) {
-    L.h = P.tf - L.t;
-    L.absh = L.h;
+    L.absh = P.tf - L.t;
     L.done = true;
   }
   L.nofailed = true;
 }
 
-// One Dormand-Prince attempt of size L.h from (L.t, L.y) followed by the error
-// test and the controller; on acceptance the state advances and the
-// observables and exits are updated.
+// One Dormand-Prince attempt of size h = absh from (t, x, v), the error test
+// and the controller; on acceptance the state advances and the observables
+// and exits are updated.
 __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
-  const double t = L.t, h = L.h;
+  const double t = L.t, h = L.absh, hh = h * h;
   const double tnew = L.done ? P.tf : t + h;
-  const double* y = L.y;
-  const double* k1 = L.k1;
-  double ys[12], k2[12], k3[12], k4[12], k5[12], k6[12], k7[12], yn[12];
+  const double* x = L.x;
+  const double* v = L.v;
+  const double* F1 = L.F1;
+  double X[6], F2[6], F3[6], F4[6], F5[6], F6[6], F7[6];
+  double dx, dy, dz;
 
-  const double h21 = h * A21;
+  {
+    const double a = C2 * h;
 #pragma unroll
-  for (int c = 0; c < 12; ++c) ys[c] = y[c] + h21 * k1[c];
-  force(P, cos(P.omega * (t + C2 * h)), ys, k2);
-
-  const double h31 = h * A31, h32 = h * A32;
+    for (int c = 0; c < 6; ++c) X[c] = x[c] + a * v[c];
+    accel(P, cos_rf(P.omega * (t + C2 * h)), X, F2, dx, dy, dz);
+  }
+  {
+    const double a = C3 * h, q1 = Q31 * hh;
 #pragma unroll
-  for (int c = 0; c < 12; ++c) ys[c] = y[c] + (h31 * k1[c] + h32 * k2[c]);
-  force(P, cos(P.omega * (t + C3 * h)), ys, k3);
-
-  const double h41 = h * A41, h42 = h * A42, h43 = h * A43;
+    for (int c = 0; c < 6; ++c) X[c] = x[c] + a * v[c] + q1 * F1[c];
+    accel(P, cos_rf(P.omega * (t + C3 * h)), X, F3, dx, dy, dz);
+  }
+  {
+    const double a = C4 * h, q1 = Q41 * hh, q2 = Q42 * hh;
 #pragma unroll
-  for (int c = 0; c < 12; ++c) ys[c] = y[c] + (h41 * k1[c] + h42 * k2[c] + h43 * k3[c]);
-  force(P, cos(P.omega * (t + C4 * h)), ys, k4);
-
-  const double h51 = h * A51, h52 = h * A52, h53 = h * A53, h54 = h * A54;
+    for (int c = 0; c < 6; ++c) X[c] = x[c] + a * v[c] + (q1 * F1[c] + q2 * F2[c]);
+    accel(P, cos_rf(P.omega * (t + C4 * h)), X, F4, dx, dy, dz);
+  }
+  {
+    const double a = C5 * h, q1 = Q51 * hh, q2 = Q52 * hh, q3 = Q53 * hh;
 #pragma unroll
-  for (int c = 0; c < 12; ++c)
-    ys[c] = y[c] + (h51 * k1[c] + h52 * k2[c] + h53 * k3[c] + h54 * k4[c]);
-  force(P, cos(P.omega * (t + C5 * h)), ys, k5);
-
-  const double h61 = h * A61, h62 = h * A62, h63 = h * A63, h64 = h * A64, h65 = h * A65;
+    for (int c = 0; c < 6; ++c)
+      X[c] = x[c] + a * v[c] + (q1 * F1[c] + q2 * F2[c] + q3 * F3[c]);
+    accel(P, cos_rf(P.omega * (t + C5 * h)), X, F5, dx, dy, dz);
+  }
+  const double cos6 = cos_rf(P.omega * (t + h));
+  {
+    const double q1 = Q61 * hh, q2 = Q62 * hh, q3 = Q63 * hh, q4 = Q64 * hh;
 #pragma unroll
-  for (int c = 0; c < 12; ++c)
-    ys[c] = y[c] + (h61 * k1[c] + h62 * k2[c] + h63 * k3[c] + h64 * k4[c] + h65 * k5[c]);
-  force(P, cos(P.omega * (t + h)), ys, k6);
-
-  const double h71 = h * A71, h73 = h * A73, h74 = h * A74, h75 = h * A75, h76 = h * A76;
+    for (int c = 0; c < 6; ++c)
+      X[c] = x[c] + h * v[c] + (q1 * F1[c] + q2 * F2[c] + q3 * F3[c] + q4 * F4[c]);
+    accel(P, cos6, X, F6, dx, dy, dz);
+  }
+  // new solution, error vector (without F7) and stage 7
+  double xn[6], vn[6], ex[6], ev[6];
+  {
+    const double q1 = Q71 * hh, q3 = Q73 * hh, q4 = Q74 * hh, q5 = Q75 * hh;
+    const double b1 = B1 * h, b3 = B3 * h, b4 = B4 * h, b5 = B5 * h, b6 = B6 * h;
+    const double p1 = P1 * h, p3 = P3 * h, p4 = P4 * h, p5 = P5 * h, p6 = P6 * h;
 #pragma unroll
-  for (int c = 0; c < 12; ++c)
-    yn[c] = y[c] + (h71 * k1[c] + h73 * k3[c] + h74 * k4[c] + h75 * k5[c] + h76 * k6[c]);
-  const double r2n = force(P, cos(P.omega * tnew), yn, k7);
+    for (int c = 0; c < 6; ++c) {
+      xn[c] = x[c] + h * v[c] + (q1 * F1[c] + q3 * F3[c] + q4 * F4[c] + q5 * F5[c]);
+      vn[c] = v[c] + (b1 * F1[c] + b3 * F3[c] + b4 * F4[c] + b5 * F5[c] + b6 * F6[c]);
+      ex[c] = p1 * F1[c] + p3 * F3[c] + p4 * F4[c] + p5 * F5[c] + p6 * F6[c];
+      ev[c] = E1 * F1[c] + E3 * F3[c] + E4 * F4[c] + E5 * F5[c] + E6 * F6[c];
+    }
+  }
+  // stage 7 at tnew; tnew == t + h unless the step was stretched onto tf
+  const double cos7 = L.done ? cos_rf(P.omega * tnew) : cos6;
+  const double r2n = accel(P, cos7, xn, F7, dx, dy, dz);
 
-  // err = |h| max_c |sum_j e_j k_j| / max(|y|, |ynew|, AbsTol/RelTol)
-  double ratio = 0.0;
+  // err = |h| max_c |eps_c| / max(|y_c|, |ynew_c|, AbsTol/RelTol): the
+  // largest ratio is found by cross-multiplication, then one reciprocal
+  double num = 0.0, den = 1.0;
+  bool nan_seen = false;
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
-    const double e = E1 * k1[c] + E3 * k3[c] + E4 * k4[c] + E5 * k5[c] + E6 * k6[c] + E7 * k7[c];
-    const double sc = fmax(fmax(fabs(y[c]), fabs(yn[c])), P.thr);
-    const double v = fabs(e) / sc;
-    ratio = (v > ratio || v != v) ? v : ratio;
+    const int k = c % 6;
+    const double e = c < 6 ? ex[k] : fma(E7, F7[k], ev[k]);
+    const double y_ = c < 6 ? x[k] : v[k];
+    const double yn_ = c < 6 ? xn[k] : vn[k];
+    const double nc = fabs(e);
+    const double dc = fmax(fmax(fabs(y_), fabs(yn_)), P.thr);
+    nan_seen = nan_seen || (nc != nc);
+    if (nc * den > num * dc) {
+      num = nc;
+      den = dc;
+    }
   }
-  const double err = L.absh * ratio;
-
+  const double err = nan_seen ? __builtin_nan("") : h * num * recip(den);
   if (!isfinite(err)) {
     L.status = AI_ST_NONFINITE;
     return;
   }
+  const double w5 = inv_fifth_root(err * P.inv_rtol);  // (err/rtol)^(-1/5)
   if (err > P.rtol) {
     L.nfailed += 1;
-    if (L.absh <= L.hmin) {
+    const double hmin = 16.0 * spacing(t);
+    if (h <= hmin) {
       L.status = AI_ST_HMIN;
       return;
     }
-    if (L.nofailed)
-      L.absh = fmax(L.hmin, L.absh * fmax(0.1, 0.8 * pow(P.rtol / err, 0.2)));
-    else
-      L.absh = fmax(L.hmin, 0.5 * L.absh);
+    L.absh = L.nofailed ? fmax(hmin, h * fmax(0.1, 0.8 * w5)) : fmax(hmin, 0.5 * h);
     L.nofailed = false;
-    L.h = L.absh;
     L.done = false;
     L.fresh = false;
     return;
@@ -253,33 +357,30 @@ __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
   L.nsteps += 1;
   L.t = tnew;
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    L.y[c] = yn[c];
-    L.k1[c] = k7[c];
+  for (int c = 0; c < 6; ++c) {
+    L.x[c] = xn[c];
+    L.v[c] = vn[c];
+    L.F1[c] = F7[c];
   }
-  if (L.nofailed) {
-    const double temp = 1.25 * pow(err / P.rtol, 0.2);
-    L.absh = (temp > 0.2) ? L.absh / temp : 5.0 * L.absh;
-  }
+  // growth 1/(1.25 (err/rtol)^(1/5)), at most 5x
+  if (L.nofailed) L.absh = (w5 < 6.25) ? h * (0.8 * w5) : 5.0 * h;
   L.fresh = true;
 
   // observables: closest approach = sign change of r r' from - to +
-  const double dx = yn[0] - yn[6], dy = yn[1] - yn[7], dz = yn[2] - yn[8];
-  const double w = dx * (yn[3] - yn[9]) + dy * (yn[4] - yn[10]) + dz * (yn[5] - yn[11]);
+  const double w = dx * (vn[0] - vn[3]) + dy * (vn[1] - vn[4]) + dz * (vn[2] - vn[5]);
   if (L.w_prev < 0.0 && w >= 0.0) {
     L.approached = true;
     if (r2n < P.r_bounce2) {
       L.bounces += 1;
       if (L.bounces == 1) {
         L.t_first = tnew;
-        L.position = sqrt(yn[0] * yn[0] + yn[1] * yn[1] + yn[2] * yn[2]);
+        L.position = sqrt(xn[0] * xn[0] + xn[1] * xn[1] + xn[2] * xn[2]);
       }
       L.t_last = tnew;
     }
   }
   L.w_prev = w;
   L.rmin2 = fmin(L.rmin2, r2n);
-  L.r2 = r2n;
 
   if (L.approached && P.exit_on && r2n > P.r_exit2)
     L.status = AI_ST_ESCAPED;
@@ -289,18 +390,20 @@ __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
     L.status = AI_ST_MAXSTEPS;
 }
 
-// Final state and observables of trajectory idx.
+// Final state and observables of trajectory idx.  The atom's initial velocity
+// is read back from y0 before final_state is written (they may be the same
+// buffer).
 __device__ __forceinline__ void finish(const Launch& P, const Lane& L, long long idx,
-                                       double* __restrict__ yf, double* __restrict__ obs) {
-  const double* y = L.y;
-#pragma unroll
-  for (int c = 0; c < 12; ++c) yf[c * P.ld + idx] = y[c];
-  const double cx = L.va0[1] * y[11] - L.va0[2] * y[10];
-  const double cy = L.va0[2] * y[9] - L.va0[0] * y[11];
-  const double cz = L.va0[0] * y[10] - L.va0[1] * y[9];
-  const double dot = L.va0[0] * y[9] + L.va0[1] * y[10] + L.va0[2] * y[11];
-  const double dvx = y[9] - L.va0[0], dvy = y[10] - L.va0[1], dvz = y[11] - L.va0[2];
-  const double dx = y[0] - y[6], dy = y[1] - y[7], dz = y[2] - y[8];
+                                       const double* y0, double* yf, double* __restrict__ obs) {
+  const double va0x = y0[9 * P.ld + idx], va0y = y0[10 * P.ld + idx], va0z = y0[11 * P.ld + idx];
+  const double* x = L.x;
+  const double* v = L.v;
+  const double cx = va0y * v[5] - va0z * v[4];
+  const double cy = va0z * v[3] - va0x * v[5];
+  const double cz = va0x * v[4] - va0y * v[3];
+  const double dot = va0x * v[3] + va0y * v[4] + va0z * v[5];
+  const double dvx = v[3] - va0x, dvy = v[4] - va0y, dvz = v[5] - va0z;
+  const double dx = x[0] - x[3], dy = x[1] - x[4], dz = x[2] - x[5];
   double o[AI_NOBS];
   o[AI_OBS_TEND] = L.t;
   o[AI_OBS_STATUS] = (double)L.status;
@@ -312,16 +415,22 @@ __device__ __forceinline__ void finish(const Launch& P, const Lane& L, long long
   o[AI_OBS_TRANSFER] = P.m_atom * sqrt(dvx * dvx + dvy * dvy + dvz * dvz);
   o[AI_OBS_POSITION] = L.position;
   o[AI_OBS_DIST] = sqrt(dx * dx + dy * dy + dz * dz);
-  o[AI_OBS_KE] = P.half_mi * (y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
+  o[AI_OBS_KE] = P.half_mi * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
   o[AI_OBS_RMIN] = sqrt(L.rmin2);
   o[AI_OBS_HNEXT] = L.absh;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    yf[k * P.ld + idx] = x[k];
+    yf[(3 + k) * P.ld + idx] = v[k];
+    yf[(6 + k) * P.ld + idx] = x[3 + k];
+    yf[(9 + k) * P.ld + idx] = v[3 + k];
+  }
 #pragma unroll
   for (int c = 0; c < AI_NOBS; ++c) obs[c * P.ld + idx] = o[c];
 }
 
 // One trajectory per lane; the grid covers n.
-__global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P, const double* __restrict__ y0,
-                                                         double* __restrict__ yf,
+__global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P, const double* y0, double* yf,
                                                          double* __restrict__ obs) {
   const long long idx = (long long)blockIdx.x * BLOCK + threadIdx.x;
   if (idx >= P.n) return;
@@ -331,7 +440,7 @@ __global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P, const double*
     if (L.fresh) begin_step(P, L);
     attempt(P, L);
   }
-  finish(P, L, idx, yf, obs);
+  finish(P, L, idx, y0, yf, obs);
 }
 
 __global__ void ai_queue_reset_kernel(unsigned long long* queue) { *queue = 0ull; }
@@ -343,25 +452,22 @@ __device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
 
 // Resident waves; lanes whose trajectory has ended take new indices from the
 // device queue.  Indices below P.first_dynamic are assigned statically (lane
-// i of the grid starts trajectory i), the rest in order of request.
-__global__ __launch_bounds__(BLOCK) void ai_persistent_kernel(Launch P,
-                                                              const double* __restrict__ y0,
-                                                              double* __restrict__ yf,
+// i of the grid starts trajectory i), the rest in order of request.  Each
+// loop iteration: idle lanes draw indices (one atomic per wave), lanes with a
+// new index start it, busy lanes make one attempt, finished lanes store.
+__global__ __launch_bounds__(BLOCK) void ai_persistent_kernel(Launch P, const double* y0,
+                                                              double* yf,
                                                               double* __restrict__ obs,
                                                               unsigned long long* queue) {
   long long idx = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  Lane L;
-  bool busy = false;
-  if (idx < P.n) {
-    start(P, y0, idx, L);
-    busy = (L.status == 0);
-    if (!busy) finish(P, L, idx, yf, obs);
-  }
+  bool pending = idx < P.n;  // holds an index not yet started
+  bool busy = false;         // integrating (or finished, awaiting its store)
   bool exhausted = P.first_dynamic >= P.n;  // wave-uniform
+  Lane L;
 
   for (;;) {
     if (!exhausted) {
-      const unsigned long long idle = __ballot(!busy);
+      const unsigned long long idle = __ballot(!busy && !pending);
       if (idle) {
         // one atomic per wave hands out as many indices as the wave has idle lanes
         const int cnt = __popcll(idle);
@@ -370,27 +476,32 @@ __global__ __launch_bounds__(BLOCK) void ai_persistent_kernel(Launch P,
         if ((int)(threadIdx.x % WAVE) == leader) base = atomicAdd(queue, (unsigned long long)cnt);
         base = __shfl(base, leader, WAVE);
         const long long first = P.first_dynamic + (long long)base;
-        if (!busy) {
+        if (!busy && !pending) {
           const long long mine = first + lanes_below(idle);
           if (mine < P.n) {
             idx = mine;
-            start(P, y0, idx, L);
-            busy = (L.status == 0);
-            if (!busy) finish(P, L, idx, yf, obs);
+            pending = true;
           }
         }
         if (first + cnt >= P.n) exhausted = true;
       }
+    }
+    if (pending) {
+      start(P, y0, idx, L);
+      pending = false;
+      busy = true;
     }
     if (__ballot(busy) == 0ull) {
       if (exhausted) break;
       continue;
     }
     if (busy) {
-      if (L.fresh) begin_step(P, L);
-      attempt(P, L);
+      if (L.status == 0) {
+        if (L.fresh) begin_step(P, L);
+        attempt(P, L);
+      }
       if (L.status != 0) {
-        finish(P, L, idx, yf, obs);
+        finish(P, L, idx, y0, yf, obs);
         busy = false;
       }
     }
@@ -487,7 +598,8 @@ int validate(const ai_params* p, const double* y0, int64_t n, int64_t ld, double
   if (p->n < 1 || p->n >= p->m) return fail(AI_EINVAL, "need 1 <= n < m");
   if (p->hmax < 0.0 || p->r_exit < 0.0 || p->r_bounce < 0.0)
     return fail(AI_EINVAL, "hmax, r_exit and r_bounce must be >= 0");
-  if (p->max_steps < 1) return fail(AI_EINVAL, "max_steps must be >= 1");
+  if (p->max_steps < 1 || p->max_steps > 2147483647LL)
+    return fail(AI_EINVAL, "max_steps must be in [1, 2^31 - 1]");
   if (!std::isfinite(t0) || !std::isfinite(tmax) || !(tmax > t0))
     return fail(AI_EINVAL, "need finite t0 < tmax");
   if (!std::isfinite(rtol) || !(rtol > 0.0) || !std::isfinite(atol) || !(atol > 0.0))
@@ -495,6 +607,10 @@ int validate(const ai_params* p, const double* y0, int64_t n, int64_t ld, double
   if (p->n != 4 || p->m != 8)
     return fail(AI_EUNSUPPORTED, "exponents n=%d, m=%d: this build integrates n=4, m=8",
                 p->n, p->m);
+  // the trap phase omega t is reduced with a two-part pi/2 valid below 2^31 pi/2
+  if (std::fabs(p->omega_rf) * std::fmax(std::fabs(t0), std::fabs(tmax)) >= 3.0e9)
+    return fail(AI_EUNSUPPORTED, "|omega_rf t| reaches %.3g rad; this build evaluates the trap "
+                "phase below 3e9 rad", std::fabs(p->omega_rf) * std::fmax(std::fabs(t0), std::fabs(tmax)));
   if (n == 0) return AI_OK;
   if (!y0 || !yf || !obs) return fail(AI_EINVAL, "NULL buffer with n > 0");
   // plane extents, in elements
@@ -537,9 +653,10 @@ Launch launch_constants(const ai_params* p, int64_t n, int64_t ld, double t0, do
   P.tf = tmax;
   P.hmax = p->hmax > 0.0 ? p->hmax : 0.1 * (tmax - t0);
   P.rtol = rtol;
+  P.inv_rtol = 1.0 / rtol;
   P.thr = atol / rtol;
   P.hinit_den = 0.8 * std::pow(rtol, 0.2);
-  P.max_steps = p->max_steps;
+  P.max_steps = (int)p->max_steps;
   P.n = n;
   P.ld = ld;
   P.first_dynamic = 0;

