@@ -31,7 +31,8 @@ KERNEL_SYMBOL = {"persistent": "ai_persistent_kernel", "plain": "ai_plain_kernel
 
 def source_digest() -> str:
     h = hashlib.sha256()
-    for p in ("paper_2509_12381_amd/csrc/ai.hip", "include/ai.h"):
+    for p in ("paper_2509_12381_amd/csrc/ai.hip", "paper_2509_12381_amd/csrc/schedule.hip",
+              "paper_2509_12381_amd/csrc/schedule.h", "include/ai.h"):
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -73,6 +74,11 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--kernel", choices=("persistent", "plain"), default="persistent")
+    ap.add_argument("--schedule", choices=("longest-first", "index"), default="longest-first")
+    ap.add_argument("--refill-min", type=int, default=0,
+                    help="persistent kernel: idle lanes a wave gathers before drawing work")
+    ap.add_argument("--sweep-refill", action="store_true",
+                    help="also time the persistent kernel at several refill thresholds")
     ap.add_argument("--n", type=int, default=None, help="ensemble size (default 2^20)")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -117,13 +123,14 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    def call(kernel):
+    def call(kernel, schedule, refill):
         return binding.ai_integrate_async(wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, fin,
-                                          obs, kernel=kernel, stream=stream)
+                                          obs, kernel=kernel, stream=stream, schedule=schedule,
+                                          refill_min=refill)
 
-    def timed(kernel, steps, warmup):
+    def timed(kernel, steps, warmup, schedule=args.schedule, refill=args.refill_min):
         for _ in range(warmup):
-            call(kernel)
+            call(kernel, schedule, refill)
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
@@ -134,7 +141,7 @@ def main() -> int:
         t_start.record(stream)
         for a, b in ev:
             a.record(stream)
-            call(kernel)
+            call(kernel, schedule, refill)
             b.record(stream)
         t_end.record(stream)
         torch.cuda.synchronize()
@@ -156,13 +163,22 @@ def main() -> int:
     info = binding.ai_get_kernel_info(args.kernel)
     other = None
     if not args.no_compare:
-        okernel = "plain" if args.kernel == "persistent" else "persistent"
-        o_total, o_per, _ = timed(okernel, max(1, min(args.steps, 5)), 1)
-        o_ms = o_total / max(1, min(args.steps, 5))
-        other = {"kernel": okernel, "ms_per_step": o_ms,
-                 "steps_per_s": nsteps / (o_ms / 1e3),
-                 "speedup_of_timed_kernel": o_ms / ms_per_step,
-                 "kernel_info": binding.ai_get_kernel_info(okernel)}
+        other = []
+        for okernel in ("plain", "persistent"):
+            for osched in ("index", "longest-first"):
+                if (okernel, osched) == (args.kernel, args.schedule):
+                    continue
+                k = max(1, min(args.steps, 5))
+                o_total, o_per, _ = timed(okernel, k, 1, osched)
+                o_ms = o_total / k
+                other.append({"kernel": okernel, "schedule": osched, "ms_per_step": o_ms,
+                              "steps_per_s": nsteps / (o_ms / 1e3),
+                              "timed_kernel_speedup": o_ms / ms_per_step})
+        if args.sweep_refill:
+            for k_ in (8, 16, 32, 48, 64):
+                o_total, _, _ = timed("persistent", 3, 1, "longest-first", k_)
+                other.append({"kernel": "persistent", "schedule": "longest-first",
+                              "refill_min": k_, "ms_per_step": o_total / 3})
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -185,6 +201,7 @@ def main() -> int:
                 "sampling, generated on the host",
         "config": {"workload": wl.name, "trajectories": wl.n, "seed": wl.seed,
                    "rtol": wl.rtol, "atol": wl.atol, "kernel": args.kernel,
+                   "schedule": args.schedule, "refill_min": args.refill_min,
                    "tmax_rf_periods": 200, "R0_a0": wl.R0, "b_max_a0": wl.b_max},
         "trajectories_per_s": wl.n * args.steps / (total_ms / 1e3),
         "latency_ms": {"p50": float(np.percentile(per_ms, 50)),
@@ -198,7 +215,7 @@ def main() -> int:
                      "traffic": traffic, "kernel": KERNEL_SYMBOL[args.kernel],
                      "flop_per_launch": flop, "launch_ms": launch_ms},
         "kernel_info": info,
-        "other_kernel": other,
+        "other_variants": other,
         "cpu_baseline": cpu,
         "wall_s_timed_region": wall,
     }

@@ -78,8 +78,22 @@ enum ai_status {
 
 enum ai_kernel {
   AI_KERNEL_PLAIN = 0,     /* one trajectory per lane, grid covers n */
-  AI_KERNEL_PERSISTENT = 1 /* resident waves refill exited lanes from a device queue */
+  AI_KERNEL_PERSISTENT = 1, /* resident waves refill exited lanes from a device queue */
+  /* flag, OR-ed into either kernel: hand out trajectories by decreasing
+   * predicted duration (2 r / |v_atom| at t0, capped at tmax - t0; uniform
+   * when r_exit = 0), computed and sorted on the device.  Changes only which
+   * lane integrates which trajectory, never a result.  Takes 16 n bytes plus
+   * sort scratch from the stream-ordered allocator for the call; ignored for
+   * n >= 2^32. */
+  AI_SCHEDULE_LONGEST_FIRST = 16
 };
+
+/* Persistent kernel only, OR-ed into the kernel argument: a wave draws new
+ * trajectories once at least k (1..64) of its lanes are idle, or all are;
+ * k = 0 selects 1.  Groups of lanes started together tend to finish together.
+ * With the longest-first schedule, waves also take a scheduling priority from
+ * the predicted duration of the longest trajectory they hold. */
+#define AI_REFILL_MIN(k) ((int32_t)(k) << 8)
 
 enum ai_rc {
   AI_OK = 0,
@@ -100,7 +114,9 @@ enum ai_rc {
  * n >= 0 trajectories, ld >= n; n = 0 returns AI_OK without launching.
  * t0 < tmax, both finite: every trajectory starts at t0 and stops at tmax at
  *   the latest.  rtol > 0 and atol > 0 are ode45's RelTol and scalar AbsTol.
- * kernel: enum ai_kernel; both give bitwise-identical per-trajectory results.
+ * kernel: AI_KERNEL_PLAIN or AI_KERNEL_PERSISTENT, optionally OR
+ *   AI_SCHEDULE_LONGEST_FIRST and (persistent) AI_REFILL_MIN(k); every
+ *   combination gives bitwise-identical per-trajectory results.
  * The caller owns every buffer.  Returns AI_OK, AI_WRTOL or a negative
  * ai_rc; a failing call leaves the outputs unspecified. */
 int ai_integrate(const ai_params *p, const double *y0, int64_t n, int64_t ld, double t0,
@@ -127,7 +143,8 @@ typedef struct ai_kernel_info {
   int64_t persistent_blocks;  /* grid of the persistent kernel */
 } ai_kernel_info;
 
-/* Fill *info for enum ai_kernel `kernel`.  Returns AI_OK or a negative ai_rc. */
+/* Fill *info for AI_KERNEL_PLAIN or AI_KERNEL_PERSISTENT (schedule flag
+ * ignored).  Returns AI_OK or a negative ai_rc. */
 int ai_get_kernel_info(int32_t kernel, ai_kernel_info *info);
 
 /* Text of the last error on the calling thread ("" if none). */

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(PKG, "libai.so")
 NSTATE = 12
 NOBS = 13
 KERNELS = {"plain": 0, "persistent": 1}
+SCHEDULE_LONGEST_FIRST = 16
+SCHEDULES = {None: 0, "index": 0, "longest-first": SCHEDULE_LONGEST_FIRST}
 OK, WRTOL, EINVAL, EHIP, ENOMEM, EUNSUPPORTED = 0, 1, -1, -2, -3, -4
 
 # exported symbols of the C ABI, in declaration order
@@ -112,6 +114,14 @@ def _planes(t, rows: int, name: str):
     return t.data_ptr(), t.shape[1]
 
 
+def kernel_code(kernel, schedule=None, refill_min=0) -> int:
+    """ai_integrate's kernel argument: "plain" or "persistent" (or an int),
+    with schedule "longest-first" adding AI_SCHEDULE_LONGEST_FIRST and
+    refill_min adding AI_REFILL_MIN(refill_min)."""
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    return k | SCHEDULES[schedule] | (int(refill_min) << 8)
+
+
 def _args(system, y0, n, t0, tmax, rtol, atol, final_state, obs, kernel):
     p0, ld = _planes(y0, NSTATE, "y0")
     p1, ld1 = _planes(final_state, NSTATE, "final_state")
@@ -119,7 +129,7 @@ def _args(system, y0, n, t0, tmax, rtol, atol, final_state, obs, kernel):
     if not (ld == ld1 == ld2):
         raise ValueError("y0, final_state and obs must share the leading dimension")
     n = ld if n is None else int(n)
-    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    k = kernel if isinstance(kernel, int) else kernel_code(kernel)
     p = system if isinstance(system, AiParams) else params(system)
     return (C.byref(p), p0, n, ld, float(t0), float(tmax), float(rtol), float(atol), p1, p2, k)
 
@@ -130,26 +140,29 @@ def _check(rc: int) -> int:
     return rc
 
 
-def ai_integrate(system, y0, t0, tmax, rtol, atol, final_state, obs, kernel="plain", n=None):
+def ai_integrate(system, y0, t0, tmax, rtol, atol, final_state, obs, kernel="plain", n=None,
+                 schedule=None, refill_min=0):
     """Blocking ai_integrate.  Returns AI_OK or AI_WRTOL; raises on errors."""
+    k = kernel_code(kernel, schedule, refill_min)
     return _check(load().ai_integrate(*_args(system, y0, n, t0, tmax, rtol, atol, final_state,
-                                             obs, kernel)))
+                                             obs, k)))
 
 
 def ai_integrate_async(system, y0, t0, tmax, rtol, atol, final_state, obs, kernel="plain",
-                       n=None, stream=None):
+                       n=None, stream=None, schedule=None, refill_min=0):
     """ai_integrate_async on `stream` (a torch.cuda.Stream; default: torch's
     current stream)."""
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
+    k = kernel_code(kernel, schedule, refill_min)
     return _check(load().ai_integrate_async(*_args(system, y0, n, t0, tmax, rtol, atol,
-                                                   final_state, obs, kernel),
+                                                   final_state, obs, k),
                                             C.c_void_p(s.cuda_stream)))
 
 
 def ai_get_kernel_info(kernel="plain") -> dict:
     info = AiKernelInfo()
-    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel) & 0xf
     _check(load().ai_get_kernel_info(k, C.byref(info)))
     return info.as_dict()
 
@@ -166,12 +179,12 @@ def ai_version() -> int:
     return load().ai_version()
 
 
-def integrate(system, y0, t0, tmax, rtol, atol, kernel="plain", stream=None):
+def integrate(system, y0, t0, tmax, rtol, atol, kernel="plain", stream=None, schedule=None):
     """Allocate outputs next to y0 (a (12, n) GPU tensor), enqueue the
     integration on the current stream and return (final_state, obs, rc)."""
     import torch
     final_state = torch.empty_like(y0)
     obs = torch.empty((NOBS, y0.shape[1]), dtype=torch.float64, device=y0.device)
     rc = ai_integrate_async(system, y0, t0, tmax, rtol, atol, final_state, obs, kernel,
-                            stream=stream)
+                            stream=stream, schedule=schedule)
     return final_state, obs, rc

@@ -34,6 +34,7 @@
 #include <string>
 
 #include "ai.h"
+#include "schedule.h"
 
 namespace {
 
@@ -84,6 +85,7 @@ struct Launch {
   long long first_dynamic;   // persistent kernel: first index handed out by the queue
   int max_steps;
   int exit_on;               // r_exit > 0
+  int refill_min;            // persistent kernel: idle lanes a wave gathers before drawing work
 };
 
 // Per-lane integration state.  x and v hold (ion, atom) positions and
@@ -429,11 +431,40 @@ __device__ __forceinline__ void finish(const Launch& P, const Lane& L, long long
   for (int c = 0; c < AI_NOBS; ++c) obs[c * P.ld + idx] = o[c];
 }
 
-// One trajectory per lane; the grid covers n.
+// Wave priority from the predicted duration of the wave's longest trajectory
+// relative to the longest in the ensemble (both from the longest-first
+// schedule).  The longest trajectories set the end of the launch; while they
+// share a SIMD with other waves, the higher priority lets them issue first
+// and the others fill the gaps.  frac must be uniform across the wave.
+__device__ __forceinline__ void set_wave_priority(float frac) {
+  if (frac >= 0.5f)
+    __builtin_amdgcn_s_setprio(3);
+  else if (frac >= 0.25f)
+    __builtin_amdgcn_s_setprio(2);
+  else if (frac >= 0.125f)
+    __builtin_amdgcn_s_setprio(1);
+  else
+    __builtin_amdgcn_s_setprio(0);
+}
+
+__device__ __forceinline__ float wave_uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// One trajectory per lane; the grid covers n.  Lane g integrates trajectory
+// order[g] (g itself when order is null); with the schedule's keys the wave
+// takes the priority of its first (longest) trajectory.
 __global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P, const double* y0, double* yf,
-                                                         double* __restrict__ obs) {
-  const long long idx = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  if (idx >= P.n) return;
+                                                         double* __restrict__ obs,
+                                                         const unsigned* __restrict__ order,
+                                                         const float* __restrict__ key) {
+  const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (key) {
+    const float top = key[0], mine = key[(long long)blockIdx.x * BLOCK];
+    set_wave_priority(wave_uniform(top > 0.0f ? mine / top : 0.0f));
+  }
+  if (g >= P.n) return;
+  const long long idx = order ? (long long)order[g] : g;
   Lane L;
   start(P, y0, idx, L);
   while (L.status == 0) {
@@ -450,17 +481,23 @@ __device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
                                    __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
-// Resident waves; lanes whose trajectory has ended take new indices from the
-// device queue.  Indices below P.first_dynamic are assigned statically (lane
-// i of the grid starts trajectory i), the rest in order of request.  Each
+// Resident waves; lanes whose trajectory has ended take new positions from the
+// device queue.  Positions below P.first_dynamic are assigned statically (lane
+// g of the grid starts position g), the rest in order of request; position p
+// is trajectory order[p] (p itself when order is null).  Each
 // loop iteration: idle lanes draw indices (one atomic per wave), lanes with a
 // new index start it, busy lanes make one attempt, finished lanes store.
 __global__ __launch_bounds__(BLOCK) void ai_persistent_kernel(Launch P, const double* y0,
                                                               double* yf,
                                                               double* __restrict__ obs,
-                                                              unsigned long long* queue) {
+                                                              unsigned long long* queue,
+                                                              const unsigned* __restrict__ order,
+                                                              const float* __restrict__ key) {
   long long idx = (long long)blockIdx.x * BLOCK + threadIdx.x;
   bool pending = idx < P.n;  // holds an index not yet started
+  float mykey = pending && key ? key[idx] : 0.0f;
+  if (pending && order) idx = order[idx];
+  const float top = key ? key[0] : 0.0f;
   bool busy = false;         // integrating (or finished, awaiting its store)
   bool exhausted = P.first_dynamic >= P.n;  // wave-uniform
   Lane L;
@@ -468,7 +505,7 @@ __global__ __launch_bounds__(BLOCK) void ai_persistent_kernel(Launch P, const do
   for (;;) {
     if (!exhausted) {
       const unsigned long long idle = __ballot(!busy && !pending);
-      if (idle) {
+      if (idle && (__popcll(idle) >= P.refill_min || __ballot(busy) == 0ull)) {
         // one atomic per wave hands out as many indices as the wave has idle lanes
         const int cnt = __popcll(idle);
         const int leader = __ffsll((unsigned long long)idle) - 1;
@@ -479,17 +516,26 @@ __global__ __launch_bounds__(BLOCK) void ai_persistent_kernel(Launch P, const do
         if (!busy && !pending) {
           const long long mine = first + lanes_below(idle);
           if (mine < P.n) {
-            idx = mine;
+            idx = order ? (long long)order[mine] : mine;
+            mykey = key ? key[mine] : 0.0f;
             pending = true;
           }
         }
         if (first + cnt >= P.n) exhausted = true;
       }
     }
-    if (pending) {
-      start(P, y0, idx, L);
-      pending = false;
-      busy = true;
+    if (__ballot(pending)) {
+      if (key) {
+        // priority of the longest trajectory the wave holds
+        float m = (busy || pending) ? mykey : 0.0f;
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, WAVE));
+        set_wave_priority(wave_uniform(top > 0.0f ? m / top : 0.0f));
+      }
+      if (pending) {
+        start(P, y0, idx, L);
+        pending = false;
+        busy = true;
+      }
     }
     if (__ballot(busy) == 0ull) {
       if (exhausted) break;
@@ -503,6 +549,7 @@ __global__ __launch_bounds__(BLOCK) void ai_persistent_kernel(Launch P, const do
       if (L.status != 0) {
         finish(P, L, idx, y0, yf, obs);
         busy = false;
+        mykey = 0.0f;
       }
     }
   }
@@ -591,8 +638,11 @@ int validate(const ai_params* p, const double* y0, int64_t n, int64_t ld, double
   if (!p) return fail(AI_EINVAL, "params is NULL");
   if (n < 0) return fail(AI_EINVAL, "n = %lld < 0", (long long)n);
   if (ld < n) return fail(AI_EINVAL, "ld = %lld < n = %lld", (long long)ld, (long long)n);
-  if (kernel != AI_KERNEL_PLAIN && kernel != AI_KERNEL_PERSISTENT)
-    return fail(AI_EINVAL, "unknown kernel %d", kernel);
+  const int32_t base_kernel = kernel & 0xf;
+  if ((base_kernel != AI_KERNEL_PLAIN && base_kernel != AI_KERNEL_PERSISTENT) ||
+      (kernel & ~(0xf | AI_SCHEDULE_LONGEST_FIRST | (0x7f << 8))) != 0 ||
+      ((kernel >> 8) & 0x7f) > 64)
+    return fail(AI_EINVAL, "unknown kernel argument 0x%x", (unsigned)kernel);
   if (!finite_params(p)) return fail(AI_EINVAL, "non-finite system constant");
   if (!(p->m_ion > 0.0) || !(p->m_atom > 0.0)) return fail(AI_EINVAL, "masses must be > 0");
   if (p->n < 1 || p->n >= p->m) return fail(AI_EINVAL, "need 1 <= n < m");
@@ -661,6 +711,7 @@ Launch launch_constants(const ai_params* p, int64_t n, int64_t ld, double t0, do
   P.ld = ld;
   P.first_dynamic = 0;
   P.exit_on = p->r_exit > 0.0;
+  P.refill_min = 1;
   return P;
 }
 
@@ -674,6 +725,7 @@ const char* ai_last_error(void) { return g_error.c_str(); }
 
 int ai_get_kernel_info(int32_t kernel, ai_kernel_info* info) {
   if (!info) return fail(AI_EINVAL, "info is NULL");
+  kernel &= 0xf;
   if (kernel != AI_KERNEL_PLAIN && kernel != AI_KERNEL_PERSISTENT)
     return fail(AI_EINVAL, "unknown kernel %d", kernel);
   int dev = 0;
@@ -716,15 +768,45 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
   rc = device_facts(dev, &f);
   if (rc != AI_OK) return rc;
 
-  if (kernel == AI_KERNEL_PLAIN) {
+  // optional schedule: longest predicted trajectories first
+  unsigned* order = nullptr;
+  float* key = nullptr;
+  void* order_ws = nullptr;
+  if ((kernel & AI_SCHEDULE_LONGEST_FIRST) && n <= 0xffffffffLL) {
+    e = ai_longest_first_order(y0, n, ld, tmax - t0, p->r_exit > 0.0, &order, &key, &order_ws, s);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return e == hipErrorOutOfMemory ? fail(AI_ENOMEM, "schedule workspace: %s",
+                                             hipGetErrorString(e))
+                                      : hip_fail(e, "schedule");
+    }
+  }
+  auto release = [&]() -> int {
+    if (order_ws) {
+      hipError_t fe = hipFreeAsync(order_ws, s);
+      if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync(schedule)");
+    }
+    return AI_OK;
+  };
+
+  if ((kernel & 0xf) == AI_KERNEL_PLAIN) {
     const long long blocks = (n + BLOCK - 1) / BLOCK;
-    if (blocks > 0x7fffffffLL) return fail(AI_EINVAL, "n too large for one launch");
+    if (blocks > 0x7fffffffLL) {
+      release();
+      return fail(AI_EINVAL, "n too large for one launch");
+    }
     hipLaunchKernelGGL(ai_plain_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P, y0,
-                       final_state, obs);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "launch(plain)");
-    return warn;
+                       final_state, obs, order, key);
+    if ((e = hipGetLastError()) != hipSuccess) {
+      release();
+      return hip_fail(e, "launch(plain)");
+    }
+    rc = release();
+    return rc != AI_OK ? rc : warn;
   }
 
+  const int refill_min = (kernel >> 8) & 0x7f;
+  P.refill_min = refill_min > 0 ? refill_min : 1;
   long long blocks = (long long)f->cus * f->persistent_blocks_per_cu;
   const long long need = (n + BLOCK - 1) / BLOCK;
   if (blocks > need) blocks = need;
@@ -732,21 +814,28 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
   unsigned long long* queue = nullptr;
   if ((e = hipMallocAsync((void**)&queue, sizeof(unsigned long long), s)) != hipSuccess) {
     (void)hipGetLastError();
+    release();
     return fail(AI_ENOMEM, "hipMallocAsync(queue): %s", hipGetErrorString(e));
   }
   hipLaunchKernelGGL(ai_queue_reset_kernel, dim3(1), dim3(1), 0, s, queue);
   if ((e = hipGetLastError()) != hipSuccess) {
     (void)hipFreeAsync(queue, s);
+    release();
     return hip_fail(e, "launch(queue reset)");
   }
   hipLaunchKernelGGL(ai_persistent_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P, y0,
-                     final_state, obs, queue);
+                     final_state, obs, queue, order, key);
   if ((e = hipGetLastError()) != hipSuccess) {
     (void)hipFreeAsync(queue, s);
+    release();
     return hip_fail(e, "launch(persistent)");
   }
-  if ((e = hipFreeAsync(queue, s)) != hipSuccess) return hip_fail(e, "hipFreeAsync(queue)");
-  return warn;
+  if ((e = hipFreeAsync(queue, s)) != hipSuccess) {
+    release();
+    return hip_fail(e, "hipFreeAsync(queue)");
+  }
+  rc = release();
+  return rc != AI_OK ? rc : warn;
 }
 
 int ai_integrate(const ai_params* p, const double* y0, int64_t n, int64_t ld, double t0,

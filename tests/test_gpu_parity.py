@@ -57,7 +57,8 @@ def ai(torch):
     return binding
 
 
-def run_gpu(ai, torch, system, y0, t0, tmax, rtol, atol, kernel="plain", ld=None, n=None):
+def run_gpu(ai, torch, system, y0, t0, tmax, rtol, atol, kernel="plain", ld=None, n=None,
+            schedule=None, refill_min=0):
     n = y0.shape[1] if n is None else n
     ld = y0.shape[1] if ld is None else ld
     y0p = np.zeros((12, ld))
@@ -65,7 +66,8 @@ def run_gpu(ai, torch, system, y0, t0, tmax, rtol, atol, kernel="plain", ld=None
     dy0 = torch.from_numpy(y0p).cuda()
     fin = torch.full((12, ld), -7.0, dtype=torch.float64, device="cuda")
     obs = torch.full((13, ld), -7.0, dtype=torch.float64, device="cuda")
-    rc = ai.ai_integrate(system, dy0, t0, tmax, rtol, atol, fin, obs, kernel=kernel, n=n)
+    rc = ai.ai_integrate(system, dy0, t0, tmax, rtol, atol, fin, obs, kernel=kernel, n=n,
+                         schedule=schedule, refill_min=refill_min)
     torch.cuda.synchronize()
     return fin.cpu().numpy(), obs.cpu().numpy(), rc
 
@@ -181,12 +183,15 @@ the 1e-6 bar (it is still checked at 1e-4, which catches wrong physics)."""
     assert rel.max() <= 1e-6 and same >= 0.99 and loose.max() <= 1e-4
 
 
-def test_plain_and_persistent_agree_bitwise(ai, torch):
+@pytest.mark.parametrize("kernel,schedule,refill", [
+    ("persistent", None, 0), ("plain", "longest-first", 0), ("persistent", "longest-first", 0),
+    ("persistent", "longest-first", 32), ("persistent", None, 64)])
+def test_kernels_and_schedules_agree_bitwise(ai, torch, kernel, schedule, refill):
     wl = W.small_ensemble()
     y0 = wl.initial_states(1000)
     a = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "plain", ld=1031)
-    b = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "persistent",
-                ld=1031)
+    b = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, kernel, ld=1031,
+                schedule=schedule, refill_min=refill)
     np.testing.assert_array_equal(a[0], b[0])
     np.testing.assert_array_equal(a[1], b[1])
     # columns past n are not written
@@ -301,6 +306,10 @@ def test_argument_errors_launch_nothing(ai, torch):
     with pytest.raises(ai.AiError) as e:
         ai.ai_integrate(wl.system, y0, 0.0, 1.0, -1.0, 1e-10, fin, obs)
     assert e.value.rc == ai.EINVAL
+    with pytest.raises(ai.AiError) as e:       # refill threshold beyond a wave
+        ai.ai_integrate(wl.system, y0, 0.0, 1.0, 1e-8, 1e-10, fin, obs, "persistent",
+                        refill_min=65)
+    assert e.value.rc == ai.EINVAL
     import dataclasses
     with pytest.raises(ai.AiError) as e:
         ai.ai_integrate(dataclasses.replace(wl.system, n=6, m=12), y0, 0.0, 1.0, 1e-8, 1e-10,
@@ -321,6 +330,7 @@ def test_argument_errors_launch_nothing(ai, torch):
 def test_kernel_info(ai, torch):
     for kernel in ("plain", "persistent"):
         info = ai.ai_get_kernel_info(kernel)
+        assert info == ai.ai_get_kernel_info(ai.kernel_code(kernel, "longest-first"))
         print(kernel, info, flush=True)
         assert info["vgprs"] > 0 and info["waves_per_simd"] >= 1
         assert info["spill_bytes"] == 0
@@ -335,9 +345,12 @@ def test_full_ensemble_sampled_and_distributions(ai, torch, aio):
     wl = W.full_ensemble()
     y0 = wl.initial_states()
     gfin, gob, grc = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol,
-                             "persistent")
+                             "persistent", schedule="longest-first")
     assert grc == 0
     assert np.all(gob[O["status"]] >= 1) and np.all(gob[O["status"]] <= 5)
+    pfin, pob, _ = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "plain")
+    np.testing.assert_array_equal(gfin, pfin)
+    np.testing.assert_array_equal(gob, pob)
     rng = np.random.default_rng(123)
     idx = np.sort(rng.choice(wl.n, 2048, replace=False))
     ofin, oob, _ = run_oracle(aio, wl.system, y0[:, idx], wl.t0, wl.tmax, wl.rtol, wl.atol)
