@@ -3,12 +3,16 @@
 
 One step = one call of the C ABI (ai_integrate_async) integrating the whole
 2^20-trajectory thermal Li + Yb+ ensemble (seed 0, RelTol 1e-8, AbsTol 1e-10,
-exit at r > R0 after closest approach or after 200 RF periods) with the
-persistent kernel, inputs already resident in device memory.  W untimed
+exit at r > R0 after closest approach or after 200 RF periods), inputs already
+resident in device memory.  The timed configuration is the fastest one: the
+plain one-trajectory-per-lane kernel on the longest-predicted-first schedule
+(the call includes computing and sorting the schedule); the other
+kernel/schedule combinations are timed too and reported beside it.  W untimed
 warm-up steps, then K timed steps bracketed by device synchronisation; prints
 one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--kernel persistent|plain]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--kernel plain|persistent]
+                    [--schedule longest-first|index]
 """
 from __future__ import annotations
 
@@ -73,7 +77,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--kernel", choices=("persistent", "plain"), default="persistent")
+    ap.add_argument("--kernel", choices=("persistent", "plain"), default="plain")
     ap.add_argument("--schedule", choices=("longest-first", "index"), default="longest-first")
     ap.add_argument("--refill-min", type=int, default=0,
                     help="persistent kernel: idle lanes a wave gathers before drawing work")

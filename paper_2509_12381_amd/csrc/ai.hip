@@ -90,11 +90,15 @@ struct Launch {
 
 // Per-lane integration state.  x and v hold (ion, atom) positions and
 // velocities, F1 the accelerations at (t, x): the first stage of the next
-// attempt (first same as last).  The step size h always equals absh here
+// attempt (first same as last).  cph, sph track the trap phase omega t; each
+// accepted step rotates them by omega (t_new - t) (the exact difference of the
+// two doubles), so they follow the rounded time t as a direct evaluation
+// would.  The step size h always equals absh here
 // (integration runs forward), and the step floor 16 eps(t) is recomputed.
 struct Lane {
   double x[6], v[6], F1[6];
   double t, absh;
+  double cph, sph;           // cos and sin of omega t
   double w_prev, t_first, t_last, position, rmin2;
   long long nfailed;
   int nsteps, bounces, status;
@@ -116,12 +120,36 @@ __device__ __forceinline__ double recip(double a) {
   return fma(r, e, r);
 }
 
-// cos(x) for |x| < 2^31 pi/2 (checked on the host).  Cody-Waite reduction
-// x = n pi/2 + r with pi/2 split into two doubles (the first product is exact
-// under the fused multiply-add, the split error is 1.5e-33 per unit of n),
-// then the Taylor series of cos and sin on |r| <= pi/4, truncated after
-// r^16 and r^17 (remainders below 3e-18).
-__device__ __forceinline__ double cos_rf(double x) {
+// Taylor polynomials of cos and sin of a small angle u (|u| <= pi/4 on every
+// call), truncated after u^16 and u^17 (remainders below 3e-18).
+__device__ __forceinline__ double cos_poly(double u2) {
+  double c = 1.0 / 20922789888000.0;                     // 1/16!
+  c = fma(c, u2, -1.0 / 87178291200.0);                  // -1/14!
+  c = fma(c, u2, 1.0 / 479001600.0);                     // 1/12!
+  c = fma(c, u2, -1.0 / 3628800.0);                      // -1/10!
+  c = fma(c, u2, 1.0 / 40320.0);                         // 1/8!
+  c = fma(c, u2, -1.0 / 720.0);                          // -1/6!
+  c = fma(c, u2, 1.0 / 24.0);                            // 1/4!
+  c = fma(c, u2, -0.5);                                  // -1/2!
+  return fma(c, u2, 1.0);
+}
+__device__ __forceinline__ double sin_poly(double u, double u2) {
+  double s = 1.0 / 355687428096000.0;                    // 1/17!
+  s = fma(s, u2, -1.0 / 1307674368000.0);                // -1/15!
+  s = fma(s, u2, 1.0 / 6227020800.0);                    // 1/13!
+  s = fma(s, u2, -1.0 / 39916800.0);                     // -1/11!
+  s = fma(s, u2, 1.0 / 362880.0);                        // 1/9!
+  s = fma(s, u2, -1.0 / 5040.0);                         // -1/7!
+  s = fma(s, u2, 1.0 / 120.0);                           // 1/5!
+  s = fma(s, u2, -1.0 / 6.0);                            // -1/3!
+  return fma(s * u2, u, u);
+}
+
+// cos(x) and sin(x) for |x| < 2^31 pi/2 (checked on the host): Cody-Waite
+// reduction x = n pi/2 + r with pi/2 split into two doubles (the first
+// product is exact under the fused multiply-add, the split error is 1.5e-33
+// per unit of n), then the polynomials above on |r| <= pi/4.
+__device__ __forceinline__ void sincos_rf(double x, double& cx, double& sx) {
   constexpr double TWO_OVER_PI = 0.63661977236758134;  // 2/pi rounded
   constexpr double PIO2_HI = 1.5707963267948966;       // pi/2 rounded
   constexpr double PIO2_LO = 6.123233995736766e-17;    // pi/2 - PIO2_HI rounded
@@ -130,35 +158,52 @@ __device__ __forceinline__ double cos_rf(double x) {
   r = fma(-n, PIO2_LO, r);
   const int q = (int)n;
   const double r2 = r * r;
-  double c = 1.0 / 20922789888000.0;                     // 1/16!
-  c = fma(c, r2, -1.0 / 87178291200.0);                  // -1/14!
-  c = fma(c, r2, 1.0 / 479001600.0);                     // 1/12!
-  c = fma(c, r2, -1.0 / 3628800.0);                      // -1/10!
-  c = fma(c, r2, 1.0 / 40320.0);                         // 1/8!
-  c = fma(c, r2, -1.0 / 720.0);                          // -1/6!
-  c = fma(c, r2, 1.0 / 24.0);                            // 1/4!
-  c = fma(c, r2, -0.5);                                  // -1/2!
-  c = fma(c, r2, 1.0);
-  double s = 1.0 / 355687428096000.0;                    // 1/17!
-  s = fma(s, r2, -1.0 / 1307674368000.0);                // -1/15!
-  s = fma(s, r2, 1.0 / 6227020800.0);                    // 1/13!
-  s = fma(s, r2, -1.0 / 39916800.0);                     // -1/11!
-  s = fma(s, r2, 1.0 / 362880.0);                        // 1/9!
-  s = fma(s, r2, -1.0 / 5040.0);                         // -1/7!
-  s = fma(s, r2, 1.0 / 120.0);                           // 1/5!
-  s = fma(s, r2, -1.0 / 6.0);                            // -1/3!
-  s = s * r2;
-  s = fma(s, r, r);
-  // cos(q pi/2 + r) = cos r, -sin r, -cos r, sin r for q = 0, 1, 2, 3 (mod 4)
-  const double v = (q & 1) ? s : c;
-  return ((q + 1) & 2) ? -v : v;
+  const double c = cos_poly(r2), s = sin_poly(r, r2);
+  // cos(q pi/2 + r) = cos r, -sin r, -cos r, sin r and
+  // sin(q pi/2 + r) = sin r, cos r, -sin r, -cos r for q = 0, 1, 2, 3 (mod 4)
+  const double cv = (q & 1) ? s : c, sv = (q & 1) ? c : s;
+  cx = ((q + 1) & 2) ? -cv : cv;
+  sx = (q & 2) ? -sv : sv;
+}
+
+__device__ __forceinline__ double cos_rf(double x) {
+  double c, s;
+  sincos_rf(x, c, s);
+  return c;
+}
+
+// Largest stage angle omega h for which the stage phases are rotations of
+// the step's start phase by the small-angle polynomials below.
+constexpr double SMALL_ANGLE = 0.5;
+
+// cos and sin of |u| <= SMALL_ANGLE: Taylor series truncated after u^14 and
+// u^15 (remainders below 0.5^16/16! = 7e-19 and 0.5^17/17! = 2e-20).
+__device__ __forceinline__ double cos_small(double u2) {
+  double c = -1.0 / 87178291200.0;                       // -1/14!
+  c = fma(c, u2, 1.0 / 479001600.0);                     // 1/12!
+  c = fma(c, u2, -1.0 / 3628800.0);                      // -1/10!
+  c = fma(c, u2, 1.0 / 40320.0);                         // 1/8!
+  c = fma(c, u2, -1.0 / 720.0);                          // -1/6!
+  c = fma(c, u2, 1.0 / 24.0);                            // 1/4!
+  c = fma(c, u2, -0.5);                                  // -1/2!
+  return fma(c, u2, 1.0);
+}
+__device__ __forceinline__ double sin_small(double u, double u2) {
+  double s = -1.0 / 1307674368000.0;                     // -1/15!
+  s = fma(s, u2, 1.0 / 6227020800.0);                    // 1/13!
+  s = fma(s, u2, -1.0 / 39916800.0);                     // -1/11!
+  s = fma(s, u2, 1.0 / 362880.0);                        // 1/9!
+  s = fma(s, u2, -1.0 / 5040.0);                         // -1/7!
+  s = fma(s, u2, 1.0 / 120.0);                           // 1/5!
+  s = fma(s, u2, -1.0 / 6.0);                            // -1/3!
+  return fma(s * u2, u, u);
 }
 
 // (err/rtol)^(-1/5) for the step-size controller.  Arguments are clamped to
 // [1e-30, 1e30]: outside it the controller's own limits (growth at most 5x,
-// shrink at least 0.1x) decide.  A single-precision estimate is refined by
-// two Newton steps of w <- w (6 - q w^5) / 5 (quadratic convergence from
-// ~1e-7 relative error).
+// shrink at least 0.1x) decide.  A single-precision estimate (relative error
+// ~1e-7) is refined by two Newton steps of w <- w (6 - q w^5) / 5, each of
+// which squares the relative error.
 __device__ __forceinline__ double inv_fifth_root(double q) {
   q = fmin(fmax(q, 1e-30), 1e30);
   double w = (double)__builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf((float)q));
@@ -209,7 +254,8 @@ __device__ __forceinline__ void start(const Launch& P, const double* y0, long lo
     L.v[3 + k] = y[9 + k];
   }
   double dx, dy, dz;
-  const double r2 = accel(P, cos_rf(P.omega * P.t0), L.x, L.F1, dx, dy, dz);
+  sincos_rf(P.omega * P.t0, L.cph, L.sph);
+  const double r2 = accel(P, L.cph, L.x, L.F1, dx, dy, dz);
   L.t = P.t0;
   L.nsteps = L.bounces = 0;
   L.nfailed = 0;
@@ -259,45 +305,73 @@ __device__ __forceinline__ void begin_step(const Launch& P, Lane& L) {
 // and exits are updated.
 __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
   const double t = L.t, h = L.absh, hh = h * h;
-  const double tnew = L.done ? P.tf : t + h;
+  const double tnew = L.done ? P.tf : t + h;  // t + h is also tn below
   const double* x = L.x;
   const double* v = L.v;
   const double* F1 = L.F1;
   double X[6], F2[6], F3[6], F4[6], F5[6], F6[6], F7[6];
   double dx, dy, dz;
 
+  // trap phase at the stage times t + c h: rotations of (cos, sin)(omega t)
+  // by omega c h; stage 6 sits at t_new and its rotation angle is
+  // omega (t_new - t), which also advances the phase on acceptance.  A lane
+  // whose step spans more than SMALL_ANGLE radians evaluates each phase
+  // directly instead.
+  const double tn = t + h;
+  const double d6 = P.omega * (tn - t);
+  double cs2, cs3, cs4, cs5, cs6, sn6;
+  {
+    const double d = P.omega * h;
+    const double u2 = C2 * d, u3 = C3 * d, u4 = C4 * d, u5 = C5 * d;
+    const double C = L.cph, S = L.sph;
+    double w;
+    w = u2 * u2; cs2 = C * cos_small(w) - S * sin_small(u2, w);
+    w = u3 * u3; cs3 = C * cos_small(w) - S * sin_small(u3, w);
+    w = u4 * u4; cs4 = C * cos_small(w) - S * sin_small(u4, w);
+    w = u5 * u5; cs5 = C * cos_small(w) - S * sin_small(u5, w);
+    w = d6 * d6;
+    const double c6 = cos_small(w), s6 = sin_small(d6, w);
+    cs6 = C * c6 - S * s6;
+    sn6 = S * c6 + C * s6;
+    if (!(fabs(d) <= SMALL_ANGLE && fabs(d6) <= SMALL_ANGLE)) {
+      cs2 = cos_rf(P.omega * (t + C2 * h));
+      cs3 = cos_rf(P.omega * (t + C3 * h));
+      cs4 = cos_rf(P.omega * (t + C4 * h));
+      cs5 = cos_rf(P.omega * (t + C5 * h));
+      sincos_rf(P.omega * tn, cs6, sn6);
+    }
+  }
   {
     const double a = C2 * h;
 #pragma unroll
     for (int c = 0; c < 6; ++c) X[c] = x[c] + a * v[c];
-    accel(P, cos_rf(P.omega * (t + C2 * h)), X, F2, dx, dy, dz);
+    accel(P, cs2, X, F2, dx, dy, dz);
   }
   {
     const double a = C3 * h, q1 = Q31 * hh;
 #pragma unroll
     for (int c = 0; c < 6; ++c) X[c] = x[c] + a * v[c] + q1 * F1[c];
-    accel(P, cos_rf(P.omega * (t + C3 * h)), X, F3, dx, dy, dz);
+    accel(P, cs3, X, F3, dx, dy, dz);
   }
   {
     const double a = C4 * h, q1 = Q41 * hh, q2 = Q42 * hh;
 #pragma unroll
     for (int c = 0; c < 6; ++c) X[c] = x[c] + a * v[c] + (q1 * F1[c] + q2 * F2[c]);
-    accel(P, cos_rf(P.omega * (t + C4 * h)), X, F4, dx, dy, dz);
+    accel(P, cs4, X, F4, dx, dy, dz);
   }
   {
     const double a = C5 * h, q1 = Q51 * hh, q2 = Q52 * hh, q3 = Q53 * hh;
 #pragma unroll
     for (int c = 0; c < 6; ++c)
       X[c] = x[c] + a * v[c] + (q1 * F1[c] + q2 * F2[c] + q3 * F3[c]);
-    accel(P, cos_rf(P.omega * (t + C5 * h)), X, F5, dx, dy, dz);
+    accel(P, cs5, X, F5, dx, dy, dz);
   }
-  const double cos6 = cos_rf(P.omega * (t + h));
   {
     const double q1 = Q61 * hh, q2 = Q62 * hh, q3 = Q63 * hh, q4 = Q64 * hh;
 #pragma unroll
     for (int c = 0; c < 6; ++c)
       X[c] = x[c] + h * v[c] + (q1 * F1[c] + q2 * F2[c] + q3 * F3[c] + q4 * F4[c]);
-    accel(P, cos6, X, F6, dx, dy, dz);
+    accel(P, cs6, X, F6, dx, dy, dz);
   }
   // new solution, error vector (without F7) and stage 7
   double xn[6], vn[6], ex[6], ev[6];
@@ -314,7 +388,7 @@ __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
     }
   }
   // stage 7 at tnew; tnew == t + h unless the step was stretched onto tf
-  const double cos7 = L.done ? cos_rf(P.omega * tnew) : cos6;
+  const double cos7 = L.done ? cos_rf(P.omega * tnew) : cs6;
   const double r2n = accel(P, cos7, xn, F7, dx, dy, dz);
 
   // err = |h| max_c |eps_c| / max(|y_c|, |ynew_c|, AbsTol/RelTol): the
@@ -358,6 +432,8 @@ __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
   // accepted
   L.nsteps += 1;
   L.t = tnew;
+  L.cph = cs6;
+  L.sph = sn6;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     L.x[c] = xn[c];
