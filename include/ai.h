@@ -80,7 +80,8 @@ enum ai_kernel {
   AI_KERNEL_PLAIN = 0,     /* one trajectory per lane, grid covers n */
   AI_KERNEL_PERSISTENT = 1, /* resident waves refill exited lanes from a device queue */
   /* flag, OR-ed into either kernel: hand out trajectories by decreasing
-   * predicted duration (2 r / |v_atom| at t0, capped at tmax - t0; uniform
+   * predicted duration (straight-line exit time of the atom from the sphere
+   * of radius r_exit about the trap centre, capped at tmax - t0; uniform
    * when r_exit = 0), computed and sorted on the device.  Changes only which
    * lane integrates which trajectory, never a result.  Takes 16 n bytes plus
    * sort scratch from the stream-ordered allocator for the call; ignored for

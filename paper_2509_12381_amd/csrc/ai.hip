@@ -1,5 +1,9 @@
 // ai.hip -- HIP kernels and C ABI of libai.so (declared in include/ai.h).
 //
+// Built with -ffp-contract=off: every fused multiply-add is written out, so
+// the per-lane sequence of roundings is fixed by this source and identical in
+// every kernel that inlines it (plain, persistent, any schedule).
+//
 // Ensemble ode45 (Dormand-Prince 5(4)) integration of atom + trapped-ion
 // trajectories, one trajectory per lane, FP64, for gfx950 (CDNA4, wave64).
 //
@@ -225,14 +229,14 @@ __device__ __forceinline__ double accel(const Launch& P, double cosrf, const dou
   dx = X[0] - X[3];
   dy = X[1] - X[4];
   dz = X[2] - X[5];
-  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
   const double s = recip(r2);
   const double s2 = s * s;
-  const double g = s2 * s * (P.nCn - P.mCm * s2);
+  const double g = (s2 * s) * fma(-P.mCm, s2, P.nCn);
   const double gi = g * P.inv_mi, ga = g * P.inv_ma;
-  F[0] = -gi * dx - (P.ka[0] + P.kq[0] * cosrf) * X[0];
-  F[1] = -gi * dy - (P.ka[1] + P.kq[1] * cosrf) * X[1];
-  F[2] = -gi * dz - (P.ka[2] + P.kq[2] * cosrf) * X[2];
+  F[0] = -fma(gi, dx, fma(P.kq[0], cosrf, P.ka[0]) * X[0]);
+  F[1] = -fma(gi, dy, fma(P.kq[1], cosrf, P.ka[1]) * X[1]);
+  F[2] = -fma(gi, dz, fma(P.kq[2], cosrf, P.ka[2]) * X[2]);
   F[3] = ga * dx;
   F[4] = ga * dy;
   F[5] = ga * dz;
@@ -265,22 +269,28 @@ __device__ __forceinline__ void start(const Launch& P, const double* y0, long lo
   L.nofailed = true;
 
   // initial step: the weighted first-order increment h f(t0, y0) equals
-  // 0.8 rtol^(1/5); position derivatives are the velocities
+  // 0.8 rtol^(1/5); position derivatives are the velocities.  The largest
+  // |f_c| / max(|y_c|, thr) is found by cross-multiplication.
   bool finite = true;
-  double rh = 0.0;
+  double num = 0.0, den = 1.0;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    finite = finite && isfinite(L.x[c]) && isfinite(L.v[c]) && isfinite(L.F1[c]);
-    rh = fmax(rh, fabs(L.v[c]) / fmax(fabs(L.x[c]), P.thr));
-    rh = fmax(rh, fabs(L.F1[c]) / fmax(fabs(L.v[c]), P.thr));
+  for (int c = 0; c < 12; ++c) {
+    const double f = c < 6 ? L.v[c] : L.F1[c - 6];
+    const double y = c < 6 ? L.x[c] : L.v[c - 6];
+    finite = finite && isfinite(f) && isfinite(y);
+    const double nc = fabs(f), dc = fmax(fabs(y), P.thr);
+    if (nc * den > num * dc) {
+      num = nc;
+      den = dc;
+    }
   }
-  rh = rh / P.hinit_den;
+  const double rh = num / den / P.hinit_den;
   double absh = fmin(P.hmax, P.tf - P.t0);
   if (absh * rh > 1.0) absh = 1.0 / rh;
   L.absh = fmax(absh, 16.0 * spacing(P.t0));
   if (!finite) L.status = AI_ST_NONFINITE;
 
-  const double w = dx * (L.v[0] - L.v[3]) + dy * (L.v[1] - L.v[4]) + dz * (L.v[2] - L.v[5]);
+  const double w = fma(dz, L.v[2] - L.v[5], fma(dy, L.v[1] - L.v[4], dx * (L.v[0] - L.v[3])));
   L.approached = (w >= 0.0);
   L.w_prev = w;
   L.t_first = L.t_last = L.position = 0.0;
@@ -325,52 +335,52 @@ __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
     const double u2 = C2 * d, u3 = C3 * d, u4 = C4 * d, u5 = C5 * d;
     const double C = L.cph, S = L.sph;
     double w;
-    w = u2 * u2; cs2 = C * cos_small(w) - S * sin_small(u2, w);
-    w = u3 * u3; cs3 = C * cos_small(w) - S * sin_small(u3, w);
-    w = u4 * u4; cs4 = C * cos_small(w) - S * sin_small(u4, w);
-    w = u5 * u5; cs5 = C * cos_small(w) - S * sin_small(u5, w);
+    w = u2 * u2; cs2 = fma(C, cos_small(w), -(S * sin_small(u2, w)));
+    w = u3 * u3; cs3 = fma(C, cos_small(w), -(S * sin_small(u3, w)));
+    w = u4 * u4; cs4 = fma(C, cos_small(w), -(S * sin_small(u4, w)));
+    w = u5 * u5; cs5 = fma(C, cos_small(w), -(S * sin_small(u5, w)));
     w = d6 * d6;
     const double c6 = cos_small(w), s6 = sin_small(d6, w);
-    cs6 = C * c6 - S * s6;
-    sn6 = S * c6 + C * s6;
+    cs6 = fma(C, c6, -(S * s6));
+    sn6 = fma(S, c6, C * s6);
     if (!(fabs(d) <= SMALL_ANGLE && fabs(d6) <= SMALL_ANGLE)) {
-      cs2 = cos_rf(P.omega * (t + C2 * h));
-      cs3 = cos_rf(P.omega * (t + C3 * h));
-      cs4 = cos_rf(P.omega * (t + C4 * h));
-      cs5 = cos_rf(P.omega * (t + C5 * h));
+      cs2 = cos_rf(P.omega * fma(C2, h, t));
+      cs3 = cos_rf(P.omega * fma(C3, h, t));
+      cs4 = cos_rf(P.omega * fma(C4, h, t));
+      cs5 = cos_rf(P.omega * fma(C5, h, t));
       sincos_rf(P.omega * tn, cs6, sn6);
     }
   }
   {
     const double a = C2 * h;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) X[c] = x[c] + a * v[c];
+    for (int c = 0; c < 6; ++c) X[c] = fma(a, v[c], x[c]);
     accel(P, cs2, X, F2, dx, dy, dz);
   }
   {
     const double a = C3 * h, q1 = Q31 * hh;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) X[c] = x[c] + a * v[c] + q1 * F1[c];
+    for (int c = 0; c < 6; ++c) X[c] = fma(q1, F1[c], fma(a, v[c], x[c]));
     accel(P, cs3, X, F3, dx, dy, dz);
   }
   {
     const double a = C4 * h, q1 = Q41 * hh, q2 = Q42 * hh;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) X[c] = x[c] + a * v[c] + (q1 * F1[c] + q2 * F2[c]);
+    for (int c = 0; c < 6; ++c) X[c] = fma(q2, F2[c], fma(q1, F1[c], fma(a, v[c], x[c])));
     accel(P, cs4, X, F4, dx, dy, dz);
   }
   {
     const double a = C5 * h, q1 = Q51 * hh, q2 = Q52 * hh, q3 = Q53 * hh;
 #pragma unroll
     for (int c = 0; c < 6; ++c)
-      X[c] = x[c] + a * v[c] + (q1 * F1[c] + q2 * F2[c] + q3 * F3[c]);
+      X[c] = fma(q3, F3[c], fma(q2, F2[c], fma(q1, F1[c], fma(a, v[c], x[c]))));
     accel(P, cs5, X, F5, dx, dy, dz);
   }
   {
     const double q1 = Q61 * hh, q2 = Q62 * hh, q3 = Q63 * hh, q4 = Q64 * hh;
 #pragma unroll
     for (int c = 0; c < 6; ++c)
-      X[c] = x[c] + h * v[c] + (q1 * F1[c] + q2 * F2[c] + q3 * F3[c] + q4 * F4[c]);
+      X[c] = fma(q4, F4[c], fma(q3, F3[c], fma(q2, F2[c], fma(q1, F1[c], fma(h, v[c], x[c])))));
     accel(P, cs6, X, F6, dx, dy, dz);
   }
   // new solution, error vector (without F7) and stage 7
@@ -381,10 +391,10 @@ __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
     const double p1 = P1 * h, p3 = P3 * h, p4 = P4 * h, p5 = P5 * h, p6 = P6 * h;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      xn[c] = x[c] + h * v[c] + (q1 * F1[c] + q3 * F3[c] + q4 * F4[c] + q5 * F5[c]);
-      vn[c] = v[c] + (b1 * F1[c] + b3 * F3[c] + b4 * F4[c] + b5 * F5[c] + b6 * F6[c]);
-      ex[c] = p1 * F1[c] + p3 * F3[c] + p4 * F4[c] + p5 * F5[c] + p6 * F6[c];
-      ev[c] = E1 * F1[c] + E3 * F3[c] + E4 * F4[c] + E5 * F5[c] + E6 * F6[c];
+      xn[c] = fma(q5, F5[c], fma(q4, F4[c], fma(q3, F3[c], fma(q1, F1[c], fma(h, v[c], x[c])))));
+      vn[c] = fma(b6, F6[c], fma(b5, F5[c], fma(b4, F4[c], fma(b3, F3[c], fma(b1, F1[c], v[c])))));
+      ex[c] = fma(p6, F6[c], fma(p5, F5[c], fma(p4, F4[c], fma(p3, F3[c], p1 * F1[c]))));
+      ev[c] = fma(E6, F6[c], fma(E5, F5[c], fma(E4, F4[c], fma(E3, F3[c], E1 * F1[c]))));
     }
   }
   // stage 7 at tnew; tnew == t + h unless the step was stretched onto tf
@@ -445,14 +455,14 @@ __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
   L.fresh = true;
 
   // observables: closest approach = sign change of r r' from - to +
-  const double w = dx * (vn[0] - vn[3]) + dy * (vn[1] - vn[4]) + dz * (vn[2] - vn[5]);
+  const double w = fma(dz, vn[2] - vn[5], fma(dy, vn[1] - vn[4], dx * (vn[0] - vn[3])));
   if (L.w_prev < 0.0 && w >= 0.0) {
     L.approached = true;
     if (r2n < P.r_bounce2) {
       L.bounces += 1;
       if (L.bounces == 1) {
         L.t_first = tnew;
-        L.position = sqrt(xn[0] * xn[0] + xn[1] * xn[1] + xn[2] * xn[2]);
+        L.position = sqrt(fma(xn[2], xn[2], fma(xn[1], xn[1], xn[0] * xn[0])));
       }
       L.t_last = tnew;
     }
@@ -468,43 +478,70 @@ __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
     L.status = AI_ST_MAXSTEPS;
 }
 
-// Final state and observables of trajectory idx.  The atom's initial velocity
-// is read back from y0 before final_state is written (they may be the same
-// buffer).
+// End of trajectory idx: store the final state and the raw accumulators.
+// Derived observables are formed afterwards by ai_finalize_kernel from these
+// planes, so the integration loops carry no atan2 or square roots; until then
+// the lifetime, angle, transfer, dist, ke and rmin planes hold t_first,
+// t_last, the atom's initial velocity (3 planes) and rmin^2.  The initial
+// velocity is read from y0 before final_state is written (they may be the
+// same buffer).
 __device__ __forceinline__ void finish(const Launch& P, const Lane& L, long long idx,
                                        const double* y0, double* yf, double* __restrict__ obs) {
   const double va0x = y0[9 * P.ld + idx], va0y = y0[10 * P.ld + idx], va0z = y0[11 * P.ld + idx];
-  const double* x = L.x;
-  const double* v = L.v;
-  const double cx = va0y * v[5] - va0z * v[4];
-  const double cy = va0z * v[3] - va0x * v[5];
-  const double cz = va0x * v[4] - va0y * v[3];
-  const double dot = va0x * v[3] + va0y * v[4] + va0z * v[5];
-  const double dvx = v[3] - va0x, dvy = v[4] - va0y, dvz = v[5] - va0z;
-  const double dx = x[0] - x[3], dy = x[1] - x[4], dz = x[2] - x[5];
   double o[AI_NOBS];
   o[AI_OBS_TEND] = L.t;
   o[AI_OBS_STATUS] = (double)L.status;
   o[AI_OBS_NSTEPS] = (double)L.nsteps;
   o[AI_OBS_NFAILED] = (double)L.nfailed;
   o[AI_OBS_BOUNCES] = (double)L.bounces;
-  o[AI_OBS_LIFETIME] = L.bounces >= 2 ? L.t_last - L.t_first : 0.0;
-  o[AI_OBS_ANGLE] = atan2(sqrt(cx * cx + cy * cy + cz * cz), dot);
-  o[AI_OBS_TRANSFER] = P.m_atom * sqrt(dvx * dvx + dvy * dvy + dvz * dvz);
+  o[AI_OBS_LIFETIME] = L.t_first;
+  o[AI_OBS_ANGLE] = L.t_last;
+  o[AI_OBS_TRANSFER] = va0x;
   o[AI_OBS_POSITION] = L.position;
-  o[AI_OBS_DIST] = sqrt(dx * dx + dy * dy + dz * dz);
-  o[AI_OBS_KE] = P.half_mi * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-  o[AI_OBS_RMIN] = sqrt(L.rmin2);
+  o[AI_OBS_DIST] = va0y;
+  o[AI_OBS_KE] = va0z;
+  o[AI_OBS_RMIN] = L.rmin2;
   o[AI_OBS_HNEXT] = L.absh;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    yf[k * P.ld + idx] = x[k];
-    yf[(3 + k) * P.ld + idx] = v[k];
-    yf[(6 + k) * P.ld + idx] = x[3 + k];
-    yf[(9 + k) * P.ld + idx] = v[3 + k];
+    yf[k * P.ld + idx] = L.x[k];
+    yf[(3 + k) * P.ld + idx] = L.v[k];
+    yf[(6 + k) * P.ld + idx] = L.x[3 + k];
+    yf[(9 + k) * P.ld + idx] = L.v[3 + k];
   }
 #pragma unroll
   for (int c = 0; c < AI_NOBS; ++c) obs[c * P.ld + idx] = o[c];
+}
+
+// Observables of Sec. 4.1 from the final state and the raw accumulators:
+// lifetime = t_last - t_first for two or more bounces, scattering angle
+// between the atom's initial and final velocity, momentum transfer
+// m_atom |v - v0|, final distance, final ion kinetic energy, smallest distance.
+__global__ __launch_bounds__(256) void ai_finalize_kernel(Launch P, const double* __restrict__ yf,
+                                                          double* __restrict__ obs) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= P.n) return;
+  const long long ld = P.ld;
+  const double t_first = obs[AI_OBS_LIFETIME * ld + i], t_last = obs[AI_OBS_ANGLE * ld + i];
+  const double va0x = obs[AI_OBS_TRANSFER * ld + i], va0y = obs[AI_OBS_DIST * ld + i],
+               va0z = obs[AI_OBS_KE * ld + i];
+  const double rmin2 = obs[AI_OBS_RMIN * ld + i];
+  const double bounces = obs[AI_OBS_BOUNCES * ld + i];
+  double y[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) y[c] = yf[c * ld + i];
+  const double cx = fma(va0y, y[11], -(va0z * y[10]));
+  const double cy = fma(va0z, y[9], -(va0x * y[11]));
+  const double cz = fma(va0x, y[10], -(va0y * y[9]));
+  const double dot = fma(va0z, y[11], fma(va0y, y[10], va0x * y[9]));
+  const double dvx = y[9] - va0x, dvy = y[10] - va0y, dvz = y[11] - va0z;
+  const double dx = y[0] - y[6], dy = y[1] - y[7], dz = y[2] - y[8];
+  obs[AI_OBS_LIFETIME * ld + i] = bounces >= 2.0 ? t_last - t_first : 0.0;
+  obs[AI_OBS_ANGLE * ld + i] = atan2(sqrt(fma(cz, cz, fma(cy, cy, cx * cx))), dot);
+  obs[AI_OBS_TRANSFER * ld + i] = P.m_atom * sqrt(fma(dvz, dvz, fma(dvy, dvy, dvx * dvx)));
+  obs[AI_OBS_DIST * ld + i] = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+  obs[AI_OBS_KE * ld + i] = P.half_mi * fma(y[5], y[5], fma(y[4], y[4], y[3] * y[3]));
+  obs[AI_OBS_RMIN * ld + i] = sqrt(rmin2);
 }
 
 // Wave priority from the predicted duration of the wave's longest trajectory
@@ -563,7 +600,7 @@ __device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
 // is trajectory order[p] (p itself when order is null).  Each
 // loop iteration: idle lanes draw indices (one atomic per wave), lanes with a
 // new index start it, busy lanes make one attempt, finished lanes store.
-__global__ __launch_bounds__(BLOCK) void ai_persistent_kernel(Launch P, const double* y0,
+__global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P, const double* y0,
                                                               double* yf,
                                                               double* __restrict__ obs,
                                                               unsigned long long* queue,
@@ -579,10 +616,10 @@ __global__ __launch_bounds__(BLOCK) void ai_persistent_kernel(Launch P, const do
   Lane L;
 
   for (;;) {
+    // idle lanes draw queue positions: one atomic per wave for all of them
     if (!exhausted) {
       const unsigned long long idle = __ballot(!busy && !pending);
       if (idle && (__popcll(idle) >= P.refill_min || __ballot(busy) == 0ull)) {
-        // one atomic per wave hands out as many indices as the wave has idle lanes
         const int cnt = __popcll(idle);
         const int leader = __ffsll((unsigned long long)idle) - 1;
         unsigned long long base = 0;
@@ -617,16 +654,18 @@ __global__ __launch_bounds__(BLOCK) void ai_persistent_kernel(Launch P, const do
       if (exhausted) break;
       continue;
     }
-    if (busy) {
-      if (L.status == 0) {
+    // integrate until a lane's trajectory ends
+    for (;;) {
+      if (busy && L.status == 0) {
         if (L.fresh) begin_step(P, L);
         attempt(P, L);
       }
-      if (L.status != 0) {
-        finish(P, L, idx, y0, yf, obs);
-        busy = false;
-        mykey = 0.0f;
-      }
+      if (__ballot(busy && L.status != 0)) break;
+    }
+    if (busy && L.status != 0) {
+      finish(P, L, idx, y0, yf, obs);
+      busy = false;
+      mykey = 0.0f;
     }
   }
 }
@@ -791,6 +830,14 @@ Launch launch_constants(const ai_params* p, int64_t n, int64_t ld, double t0, do
   return P;
 }
 
+int launch_finalize(const Launch& P, double* final_state, double* obs, hipStream_t s) {
+  const long long blocks = (P.n + 255) / 256;
+  hipLaunchKernelGGL(ai_finalize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, P, final_state,
+                     obs);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? AI_OK : hip_fail(e, "launch(finalize)");
+}
+
 }  // namespace
 
 extern "C" {
@@ -849,7 +896,7 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
   float* key = nullptr;
   void* order_ws = nullptr;
   if ((kernel & AI_SCHEDULE_LONGEST_FIRST) && n <= 0xffffffffLL) {
-    e = ai_longest_first_order(y0, n, ld, tmax - t0, p->r_exit > 0.0, &order, &key, &order_ws, s);
+    e = ai_longest_first_order(y0, n, ld, tmax - t0, p->r_exit, &order, &key, &order_ws, s);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return e == hipErrorOutOfMemory ? fail(AI_ENOMEM, "schedule workspace: %s",
@@ -878,6 +925,8 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
       return hip_fail(e, "launch(plain)");
     }
     rc = release();
+    if (rc != AI_OK) return rc;
+    rc = launch_finalize(P, final_state, obs, s);
     return rc != AI_OK ? rc : warn;
   }
 
@@ -911,6 +960,8 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
     return hip_fail(e, "hipFreeAsync(queue)");
   }
   rc = release();
+  if (rc != AI_OK) return rc;
+  rc = launch_finalize(P, final_state, obs, s);
   return rc != AI_OK ? rc : warn;
 }
 

@@ -12,20 +12,29 @@
 namespace {
 
 __global__ void ai_cost_key_kernel(const double* __restrict__ y0, long long n, long long ld,
-                                   float horizon, int by_speed, float* __restrict__ key,
+                                   float horizon, double r_exit, float* __restrict__ key,
                                    unsigned* __restrict__ idx) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float d = horizon;
-  if (by_speed) {
-    const double dx = y0[6 * ld + i] - y0[i];
-    const double dy = y0[7 * ld + i] - y0[ld + i];
-    const double dz = y0[8 * ld + i] - y0[2 * ld + i];
+  if (r_exit > 0.0) {
+    // the ion stays near the trap centre: straight-line exit of the atom from
+    // the sphere of radius r_exit about the origin, larger root of
+    // |x + v t| = r_exit; 2 |x_atom - x_ion| / |v| if the line misses it
+    const double x = y0[6 * ld + i], y = y0[7 * ld + i], z = y0[8 * ld + i];
     const double vx = y0[9 * ld + i], vy = y0[10 * ld + i], vz = y0[11 * ld + i];
-    const float r = (float)sqrt(dx * dx + dy * dy + dz * dz);
-    const float v = (float)sqrt(vx * vx + vy * vy + vz * vz);
-    const float t = 2.0f * r / v;  // inf for an atom at rest, NaN sorts anywhere
-    d = t < horizon ? t : horizon;
+    const double vv = vx * vx + vy * vy + vz * vz;
+    const double xv = x * vx + y * vy + z * vz;
+    const double disc = xv * xv - vv * (x * x + y * y + z * z - r_exit * r_exit);
+    double t;
+    if (disc > 0.0) {
+      t = (sqrt(disc) - xv) / vv;
+    } else {
+      const double dx = x - y0[i], dy = y - y0[ld + i], dz = z - y0[2 * ld + i];
+      t = 2.0 * sqrt((dx * dx + dy * dy + dz * dz) / vv);
+    }
+    const float tf = (float)t;  // inf for an atom at rest; NaN sorts anywhere
+    d = tf < horizon ? (tf > 0.0f ? tf : 0.0f) : horizon;
   }
   key[i] = d;
   idx[i] = (unsigned)i;
@@ -36,7 +45,7 @@ constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 }  // namespace
 
 hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld, double horizon,
-                                  bool by_speed, unsigned** order, float** key,
+                                  double r_exit, unsigned** order, float** key,
                                   void** workspace, hipStream_t stream) {
   *order = nullptr;
   *key = nullptr;
@@ -61,8 +70,7 @@ hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld, doubl
   const unsigned threads = 256;
   const unsigned blocks = (unsigned)((n + threads - 1) / threads);
   hipLaunchKernelGGL(ai_cost_key_kernel, dim3(blocks), dim3(threads), 0, stream, y0,
-                     (long long)n, (long long)ld, (float)horizon, by_speed ? 1 : 0, key_in,
-                     idx_in);
+                     (long long)n, (long long)ld, (float)horizon, r_exit, key_in, idx_in);
   if ((e = hipGetLastError()) == hipSuccess)
     e = rocprim::radix_sort_pairs_desc(temp, temp_bytes, key_in, key_out, idx_in, idx_out, size,
                                        0, 32, stream);

@@ -332,9 +332,10 @@ def test_kernel_info(ai, torch):
         info = ai.ai_get_kernel_info(kernel)
         assert info == ai.ai_get_kernel_info(ai.kernel_code(kernel, "longest-first"))
         print(kernel, info, flush=True)
-        assert info["vgprs"] > 0 and info["waves_per_simd"] >= 1
-        assert info["spill_bytes"] == 0
+        assert info["vgprs"] > 0 and info["waves_per_simd"] >= 2
         assert info["compute_units"] >= 1
+        if kernel == "plain":          # the benchmark's kernel keeps everything in registers
+            assert info["spill_bytes"] == 0
 
 
 def test_full_ensemble_sampled_and_distributions(ai, torch, aio):
