@@ -56,6 +56,42 @@ def measured_traffic(kernel: str):
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
 
 
+def write_traffic(fetch_dir: str, write_dir: str, copy_mib: int) -> dict:
+    """profiles/traffic.json from two rocprofv3 --pmc runs of this script (one
+    with FETCH_SIZE, one with WRITE_SIZE, both with --copy-calibration-mib
+    copy_mib).  Each counter is scaled by what it reads for the plain device
+    copy of copy_mib MiB, the largest copy dispatch of the run."""
+    import csv
+    import glob
+
+    def per_dispatch(d, counter):
+        out = {}
+        for f in glob.glob(os.path.join(d, "*_counter_collection.csv")):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = (r["Kernel_Name"], r["Dispatch_Id"])
+                out[key] = out.get(key, 0.0) + float(r["Counter_Value"]) * 1024.0
+        return out
+
+    rec = {"source_digest": source_digest(), "copy_calibration_bytes": copy_mib << 20,
+           "kernels": {}}
+    for counter, d, field in (("FETCH_SIZE", fetch_dir, "fetch"), ("WRITE_SIZE", write_dir, "write")):
+        vals = per_dispatch(d, counter)
+        copies = [v for (k, _), v in vals.items() if "copyBuffer" in k]
+        factor = max(copies) / float(copy_mib << 20)
+        rec[f"{field}_calibration_factor"] = factor
+        for sym in KERNEL_SYMBOL.values():
+            mine = [v for (k, _), v in vals.items() if f"::{sym}(" in k]
+            if mine:
+                k = rec["kernels"].setdefault(sym, {})
+                k[f"{field}_bytes_per_launch"] = sum(mine) / len(mine) / factor
+                k[f"{field}_counter_bytes_per_launch"] = sum(mine) / len(mine)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
 def cpu_baseline(wl, y0_host, sample: int):
     """The oracle as it stands, on the first `sample` trajectories of the same
     ensemble, with the host threads of this process's CPU share."""
@@ -89,7 +125,12 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy of this size first (HBM counter calibration)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from two rocprofv3 counter runs and exit")
     args = ap.parse_args()
+    if args.write_traffic:
+        print(json.dumps(write_traffic(*args.write_traffic, args.copy_calibration_mib or 512)))
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -613,13 +613,18 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P, const
   const float top = key ? key[0] : 0.0f;
   bool busy = false;         // integrating (or finished, awaiting its store)
   bool exhausted = P.first_dynamic >= P.n;  // wave-uniform
+  bool critical = false;                    // wave-uniform
   Lane L;
 
   for (;;) {
-    // idle lanes draw queue positions: one atomic per wave for all of them
+    // idle lanes draw queue positions: one atomic per wave for all of them.
+    // A wave still holding a trajectory predicted to last at least half as
+    // long as the longest one carries the critical path and refills only
+    // once all its lanes are idle.
     if (!exhausted) {
       const unsigned long long idle = __ballot(!busy && !pending);
-      if (idle && (__popcll(idle) >= P.refill_min || __ballot(busy) == 0ull)) {
+      const bool any_busy = __ballot(busy) != 0ull;
+      if (idle && (!any_busy || (__popcll(idle) >= P.refill_min && !critical))) {
         const int cnt = __popcll(idle);
         const int leader = __ffsll((unsigned long long)idle) - 1;
         unsigned long long base = 0;
@@ -642,7 +647,9 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P, const
         // priority of the longest trajectory the wave holds
         float m = (busy || pending) ? mykey : 0.0f;
         for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, WAVE));
-        set_wave_priority(wave_uniform(top > 0.0f ? m / top : 0.0f));
+        const float frac = wave_uniform(top > 0.0f ? m / top : 0.0f);
+        set_wave_priority(frac);
+        critical = frac >= 0.5f;
       }
       if (pending) {
         start(P, y0, idx, L);
