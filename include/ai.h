@@ -80,9 +80,9 @@ enum ai_kernel {
   AI_KERNEL_PLAIN = 0,     /* one trajectory per lane, grid covers n */
   AI_KERNEL_PERSISTENT = 1, /* resident waves refill exited lanes from a device queue */
   /* flag, OR-ed into either kernel: hand out trajectories by decreasing
-   * predicted duration (straight-line exit time of the atom from the sphere
-   * of radius r_exit about the trap centre, capped at tmax - t0; uniform
-   * when r_exit = 0), computed and sorted on the device.  Changes only which
+   * predicted duration (the time at which the atom, on a straight line, is
+   * r_exit away from the ion on its secular trap motion; capped at
+   * tmax - t0; uniform when r_exit = 0), computed and sorted on the device.  Changes only which
    * lane integrates which trajectory, never a result.  Takes 16 n bytes plus
    * sort scratch from the stream-ordered allocator for the call; ignored for
    * n >= 2^32. */

@@ -74,8 +74,10 @@ constexpr int WAVE = 64;
 constexpr int BLOCK = 64;  // one wave per workgroup: a finished wave frees its slot at once
 
 // Launch constants: the system constants folded into the forms the force and
-// the controller use, computed once per call on the host.  Passed by value,
-// so they sit in scalar registers, uniform across the wave.
+// the controller use, computed once per call on the host, and the call's
+// buffers.  The integration kernels take it as their only argument; the force
+// constants are held in scalar registers, the loop's other constants in
+// vector registers (Ctl below).
 struct Launch {
   double inv_mi, inv_ma;     // 1/m_ion, 1/m_atom
   double nCn, mCm;           // 4 C4 and 8 C8: (dV/dr)/r = s^3 (4 C4 - 8 C8 s^2), s = 1/r^2
@@ -90,6 +92,12 @@ struct Launch {
   int max_steps;
   int exit_on;               // r_exit > 0
   int refill_min;            // persistent kernel: idle lanes a wave gathers before drawing work
+  const double* y0;          // n x 12 initial states (planes of ld)
+  double* yf;                // n x 12 final states (may alias y0)
+  double* obs;               // n x AI_NOBS observables
+  const unsigned* order;     // schedule: trajectory at each position (null: identity)
+  const float* key;          // schedule: predicted duration at each position (null: none)
+  unsigned long long* queue; // persistent kernel: dynamic positions handed out so far
 };
 
 // Per-lane integration state.  x and v hold (ion, atom) positions and
@@ -109,19 +117,51 @@ struct Lane {
   bool done, nofailed, fresh, approached;
 };
 
+// The integration loop's constants other than the force constants, one copy
+// per lane in vector registers.  A wave has about 100 scalar registers; the
+// force constants, the tableau constants that FMAs take as scalar operands and
+// these do not all fit, and spilled scalars are restored with a v_readlane
+// (one VALU slot) at every use inside the loop.  The empty asm gives each
+// value a vector-register definition, so it stays there.
+struct Ctl {
+  double tf, hmax, rtol, inv_rtol, thr, r_exit2, r_bounce2, omega;
+  int max_steps, exit_on;
+};
+
+template <typename T>
+__device__ __forceinline__ T in_vgpr(T x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+__device__ __forceinline__ Ctl lane_ctl(const Launch& P) {
+  Ctl c;
+  c.tf = in_vgpr(P.tf);
+  c.hmax = in_vgpr(P.hmax);
+  c.rtol = in_vgpr(P.rtol);
+  c.inv_rtol = in_vgpr(P.inv_rtol);
+  c.thr = in_vgpr(P.thr);
+  c.r_exit2 = in_vgpr(P.r_exit2);
+  c.r_bounce2 = in_vgpr(P.r_bounce2);
+  c.omega = in_vgpr(P.omega);
+  c.max_steps = in_vgpr(P.max_steps);
+  c.exit_on = in_vgpr(P.exit_on);
+  return c;
+}
+
 // Distance from |t| to the next larger double (MATLAB's eps(t)); exact.
 __device__ __forceinline__ double spacing(double t) {
   const double at = fabs(t);
   return __longlong_as_double(__double_as_longlong(at) + 1) - at;
 }
 
-// 1/a: hardware reciprocal estimate refined by two Newton steps.
+// 1/a from the hardware estimate r (relative error e = 1 - a r below 2^-23,
+// computed exactly enough by one FMA): 1/a = r / (1 - e) = r (1 + e + e^2)
+// up to r e^3 (below 2^-69 relative), in three dependent FMAs.
 __device__ __forceinline__ double recip(double a) {
-  double r = __builtin_amdgcn_rcp(a);
-  double e = fma(-a, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-a, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(a);
+  const double e = fma(-a, r, 1.0);
+  return fma(r, fma(e, e, e), r);
 }
 
 // Taylor polynomials of cos and sin of a small angle u (|u| <= pi/4 on every
@@ -176,46 +216,65 @@ __device__ __forceinline__ double cos_rf(double x) {
   return c;
 }
 
-// Largest stage angle omega h for which the stage phases are rotations of
-// the step's start phase by the small-angle polynomials below.
+// Largest step angle omega (t_new - t) for which the stage phases are
+// rotations of the step's start phase built from the small angles below.
 constexpr double SMALL_ANGLE = 0.5;
 
-// cos and sin of |u| <= SMALL_ANGLE: Taylor series truncated after u^14 and
-// u^15 (remainders below 0.5^16/16! = 7e-19 and 0.5^17/17! = 2e-20).
-__device__ __forceinline__ double cos_small(double u2) {
-  double c = -1.0 / 87178291200.0;                       // -1/14!
-  c = fma(c, u2, 1.0 / 479001600.0);                     // 1/12!
-  c = fma(c, u2, -1.0 / 3628800.0);                      // -1/10!
-  c = fma(c, u2, 1.0 / 40320.0);                         // 1/8!
+// A rotation by an angle: its cosine and sine.
+struct Rot {
+  double c, s;
+};
+
+// cos and sin of |u| <= SMALL_ANGLE / 9: Taylor series truncated after u^8
+// and u^9 (remainders below 0.056^10/10! = 8e-20 and 0.056^11/11! = 4e-22).
+__device__ __forceinline__ Rot rot_small(double u) {
+  const double u2 = u * u;
+  double c = 1.0 / 40320.0;                              // 1/8!
   c = fma(c, u2, -1.0 / 720.0);                          // -1/6!
   c = fma(c, u2, 1.0 / 24.0);                            // 1/4!
   c = fma(c, u2, -0.5);                                  // -1/2!
-  return fma(c, u2, 1.0);
-}
-__device__ __forceinline__ double sin_small(double u, double u2) {
-  double s = -1.0 / 1307674368000.0;                     // -1/15!
-  s = fma(s, u2, 1.0 / 6227020800.0);                    // 1/13!
-  s = fma(s, u2, -1.0 / 39916800.0);                     // -1/11!
-  s = fma(s, u2, 1.0 / 362880.0);                        // 1/9!
+  double s = 1.0 / 362880.0;                             // 1/9!
   s = fma(s, u2, -1.0 / 5040.0);                         // -1/7!
   s = fma(s, u2, 1.0 / 120.0);                           // 1/5!
   s = fma(s, u2, -1.0 / 6.0);                            // -1/3!
-  return fma(s * u2, u, u);
+  return {fma(c, u2, 1.0), fma(s * u2, u, u)};
+}
+// Sum and difference of two angles, and twice an angle.
+__device__ __forceinline__ Rot rot_add(Rot a, Rot b) {
+  return {fma(a.c, b.c, -(a.s * b.s)), fma(a.s, b.c, a.c * b.s)};
+}
+__device__ __forceinline__ Rot rot_sub(Rot a, Rot b) {
+  return {fma(a.c, b.c, a.s * b.s), fma(a.s, b.c, -(a.c * b.s))};
+}
+__device__ __forceinline__ Rot rot_twice(Rot a) {
+  const double s2 = a.s + a.s;
+  return {fma(-s2, a.s, 1.0), s2 * a.c};
+}
+
+// max(|a|, |b|) as one v_max_f64 with absolute-value modifiers.  fmax would
+// first quiet a possible signalling NaN in each operand (one more instruction
+// per operand); the error norm tests for NaN separately, so that is not needed.
+__device__ __forceinline__ double max_abs(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+  return r;
 }
 
 // (err/rtol)^(-1/5) for the step-size controller.  Arguments are clamped to
 // [1e-30, 1e30]: outside it the controller's own limits (growth at most 5x,
 // shrink at least 0.1x) decide.  A single-precision estimate (relative error
 // ~1e-7) is refined by two Newton steps of w <- w (6 - q w^5) / 5, each of
-// which squares the relative error.
+// which squares the relative error; a step is written 1.2 w - 0.2 q w^6 so
+// that it is four dependent operations deep.
 __device__ __forceinline__ double inv_fifth_root(double q) {
   q = fmin(fmax(q, 1e-30), 1e30);
+  const double q5 = 0.2 * q;
   double w = (double)__builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf((float)q));
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
     const double w2 = w * w;
-    const double w5 = w2 * w2 * w;
-    w = w * fma(-q, w5, 6.0) * 0.2;
+    const double w3 = w2 * w;
+    w = fma(-q5, w3 * w3, 1.2 * w);
   }
   return w;
 }
@@ -245,11 +304,12 @@ __device__ __forceinline__ double accel(const Launch& P, double cosrf, const dou
 
 // Start of trajectory idx: load its y0 column, f(t0, y0), ode45's initial
 // step and the observables' initial values.
-__device__ __forceinline__ void start(const Launch& P, const double* y0, long long idx,
-                                      Lane& L) {
+__device__ __forceinline__ void start(const Launch& P, long long idx, Lane& L) {
+  const double* y0 = P.y0;
+  const long long ld = P.ld;
   double y[12];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) y[c] = y0[c * P.ld + idx];
+  for (int c = 0; c < 12; ++c) y[c] = y0[c * ld + idx];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     L.x[k] = y[k];
@@ -258,9 +318,10 @@ __device__ __forceinline__ void start(const Launch& P, const double* y0, long lo
     L.v[3 + k] = y[9 + k];
   }
   double dx, dy, dz;
-  sincos_rf(P.omega * P.t0, L.cph, L.sph);
+  const double t0 = P.t0;
+  sincos_rf(P.omega * t0, L.cph, L.sph);
   const double r2 = accel(P, L.cph, L.x, L.F1, dx, dy, dz);
-  L.t = P.t0;
+  L.t = t0;
   L.nsteps = L.bounces = 0;
   L.nfailed = 0;
   L.status = 0;
@@ -285,9 +346,9 @@ __device__ __forceinline__ void start(const Launch& P, const double* y0, long lo
     }
   }
   const double rh = num / den / P.hinit_den;
-  double absh = fmin(P.hmax, P.tf - P.t0);
+  double absh = fmin(P.hmax, P.tf - t0);
   if (absh * rh > 1.0) absh = 1.0 / rh;
-  L.absh = fmax(absh, 16.0 * spacing(P.t0));
+  L.absh = fmax(absh, 16.0 * spacing(t0));
   if (!finite) L.status = AI_ST_NONFINITE;
 
   const double w = fma(dz, L.v[2] - L.v[5], fma(dy, L.v[1] - L.v[4], dx * (L.v[0] - L.v[3])));
@@ -299,12 +360,12 @@ __device__ __forceinline__ void start(const Launch& P, const double* y0, long lo
 
 // Step set-up of ode45: floor and cap the step, stretch it onto tf when within
 // 10% of the remaining span.
-__device__ __forceinline__ void begin_step(const Launch& P, Lane& L) {
+__device__ __forceinline__ void begin_step(const Ctl& K, Lane& L) {
   const double hmin = 16.0 * spacing(L.t);
-  L.absh = fmin(P.hmax, fmax(hmin, L.absh));
+  L.absh = fmin(K.hmax, fmax(hmin, L.absh));
   L.done = false;
-  if (1.1 * L.absh >= P.tf - L.t) {
-    L.absh = P.tf - L.t;
+  if (1.1 * L.absh >= K.tf - L.t) {
+    L.absh = K.tf - L.t;
     L.done = true;
   }
   L.nofailed = true;
@@ -313,42 +374,44 @@ __device__ __forceinline__ void begin_step(const Launch& P, Lane& L) {
 // One Dormand-Prince attempt of size h = absh from (t, x, v), the error test
 // and the controller; on acceptance the state advances and the observables
 // and exits are updated.
-__device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
+__device__ __forceinline__ void attempt(const Launch& P, const Ctl& K, Lane& L) {
   const double t = L.t, h = L.absh, hh = h * h;
-  const double tnew = L.done ? P.tf : t + h;  // t + h is also tn below
+  const double tnew = L.done ? K.tf : t + h;  // t + h is also tn below
   const double* x = L.x;
   const double* v = L.v;
   const double* F1 = L.F1;
   double X[6], F2[6], F3[6], F4[6], F5[6], F6[6], F7[6];
   double dx, dy, dz;
 
-  // trap phase at the stage times t + c h: rotations of (cos, sin)(omega t)
-  // by omega c h; stage 6 sits at t_new and its rotation angle is
-  // omega (t_new - t), which also advances the phase on acceptance.  A lane
-  // whose step spans more than SMALL_ANGLE radians evaluates each phase
-  // directly instead.
+  // trap phase at the stage times: rotations of (cos, sin)(omega t) by
+  // c omega (t_new - t), the exact step span of the double t_new (it differs
+  // from h by the rounding of t + h, a stage-time shift no larger than the
+  // rounding of t + c h itself).  The angles are built from theta = d/10 and
+  // phi = d/9 (d = omega (t_new - t)): 2, 3, 8 and 10 theta by doubling and
+  // addition, 8/9 d = 10 theta - phi.  The stage-6 rotation also advances the
+  // phase on acceptance.  A lane whose step spans more than SMALL_ANGLE
+  // radians evaluates each phase directly instead.
   const double tn = t + h;
-  const double d6 = P.omega * (tn - t);
+  const double omega = K.omega;
+  const double d6 = omega * (tn - t);
   double cs2, cs3, cs4, cs5, cs6, sn6;
   {
-    const double d = P.omega * h;
-    const double u2 = C2 * d, u3 = C3 * d, u4 = C4 * d, u5 = C5 * d;
+    const Rot r1 = rot_small(0.1 * d6), phi = rot_small((1.0 / 9.0) * d6);
+    const Rot r2 = rot_twice(r1), r3 = rot_add(r2, r1), r4 = rot_twice(r2);
+    const Rot r8 = rot_twice(r4), r10 = rot_add(r8, r2), r89 = rot_sub(r10, phi);
     const double C = L.cph, S = L.sph;
-    double w;
-    w = u2 * u2; cs2 = fma(C, cos_small(w), -(S * sin_small(u2, w)));
-    w = u3 * u3; cs3 = fma(C, cos_small(w), -(S * sin_small(u3, w)));
-    w = u4 * u4; cs4 = fma(C, cos_small(w), -(S * sin_small(u4, w)));
-    w = u5 * u5; cs5 = fma(C, cos_small(w), -(S * sin_small(u5, w)));
-    w = d6 * d6;
-    const double c6 = cos_small(w), s6 = sin_small(d6, w);
-    cs6 = fma(C, c6, -(S * s6));
-    sn6 = fma(S, c6, C * s6);
-    if (!(fabs(d) <= SMALL_ANGLE && fabs(d6) <= SMALL_ANGLE)) {
-      cs2 = cos_rf(P.omega * fma(C2, h, t));
-      cs3 = cos_rf(P.omega * fma(C3, h, t));
-      cs4 = cos_rf(P.omega * fma(C4, h, t));
-      cs5 = cos_rf(P.omega * fma(C5, h, t));
-      sincos_rf(P.omega * tn, cs6, sn6);
+    cs2 = fma(C, r2.c, -(S * r2.s));
+    cs3 = fma(C, r3.c, -(S * r3.s));
+    cs4 = fma(C, r8.c, -(S * r8.s));
+    cs5 = fma(C, r89.c, -(S * r89.s));
+    cs6 = fma(C, r10.c, -(S * r10.s));
+    sn6 = fma(S, r10.c, C * r10.s);
+    if (!(fabs(d6) <= SMALL_ANGLE)) {
+      cs2 = cos_rf(omega * fma(C2, h, t));
+      cs3 = cos_rf(omega * fma(C3, h, t));
+      cs4 = cos_rf(omega * fma(C4, h, t));
+      cs5 = cos_rf(omega * fma(C5, h, t));
+      sincos_rf(omega * tn, cs6, sn6);
     }
   }
   {
@@ -398,12 +461,13 @@ __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
     }
   }
   // stage 7 at tnew; tnew == t + h unless the step was stretched onto tf
-  const double cos7 = L.done ? cos_rf(P.omega * tnew) : cs6;
+  const double cos7 = L.done ? cos_rf(omega * tnew) : cs6;
   const double r2n = accel(P, cos7, xn, F7, dx, dy, dz);
 
   // err = |h| max_c |eps_c| / max(|y_c|, |ynew_c|, AbsTol/RelTol): the
-  // largest ratio is found by cross-multiplication, then one reciprocal
-  double num = 0.0, den = 1.0;
+  // largest ratio is found by cross-multiplication in a balanced tree (four
+  // levels instead of a chain of eleven comparisons), then one reciprocal
+  double num[12], den[12];  // error components (signed) and their scales
   bool nan_seen = false;
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
@@ -411,21 +475,27 @@ __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
     const double e = c < 6 ? ex[k] : fma(E7, F7[k], ev[k]);
     const double y_ = c < 6 ? x[k] : v[k];
     const double yn_ = c < 6 ? xn[k] : vn[k];
-    const double nc = fabs(e);
-    const double dc = fmax(fmax(fabs(y_), fabs(yn_)), P.thr);
-    nan_seen = nan_seen || (nc != nc);
-    if (nc * den > num * dc) {
-      num = nc;
-      den = dc;
+    num[c] = e;
+    den[c] = max_abs(max_abs(y_, yn_), K.thr);
+    nan_seen = nan_seen || (e != e);
+  }
+#pragma unroll
+  for (int w = 1; w < 12; w *= 2) {
+#pragma unroll
+    for (int c = 0; c + w < 12; c += 2 * w) {
+      if (fabs(num[c + w]) * den[c] > fabs(num[c]) * den[c + w]) {
+        num[c] = num[c + w];
+        den[c] = den[c + w];
+      }
     }
   }
-  const double err = nan_seen ? __builtin_nan("") : h * num * recip(den);
+  const double err = nan_seen ? __builtin_nan("") : h * fabs(num[0]) * recip(den[0]);
   if (!isfinite(err)) {
     L.status = AI_ST_NONFINITE;
     return;
   }
-  const double w5 = inv_fifth_root(err * P.inv_rtol);  // (err/rtol)^(-1/5)
-  if (err > P.rtol) {
+  const double w5 = inv_fifth_root(err * K.inv_rtol);  // (err/rtol)^(-1/5)
+  if (err > K.rtol) {
     L.nfailed += 1;
     const double hmin = 16.0 * spacing(t);
     if (h <= hmin) {
@@ -458,7 +528,7 @@ __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
   const double w = fma(dz, vn[2] - vn[5], fma(dy, vn[1] - vn[4], dx * (vn[0] - vn[3])));
   if (L.w_prev < 0.0 && w >= 0.0) {
     L.approached = true;
-    if (r2n < P.r_bounce2) {
+    if (r2n < K.r_bounce2) {
       L.bounces += 1;
       if (L.bounces == 1) {
         L.t_first = tnew;
@@ -470,11 +540,11 @@ __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
   L.w_prev = w;
   L.rmin2 = fmin(L.rmin2, r2n);
 
-  if (L.approached && P.exit_on && r2n > P.r_exit2)
+  if (L.approached && K.exit_on && r2n > K.r_exit2)
     L.status = AI_ST_ESCAPED;
   else if (L.done)
     L.status = AI_ST_TMAX;
-  else if (L.nsteps >= P.max_steps)
+  else if (L.nsteps >= K.max_steps)
     L.status = AI_ST_MAXSTEPS;
 }
 
@@ -485,9 +555,12 @@ __device__ __forceinline__ void attempt(const Launch& P, Lane& L) {
 // t_last, the atom's initial velocity (3 planes) and rmin^2.  The initial
 // velocity is read from y0 before final_state is written (they may be the
 // same buffer).
-__device__ __forceinline__ void finish(const Launch& P, const Lane& L, long long idx,
-                                       const double* y0, double* yf, double* __restrict__ obs) {
-  const double va0x = y0[9 * P.ld + idx], va0y = y0[10 * P.ld + idx], va0z = y0[11 * P.ld + idx];
+__device__ __forceinline__ void finish(const Launch& P, const Lane& L, long long idx) {
+  const double* y0 = P.y0;
+  double* yf = P.yf;
+  double* obs = P.obs;
+  const long long ld = P.ld;
+  const double va0x = y0[9 * ld + idx], va0y = y0[10 * ld + idx], va0z = y0[11 * ld + idx];
   double o[AI_NOBS];
   o[AI_OBS_TEND] = L.t;
   o[AI_OBS_STATUS] = (double)L.status;
@@ -504,13 +577,13 @@ __device__ __forceinline__ void finish(const Launch& P, const Lane& L, long long
   o[AI_OBS_HNEXT] = L.absh;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    yf[k * P.ld + idx] = L.x[k];
-    yf[(3 + k) * P.ld + idx] = L.v[k];
-    yf[(6 + k) * P.ld + idx] = L.x[3 + k];
-    yf[(9 + k) * P.ld + idx] = L.v[3 + k];
+    yf[k * ld + idx] = L.x[k];
+    yf[(3 + k) * ld + idx] = L.v[k];
+    yf[(6 + k) * ld + idx] = L.x[3 + k];
+    yf[(9 + k) * ld + idx] = L.v[3 + k];
   }
 #pragma unroll
-  for (int c = 0; c < AI_NOBS; ++c) obs[c * P.ld + idx] = o[c];
+  for (int c = 0; c < AI_NOBS; ++c) obs[c * ld + idx] = o[c];
 }
 
 // Observables of Sec. 4.1 from the final state and the raw accumulators:
@@ -567,24 +640,23 @@ __device__ __forceinline__ float wave_uniform(float v) {
 // One trajectory per lane; the grid covers n.  Lane g integrates trajectory
 // order[g] (g itself when order is null); with the schedule's keys the wave
 // takes the priority of its first (longest) trajectory.
-__global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P, const double* y0, double* yf,
-                                                         double* __restrict__ obs,
-                                                         const unsigned* __restrict__ order,
-                                                         const float* __restrict__ key) {
+__global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P) {
   const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  const float* key = P.key;
   if (key) {
     const float top = key[0], mine = key[(long long)blockIdx.x * BLOCK];
     set_wave_priority(wave_uniform(top > 0.0f ? mine / top : 0.0f));
   }
   if (g >= P.n) return;
-  const long long idx = order ? (long long)order[g] : g;
+  const long long idx = P.order ? (long long)P.order[g] : g;
+  const Ctl K = lane_ctl(P);
   Lane L;
-  start(P, y0, idx, L);
+  start(P, idx, L);
   while (L.status == 0) {
-    if (L.fresh) begin_step(P, L);
-    attempt(P, L);
+    if (L.fresh) begin_step(K, L);
+    attempt(P, K, L);
   }
-  finish(P, L, idx, y0, yf, obs);
+  finish(P, L, idx);
 }
 
 __global__ void ai_queue_reset_kernel(unsigned long long* queue) { *queue = 0ull; }
@@ -597,20 +669,17 @@ __device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
 // Resident waves; lanes whose trajectory has ended take new positions from the
 // device queue.  Positions below P.first_dynamic are assigned statically (lane
 // g of the grid starts position g), the rest in order of request; position p
-// is trajectory order[p] (p itself when order is null).  Each
-// loop iteration: idle lanes draw indices (one atomic per wave), lanes with a
-// new index start it, busy lanes make one attempt, finished lanes store.
-__global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P, const double* y0,
-                                                              double* yf,
-                                                              double* __restrict__ obs,
-                                                              unsigned long long* queue,
-                                                              const unsigned* __restrict__ order,
-                                                              const float* __restrict__ key) {
+// is trajectory order[p] (p itself when order is null).  Each outer
+// iteration: idle lanes draw indices (one atomic per wave), lanes with a new
+// index start it, busy lanes make attempts until enough lanes are free, and
+// the lanes whose trajectory ended store their results.
+__global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
   long long idx = (long long)blockIdx.x * BLOCK + threadIdx.x;
   bool pending = idx < P.n;  // holds an index not yet started
-  float mykey = pending && key ? key[idx] : 0.0f;
-  if (pending && order) idx = order[idx];
-  const float top = key ? key[0] : 0.0f;
+  float mykey = pending && P.key ? P.key[idx] : 0.0f;
+  if (pending && P.order) idx = P.order[idx];
+  const float top = P.key ? P.key[0] : 0.0f;
+  const Ctl K = lane_ctl(P);
   bool busy = false;         // integrating (or finished, awaiting its store)
   bool exhausted = P.first_dynamic >= P.n;  // wave-uniform
   bool critical = false;                    // wave-uniform
@@ -628,22 +697,24 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P, const
         const int cnt = __popcll(idle);
         const int leader = __ffsll((unsigned long long)idle) - 1;
         unsigned long long base = 0;
-        if ((int)(threadIdx.x % WAVE) == leader) base = atomicAdd(queue, (unsigned long long)cnt);
+        if ((int)(threadIdx.x % WAVE) == leader)
+          base = atomicAdd(P.queue, (unsigned long long)cnt);
         base = __shfl(base, leader, WAVE);
         const long long first = P.first_dynamic + (long long)base;
+        const long long n = P.n;
         if (!busy && !pending) {
           const long long mine = first + lanes_below(idle);
-          if (mine < P.n) {
-            idx = order ? (long long)order[mine] : mine;
-            mykey = key ? key[mine] : 0.0f;
+          if (mine < n) {
+            idx = P.order ? (long long)P.order[mine] : mine;
+            mykey = P.key ? P.key[mine] : 0.0f;
             pending = true;
           }
         }
-        if (first + cnt >= P.n) exhausted = true;
+        if (first + cnt >= n) exhausted = true;
       }
     }
     if (__ballot(pending)) {
-      if (key) {
+      if (top > 0.0f) {
         // priority of the longest trajectory the wave holds
         float m = (busy || pending) ? mykey : 0.0f;
         for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, WAVE));
@@ -652,7 +723,7 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P, const
         critical = frac >= 0.5f;
       }
       if (pending) {
-        start(P, y0, idx, L);
+        start(P, idx, L);
         pending = false;
         busy = true;
       }
@@ -661,16 +732,22 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P, const
       if (exhausted) break;
       continue;
     }
-    // integrate until a lane's trajectory ends
+    // integrate until enough lanes are free for a refill: refill_min of them
+    // (idle lanes included), or all of them once the queue is empty or while
+    // the wave is critical.  Lanes whose trajectory has ended wait, frozen,
+    // for their store, so the wave runs the store and start-up code once per
+    // batch instead of once per ended trajectory.
     for (;;) {
       if (busy && L.status == 0) {
-        if (L.fresh) begin_step(P, L);
-        attempt(P, L);
+        if (L.fresh) begin_step(K, L);
+        attempt(P, K, L);
       }
-      if (__ballot(busy && L.status != 0)) break;
+      const unsigned long long live = __ballot(busy && L.status == 0);
+      if (live == 0ull) break;
+      if (!exhausted && !critical && __popcll(~live) >= P.refill_min) break;
     }
     if (busy && L.status != 0) {
-      finish(P, L, idx, y0, yf, obs);
+      finish(P, L, idx);
       busy = false;
       mykey = 0.0f;
     }
@@ -834,6 +911,12 @@ Launch launch_constants(const ai_params* p, int64_t n, int64_t ld, double t0, do
   P.first_dynamic = 0;
   P.exit_on = p->r_exit > 0.0;
   P.refill_min = 1;
+  P.y0 = nullptr;
+  P.yf = nullptr;
+  P.obs = nullptr;
+  P.order = nullptr;
+  P.key = nullptr;
+  P.queue = nullptr;
   return P;
 }
 
@@ -898,12 +981,22 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
   rc = device_facts(dev, &f);
   if (rc != AI_OK) return rc;
 
+  P.y0 = y0;
+  P.yf = final_state;
+  P.obs = obs;
+
   // optional schedule: longest predicted trajectories first
   unsigned* order = nullptr;
   float* key = nullptr;
   void* order_ws = nullptr;
   if ((kernel & AI_SCHEDULE_LONGEST_FIRST) && n <= 0xffffffffLL) {
-    e = ai_longest_first_order(y0, n, ld, tmax - t0, p->r_exit, &order, &key, &order_ws, s);
+    // secular frequencies of the trap, (Omega/2) sqrt(a_k + q_k^2 / 2)
+    double secular[3];
+    for (int k = 0; k < 3; ++k)
+      secular[k] = 0.5 * std::fabs(p->omega_rf) *
+                   std::sqrt(std::fmax(p->a[k] + 0.5 * p->q[k] * p->q[k], 0.0));
+    e = ai_longest_first_order(y0, n, ld, tmax - t0, p->r_exit, secular, &order, &key,
+                               &order_ws, s);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return e == hipErrorOutOfMemory ? fail(AI_ENOMEM, "schedule workspace: %s",
@@ -911,6 +1004,8 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
                                       : hip_fail(e, "schedule");
     }
   }
+  P.order = order;
+  P.key = key;
   auto release = [&]() -> int {
     if (order_ws) {
       hipError_t fe = hipFreeAsync(order_ws, s);
@@ -925,8 +1020,7 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
       release();
       return fail(AI_EINVAL, "n too large for one launch");
     }
-    hipLaunchKernelGGL(ai_plain_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P, y0,
-                       final_state, obs, order, key);
+    hipLaunchKernelGGL(ai_plain_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
     if ((e = hipGetLastError()) != hipSuccess) {
       release();
       return hip_fail(e, "launch(plain)");
@@ -955,8 +1049,8 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
     release();
     return hip_fail(e, "launch(queue reset)");
   }
-  hipLaunchKernelGGL(ai_persistent_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P, y0,
-                     final_state, obs, queue, order, key);
+  P.queue = queue;
+  hipLaunchKernelGGL(ai_persistent_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
   if ((e = hipGetLastError()) != hipSuccess) {
     (void)hipFreeAsync(queue, s);
     release();

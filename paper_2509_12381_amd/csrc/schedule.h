@@ -7,15 +7,16 @@
 #include <cstdint>
 
 // Enqueue on `stream` the construction of a permutation of 0 .. n-1 that
-// lists trajectories by decreasing predicted duration: the time the atom,
-// moving in a straight line at its initial velocity, needs to leave the
-// sphere of radius r_exit about the trap centre (the ion oscillates about
-// it), capped at `horizon`; with r_exit = 0 every trajectory is predicted to
-// last `horizon`.  The
+// lists trajectories by decreasing predicted duration: the time at which the
+// atom, moving in a straight line at its initial velocity, is r_exit away
+// from the ion following its secular motion in the trap (angular frequency
+// secular_omega[k] per axis, zero for a free ion), capped at `horizon`;
+// with r_exit = 0 every trajectory is predicted to last `horizon`.  The
 // permutation (n unsigned ints, device memory) is returned in *order and the
 // predicted durations in the same (decreasing) order in *key; both live
 // inside *workspace, which the caller releases with hipFreeAsync on the same
 // stream once the consumer has been enqueued.  Needs n < 2^32.
 hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld, double horizon,
-                                  double r_exit, unsigned** order, float** key,
+                                  double r_exit, const double secular_omega[3],
+                                  unsigned** order, float** key,
                                   void** workspace, hipStream_t stream);

@@ -11,27 +11,77 @@
 
 namespace {
 
+struct SecularTrap {
+  double w[3];  // secular angular frequency per axis, (Omega/2) sqrt(a_k + q_k^2/2)
+};
+
+__device__ __forceinline__ void ion_secular(const SecularTrap& T, const double* x0,
+                                            const double* v0, double t, double* x, double* v) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double w = T.w[k];
+    if (w > 0.0) {
+      double s, c;
+      sincos(w * t, &s, &c);
+      x[k] = x0[k] * c + v0[k] / w * s;
+      v[k] = -x0[k] * w * s + v0[k] * c;
+    } else {
+      x[k] = x0[k] + v0[k] * t;
+      v[k] = v0[k];
+    }
+  }
+}
+
 __global__ void ai_cost_key_kernel(const double* __restrict__ y0, long long n, long long ld,
-                                   float horizon, double r_exit, float* __restrict__ key,
-                                   unsigned* __restrict__ idx) {
+                                   float horizon, double r_exit, SecularTrap trap,
+                                   float* __restrict__ key, unsigned* __restrict__ idx) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float d = horizon;
   if (r_exit > 0.0) {
-    // the ion stays near the trap centre: straight-line exit of the atom from
-    // the sphere of radius r_exit about the origin, larger root of
-    // |x + v t| = r_exit; 2 |x_atom - x_ion| / |v| if the line misses it
-    const double x = y0[6 * ld + i], y = y0[7 * ld + i], z = y0[8 * ld + i];
-    const double vx = y0[9 * ld + i], vy = y0[10 * ld + i], vz = y0[11 * ld + i];
-    const double vv = vx * vx + vy * vy + vz * vz;
-    const double xv = x * vx + y * vy + z * vz;
-    const double disc = xv * xv - vv * (x * x + y * y + z * z - r_exit * r_exit);
+    double xi[3], vi[3], xa[3], va[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      xi[k] = y0[k * ld + i];
+      vi[k] = y0[(3 + k) * ld + i];
+      xa[k] = y0[(6 + k) * ld + i];
+      va[k] = y0[(9 + k) * ld + i];
+    }
+    const double R2 = r_exit * r_exit;
+    // start: straight-line exit from the sphere of radius r_exit about the
+    // trap centre (larger root of |x_a + v_a t| = r_exit), or 2 r / |v_a|
+    const double vv = va[0] * va[0] + va[1] * va[1] + va[2] * va[2];
+    const double xv = xa[0] * va[0] + xa[1] * va[1] + xa[2] * va[2];
+    const double disc = xv * xv - vv * (xa[0] * xa[0] + xa[1] * xa[1] + xa[2] * xa[2] - R2);
     double t;
     if (disc > 0.0) {
       t = (sqrt(disc) - xv) / vv;
     } else {
-      const double dx = x - y0[i], dy = y - y0[ld + i], dz = z - y0[2 * ld + i];
+      const double dx = xa[0] - xi[0], dy = xa[1] - xi[1], dz = xa[2] - xi[2];
       t = 2.0 * sqrt((dx * dx + dy * dy + dz * dz) / vv);
+    }
+    // refine: the ion follows its secular motion; Newton steps on
+    // g(t) = |x_a + v_a t - x_ion(t)|^2 - r_exit^2, each kept only if it stays
+    // within a factor 2 of the straight-line value.  A trajectory whose
+    // duration is underestimated starts late and can end after everything
+    // else, so a step that leaves that range (an overshoot, or a root on the
+    // wrong side) is discarded.
+    const double ts = t;
+    for (int it = 0; it < 3; ++it) {
+      if (!(t > 0.0) || !(t < (double)horizon)) break;
+      double x[3], v[3];
+      ion_secular(trap, xi, vi, t, x, v);
+      double g = -R2, gp = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double dk = xa[k] + va[k] * t - x[k];
+        g += dk * dk;
+        gp += 2.0 * dk * (va[k] - v[k]);
+      }
+      if (gp > 0.0) {
+        const double tn = t - g / gp;
+        if (tn > 0.5 * ts && tn < 2.0 * ts) t = tn;
+      }
     }
     const float tf = (float)t;  // inf for an atom at rest; NaN sorts anywhere
     d = tf < horizon ? (tf > 0.0f ? tf : 0.0f) : horizon;
@@ -45,7 +95,8 @@ constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 }  // namespace
 
 hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld, double horizon,
-                                  double r_exit, unsigned** order, float** key,
+                                  double r_exit, const double secular_omega[3],
+                                  unsigned** order, float** key,
                                   void** workspace, hipStream_t stream) {
   *order = nullptr;
   *key = nullptr;
@@ -69,8 +120,10 @@ hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld, doubl
   void* temp = base + 2 * fbytes + 2 * ubytes;
   const unsigned threads = 256;
   const unsigned blocks = (unsigned)((n + threads - 1) / threads);
+  SecularTrap trap;
+  for (int k = 0; k < 3; ++k) trap.w[k] = secular_omega[k];
   hipLaunchKernelGGL(ai_cost_key_kernel, dim3(blocks), dim3(threads), 0, stream, y0,
-                     (long long)n, (long long)ld, (float)horizon, r_exit, key_in, idx_in);
+                     (long long)n, (long long)ld, (float)horizon, r_exit, trap, key_in, idx_in);
   if ((e = hipGetLastError()) == hipSuccess)
     e = rocprim::radix_sort_pairs_desc(temp, temp_bytes, key_in, key_out, idx_in, idx_out, size,
                                        0, 32, stream);
