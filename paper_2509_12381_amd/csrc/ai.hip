@@ -134,6 +134,27 @@ __device__ __forceinline__ T in_vgpr(T x) {
   return x;
 }
 
+// The force constants for the loop.  The trap coefficients go to vector
+// registers as well: fma(kq, cos, ka) with both in scalar registers needs a
+// copy of one of them first (an instruction reads one scalar operand).
+struct Force {
+  double inv_mi, inv_ma, nCn, mCm, ka[3], kq[3];
+};
+
+__device__ __forceinline__ Force lane_force(const Launch& P) {
+  Force f;
+  f.inv_mi = P.inv_mi;
+  f.inv_ma = P.inv_ma;
+  f.nCn = P.nCn;
+  f.mCm = P.mCm;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    f.ka[k] = in_vgpr(P.ka[k]);
+    f.kq[k] = in_vgpr(P.kq[k]);
+  }
+  return f;
+}
+
 __device__ __forceinline__ Ctl lane_ctl(const Launch& P) {
   Ctl c;
   c.tf = in_vgpr(P.tf);
@@ -251,39 +272,48 @@ __device__ __forceinline__ Rot rot_twice(Rot a) {
   return {fma(-s2, a.s, 1.0), s2 * a.c};
 }
 
-// max(|a|, |b|) as one v_max_f64 with absolute-value modifiers.  fmax would
-// first quiet a possible signalling NaN in each operand (one more instruction
-// per operand); the error norm tests for NaN separately, so that is not needed.
+// max(|a|, |b|), max(a, b) and min(a, b) as single v_max_f64 / v_min_f64.
+// fmax and fmin would first quiet a possible signalling NaN in each operand
+// whose origin the compiler cannot see (one more instruction per operand);
+// the operands here are finite or caught by the error norm's NaN test.
 __device__ __forceinline__ double max_abs(double a, double b) {
   double r;
   asm("v_max_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double vmax(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double vmin(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
   return r;
 }
 
 // (err/rtol)^(-1/5) for the step-size controller.  Arguments are clamped to
 // [1e-30, 1e30]: outside it the controller's own limits (growth at most 5x,
 // shrink at least 0.1x) decide.  A single-precision estimate (relative error
-// ~1e-7) is refined by two Newton steps of w <- w (6 - q w^5) / 5, each of
-// which squares the relative error; a step is written 1.2 w - 0.2 q w^6 so
-// that it is four dependent operations deep.
+// below 1e-6 over that range, ~6e-8 for ratios within 2^+-7) is refined by one
+// Newton step of w <- w (6 - q w^5) / 5, which maps a relative error e to
+// -3 e^2 (below 3e-12; the step size carries it, far below the ~1e-7 rounding
+// noise of the error estimate it is computed from).  The step is written
+// 1.2 w - 0.2 q w^6 so that it is four dependent operations deep.
 __device__ __forceinline__ double inv_fifth_root(double q) {
   q = fmin(fmax(q, 1e-30), 1e30);
-  const double q5 = 0.2 * q;
-  double w = (double)__builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf((float)q));
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double w2 = w * w;
-    const double w3 = w2 * w;
-    w = fma(-q5, w3 * w3, 1.2 * w);
-  }
-  return w;
+  const double w = (double)__builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf((float)q));
+  const double w2 = w * w;
+  const double w3 = w2 * w;
+  return fma(-0.2 * q, w3 * w3, 1.2 * w);
 }
 
 // Accelerations F(t, X) of Sec. 2.1 for V(r) = -C4/r^4 + C8/r^8:
 // F_ion = -(g/m_ion) d - kappa(t) x_ion, F_atom = (g/m_atom) d with
 // d = x_ion - x_atom and g = (dV/dr)/r.  cosrf = cos(omega t).  Returns r^2
 // and d.
-__device__ __forceinline__ double accel(const Launch& P, double cosrf, const double* X,
+template <class C>
+__device__ __forceinline__ double accel(const C& P, double cosrf, const double* X,
                                         double* F, double& dx, double& dy, double& dz) {
   dx = X[0] - X[3];
   dy = X[1] - X[4];
@@ -362,7 +392,7 @@ __device__ __forceinline__ void start(const Launch& P, long long idx, Lane& L) {
 // 10% of the remaining span.
 __device__ __forceinline__ void begin_step(const Ctl& K, Lane& L) {
   const double hmin = 16.0 * spacing(L.t);
-  L.absh = fmin(K.hmax, fmax(hmin, L.absh));
+  L.absh = vmin(K.hmax, vmax(hmin, L.absh));
   L.done = false;
   if (1.1 * L.absh >= K.tf - L.t) {
     L.absh = K.tf - L.t;
@@ -374,7 +404,7 @@ __device__ __forceinline__ void begin_step(const Ctl& K, Lane& L) {
 // One Dormand-Prince attempt of size h = absh from (t, x, v), the error test
 // and the controller; on acceptance the state advances and the observables
 // and exits are updated.
-__device__ __forceinline__ void attempt(const Launch& P, const Ctl& K, Lane& L) {
+__device__ __forceinline__ void attempt(const Force& P, const Ctl& K, Lane& L) {
   const double t = L.t, h = L.absh, hh = h * h;
   const double tnew = L.done ? K.tf : t + h;  // t + h is also tn below
   const double* x = L.x;
@@ -538,7 +568,7 @@ __device__ __forceinline__ void attempt(const Launch& P, const Ctl& K, Lane& L) 
     }
   }
   L.w_prev = w;
-  L.rmin2 = fmin(L.rmin2, r2n);
+  L.rmin2 = vmin(L.rmin2, r2n);
 
   if (L.approached && K.exit_on && r2n > K.r_exit2)
     L.status = AI_ST_ESCAPED;
@@ -650,11 +680,12 @@ __global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P) {
   if (g >= P.n) return;
   const long long idx = P.order ? (long long)P.order[g] : g;
   const Ctl K = lane_ctl(P);
+  const Force Fc = lane_force(P);
   Lane L;
   start(P, idx, L);
   while (L.status == 0) {
     if (L.fresh) begin_step(K, L);
-    attempt(P, K, L);
+    attempt(Fc, K, L);
   }
   finish(P, L, idx);
 }
@@ -680,6 +711,7 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
   if (pending && P.order) idx = P.order[idx];
   const float top = P.key ? P.key[0] : 0.0f;
   const Ctl K = lane_ctl(P);
+  const Force Fc = lane_force(P);
   bool busy = false;         // integrating (or finished, awaiting its store)
   bool exhausted = P.first_dynamic >= P.n;  // wave-uniform
   bool critical = false;                    // wave-uniform
@@ -740,7 +772,7 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
     for (;;) {
       if (busy && L.status == 0) {
         if (L.fresh) begin_step(K, L);
-        attempt(P, K, L);
+        attempt(Fc, K, L);
       }
       const unsigned long long live = __ballot(busy && L.status == 0);
       if (live == 0ull) break;
