@@ -114,7 +114,9 @@ struct Lane {
   double w_prev, t_first, t_last, position, rmin2;
   long long nfailed;
   int nsteps, bounces, status;
-  bool done, nofailed, fresh, approached;
+  // flags as ints: a bool that lives across the loop is kept as a 64-bit lane
+  // mask in scalar registers, an int in one vector register
+  int done, nofailed, fresh, approached;
 };
 
 // The integration loop's constants other than the force constants, one copy
@@ -332,14 +334,34 @@ __device__ __forceinline__ double accel(const C& P, double cosrf, const double* 
   return r2;
 }
 
-// Start of trajectory idx: load its y0 column, f(t0, y0), ode45's initial
-// step and the observables' initial values.
-__device__ __forceinline__ void start(const Launch& P, long long idx, Lane& L) {
-  const double* y0 = P.y0;
-  const long long ld = P.ld;
-  double y[12];
+// The y0 column of trajectory idx.
+__device__ __forceinline__ void load_column(const Launch& P, long long idx, double* y) {
 #pragma unroll
-  for (int c = 0; c < 12; ++c) y[c] = y0[c * ld + idx];
+  for (int c = 0; c < 12; ++c) y[c] = P.y0[c * P.ld + idx];
+}
+
+// What starting a trajectory needs besides its initial state, the same for
+// every trajectory of a call: t0, the trap phase at t0, the initial step's cap
+// min(hmax, tf - t0) and floor 16 eps(t0), AbsTol/RelTol, 0.8 RelTol^(1/5).
+struct StartConst {
+  double t0, cph0, sph0, hcap, hmin0, thr, hinit_den;
+};
+
+__device__ __forceinline__ StartConst start_const(const Launch& P) {
+  StartConst S;
+  S.t0 = P.t0;
+  sincos_rf(P.omega * P.t0, S.cph0, S.sph0);
+  S.hcap = fmin(P.hmax, P.tf - P.t0);
+  S.hmin0 = 16.0 * spacing(P.t0);
+  S.thr = P.thr;
+  S.hinit_den = P.hinit_den;
+  return S;
+}
+
+// Start of a trajectory from its initial state y: f(t0, y0), ode45's initial
+// step and the observables' initial values.
+__device__ __forceinline__ void start(const Force& Fc, const StartConst& S, const double* y,
+                                      Lane& L) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     L.x[k] = y[k];
@@ -348,10 +370,10 @@ __device__ __forceinline__ void start(const Launch& P, long long idx, Lane& L) {
     L.v[3 + k] = y[9 + k];
   }
   double dx, dy, dz;
-  const double t0 = P.t0;
-  sincos_rf(P.omega * t0, L.cph, L.sph);
-  const double r2 = accel(P, L.cph, L.x, L.F1, dx, dy, dz);
-  L.t = t0;
+  L.cph = S.cph0;
+  L.sph = S.sph0;
+  const double r2 = accel(Fc, L.cph, L.x, L.F1, dx, dy, dz);
+  L.t = S.t0;
   L.nsteps = L.bounces = 0;
   L.nfailed = 0;
   L.status = 0;
@@ -369,16 +391,16 @@ __device__ __forceinline__ void start(const Launch& P, long long idx, Lane& L) {
     const double f = c < 6 ? L.v[c] : L.F1[c - 6];
     const double y = c < 6 ? L.x[c] : L.v[c - 6];
     finite = finite && isfinite(f) && isfinite(y);
-    const double nc = fabs(f), dc = fmax(fabs(y), P.thr);
+    const double nc = fabs(f), dc = fmax(fabs(y), S.thr);
     if (nc * den > num * dc) {
       num = nc;
       den = dc;
     }
   }
-  const double rh = num / den / P.hinit_den;
-  double absh = fmin(P.hmax, P.tf - t0);
+  const double rh = num / den / S.hinit_den;
+  double absh = S.hcap;
   if (absh * rh > 1.0) absh = 1.0 / rh;
-  L.absh = fmax(absh, 16.0 * spacing(t0));
+  L.absh = fmax(absh, S.hmin0);
   if (!finite) L.status = AI_ST_NONFINITE;
 
   const double w = fma(dz, L.v[2] - L.v[5], fma(dy, L.v[1] - L.v[4], dx * (L.v[0] - L.v[3])));
@@ -582,15 +604,11 @@ __device__ __forceinline__ void attempt(const Force& P, const Ctl& K, Lane& L) {
 // Derived observables are formed afterwards by ai_finalize_kernel from these
 // planes, so the integration loops carry no atan2 or square roots; until then
 // the lifetime, angle, transfer, dist, ke and rmin planes hold t_first,
-// t_last, the atom's initial velocity (3 planes) and rmin^2.  The initial
-// velocity is read from y0 before final_state is written (they may be the
-// same buffer).
-__device__ __forceinline__ void finish(const Launch& P, const Lane& L, long long idx) {
-  const double* y0 = P.y0;
-  double* yf = P.yf;
-  double* obs = P.obs;
-  const long long ld = P.ld;
-  const double va0x = y0[9 * ld + idx], va0y = y0[10 * ld + idx], va0z = y0[11 * ld + idx];
+// t_last, the atom's initial velocity (3 planes) and rmin^2.
+// va0 is the atom's initial velocity (kept by the caller: final_state may be
+// the y0 buffer itself).
+__device__ __forceinline__ void finish(double* yf, double* obs, long long ld, const Lane& L,
+                                       long long idx, double va0x, double va0y, double va0z) {
   double o[AI_NOBS];
   o[AI_OBS_TEND] = L.t;
   o[AI_OBS_STATUS] = (double)L.status;
@@ -682,12 +700,18 @@ __global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P) {
   const Ctl K = lane_ctl(P);
   const Force Fc = lane_force(P);
   Lane L;
-  start(P, idx, L);
+  {
+    double y[12];
+    load_column(P, idx, y);
+    start(Fc, start_const(P), y, L);
+  }
   while (L.status == 0) {
     if (L.fresh) begin_step(K, L);
     attempt(Fc, K, L);
   }
-  finish(P, L, idx);
+  // the initial atom velocity is read before final_state (possibly y0) is written
+  const double* va0 = P.y0 + 9 * P.ld + idx;
+  finish(P.yf, P.obs, P.ld, L, idx, va0[0], va0[P.ld], va0[2 * P.ld]);
 }
 
 __global__ void ai_queue_reset_kernel(unsigned long long* queue) { *queue = 0ull; }
@@ -697,78 +721,102 @@ __device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
                                    __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
-// Resident waves; lanes whose trajectory has ended take new positions from the
-// device queue.  Positions below P.first_dynamic are assigned statically (lane
-// g of the grid starts position g), the rest in order of request; position p
-// is trajectory order[p] (p itself when order is null).  Each outer
-// iteration: idle lanes draw indices (one atomic per wave), lanes with a new
-// index start it, busy lanes make attempts until enough lanes are free, and
-// the lanes whose trajectory ended store their results.
+// Positions a wave claims from the queue at a time, and near the queue's end
+// (when fewer than TAIL_ROUNDS chunks per wave remain), so that no wave holds
+// much unstarted work while others run dry.
+constexpr int CHUNK = 32;
+constexpr int CHUNK_TAIL = 8;
+constexpr int TAIL_ROUNDS = 8;
+
+// Resident waves.  Positions below P.first_dynamic are assigned statically
+// (lane g of the grid starts position g); the rest are claimed from the device
+// queue in chunks: one atomic per chunk, and the chunk's initial states are
+// loaded into LDS at once.  Lanes whose trajectory has ended take staged
+// entries from LDS, so a refill waits on memory once per chunk rather than on
+// three dependent round trips (queue, schedule, y0) per trajectory.  Position
+// p is trajectory order[p] (p itself when order is null).  Each outer
+// iteration: busy lanes make attempts until enough lanes are free, ended
+// trajectories are stored, and free lanes start staged trajectories.
 __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
-  long long idx = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  bool pending = idx < P.n;  // holds an index not yet started
-  float mykey = pending && P.key ? P.key[idx] : 0.0f;
-  if (pending && P.order) idx = P.order[idx];
+  __shared__ double stage_y[12][WAVE];  // staged initial states, component-major
+  __shared__ long long stage_idx[WAVE];
+  __shared__ float stage_key[WAVE];
+  __shared__ double lane_va0[3][WAVE];  // each lane's initial atom velocity
+  // The launch fields and start constants the refill, start and store code
+  // uses, read from LDS where used (through an opaque pointer, so the loads
+  // stay there) instead of being held in scalar registers across the
+  // attempt loop, where they would be spilled to vector-register lanes.
+  __shared__ Launch lds_P;
+  __shared__ StartConst lds_S;
+  const int lane = (int)threadIdx.x;    // BLOCK == WAVE: one wave per workgroup
+  if (lane == 0) {
+    lds_P = P;
+    lds_S = start_const(P);
+  }
+  __syncthreads();
   const float top = P.key ? P.key[0] : 0.0f;
+  const int refill_min = in_vgpr(P.refill_min);
   const Ctl K = lane_ctl(P);
   const Force Fc = lane_force(P);
-  bool busy = false;         // integrating (or finished, awaiting its store)
-  bool exhausted = P.first_dynamic >= P.n;  // wave-uniform
-  bool critical = false;                    // wave-uniform
   Lane L;
+  long long idx = (long long)blockIdx.x * BLOCK + lane;
+  float mykey = 0.0f;
+  int busy = 0;                             // integrating, or ended and not yet stored
+  bool critical = false;                    // wave-uniform
+  bool drained = P.first_dynamic >= P.n;    // wave-uniform: no more claims succeed
+  long long front = P.first_dynamic;        // wave-uniform: queue front as last seen
+  int avail = 0, head = 0;                  // wave-uniform: staged entries, next to take
+
+  using LdsLaunch = const __attribute__((address_space(3))) Launch*;
+  using LdsStart = const __attribute__((address_space(3))) StartConst*;
+  auto launch = [&]() {
+    LdsLaunch q = (LdsLaunch)&lds_P;
+    asm volatile("" : "+v"(q));
+    return q;
+  };
+  auto begin = [&](const double* y) {
+    lane_va0[0][lane] = y[9];
+    lane_va0[1][lane] = y[10];
+    lane_va0[2][lane] = y[11];
+    LdsStart q = (LdsStart)&lds_S;
+    asm volatile("" : "+v"(q));
+    StartConst S;
+    S.t0 = q->t0;
+    S.cph0 = q->cph0;
+    S.sph0 = q->sph0;
+    S.hcap = q->hcap;
+    S.hmin0 = q->hmin0;
+    S.thr = q->thr;
+    S.hinit_den = q->hinit_den;
+    start(Fc, S, y, L);
+    busy = 1;
+  };
+  auto update_priority = [&]() {
+    // priority of the longest trajectory the wave holds; a wave holding one
+    // predicted to last at least half as long as the longest carries the
+    // critical path and refills only once all its lanes are free
+    if (top > 0.0f) {
+      float m = busy ? mykey : 0.0f;
+      for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, WAVE));
+      const float frac = wave_uniform(m / top);
+      set_wave_priority(frac);
+      critical = frac >= 0.5f;
+    }
+  };
+
+  if (idx < P.n) {
+    mykey = P.key ? P.key[idx] : 0.0f;
+    idx = P.order ? (long long)P.order[idx] : idx;
+    double y[12];
+    load_column(P, idx, y);
+    begin(y);
+  }
+  update_priority();
 
   for (;;) {
-    // idle lanes draw queue positions: one atomic per wave for all of them.
-    // A wave still holding a trajectory predicted to last at least half as
-    // long as the longest one carries the critical path and refills only
-    // once all its lanes are idle.
-    if (!exhausted) {
-      const unsigned long long idle = __ballot(!busy && !pending);
-      const bool any_busy = __ballot(busy) != 0ull;
-      if (idle && (!any_busy || (__popcll(idle) >= P.refill_min && !critical))) {
-        const int cnt = __popcll(idle);
-        const int leader = __ffsll((unsigned long long)idle) - 1;
-        unsigned long long base = 0;
-        if ((int)(threadIdx.x % WAVE) == leader)
-          base = atomicAdd(P.queue, (unsigned long long)cnt);
-        base = __shfl(base, leader, WAVE);
-        const long long first = P.first_dynamic + (long long)base;
-        const long long n = P.n;
-        if (!busy && !pending) {
-          const long long mine = first + lanes_below(idle);
-          if (mine < n) {
-            idx = P.order ? (long long)P.order[mine] : mine;
-            mykey = P.key ? P.key[mine] : 0.0f;
-            pending = true;
-          }
-        }
-        if (first + cnt >= n) exhausted = true;
-      }
-    }
-    if (__ballot(pending)) {
-      if (top > 0.0f) {
-        // priority of the longest trajectory the wave holds
-        float m = (busy || pending) ? mykey : 0.0f;
-        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, WAVE));
-        const float frac = wave_uniform(top > 0.0f ? m / top : 0.0f);
-        set_wave_priority(frac);
-        critical = frac >= 0.5f;
-      }
-      if (pending) {
-        start(P, idx, L);
-        pending = false;
-        busy = true;
-      }
-    }
-    if (__ballot(busy) == 0ull) {
-      if (exhausted) break;
-      continue;
-    }
     // integrate until enough lanes are free for a refill: refill_min of them
-    // (idle lanes included), or all of them once the queue is empty or while
-    // the wave is critical.  Lanes whose trajectory has ended wait, frozen,
-    // for their store, so the wave runs the store and start-up code once per
-    // batch instead of once per ended trajectory.
+    // (idle lanes included), or all of them once nothing is left to start or
+    // while the wave is critical.  Ended lanes wait, frozen, for their store.
     for (;;) {
       if (busy && L.status == 0) {
         if (L.fresh) begin_step(K, L);
@@ -776,13 +824,67 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
       }
       const unsigned long long live = __ballot(busy && L.status == 0);
       if (live == 0ull) break;
-      if (!exhausted && !critical && __popcll(~live) >= P.refill_min) break;
+      if ((!drained || head < avail) && !critical && __popcll(~live) >= refill_min) break;
     }
     if (busy && L.status != 0) {
-      finish(P, L, idx);
-      busy = false;
+      const LdsLaunch Q = launch();
+      finish(Q->yf, Q->obs, Q->ld, L, idx, lane_va0[0][lane], lane_va0[1][lane], lane_va0[2][lane]);
+      busy = 0;
       mykey = 0.0f;
     }
+    // free lanes take staged entries; a new chunk is claimed when none are left
+    bool started = false;
+    for (;;) {
+      const unsigned long long idle = __ballot(!busy);
+      if (idle == 0ull) break;
+      if (head >= avail) {
+        if (drained) break;
+        const LdsLaunch Q = launch();
+        const long long n = Q->n;
+        const long long left = n - front;
+        const int want =
+            left > (long long)CHUNK * TAIL_ROUNDS * (long long)gridDim.x ? CHUNK : CHUNK_TAIL;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(Q->queue, (unsigned long long)want);
+        base = __shfl(base, 0, WAVE);
+        const long long first = Q->first_dynamic + (long long)base;
+        long long cnt = n - first;
+        cnt = cnt < 0 ? 0 : (cnt > want ? want : cnt);
+        front = first + want;
+        if (front >= n) drained = true;
+        __syncthreads();  // earlier reads of the staging area are complete
+        if (lane < cnt) {
+          const long long pos = first + lane;
+          const unsigned* order = Q->order;
+          const float* key = Q->key;
+          const double* y0 = Q->y0;
+          const long long ld = Q->ld;
+          const long long t = order ? (long long)order[pos] : pos;
+          stage_idx[lane] = t;
+          stage_key[lane] = key ? key[pos] : 0.0f;
+#pragma unroll
+          for (int c = 0; c < 12; ++c) stage_y[c][lane] = y0[c * ld + t];
+        }
+        __syncthreads();  // staged entries visible to every lane
+        avail = (int)cnt;
+        head = 0;
+        if (avail == 0) break;
+      }
+      const int e = head + (int)lanes_below(idle);
+      if (!busy && e < avail) {
+        idx = stage_idx[e];
+        mykey = stage_key[e];
+        double y[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) y[c] = stage_y[c][e];
+        begin(y);
+      }
+      const int took = __popcll(idle);
+      head = head + took < avail ? head + took : avail;
+      started = true;
+    }
+    if (__ballot(busy) == 0ull) break;  // nothing running and nothing left to start
+    if (started) update_priority();
   }
 }
 
