@@ -344,7 +344,7 @@ __device__ __forceinline__ void load_column(const Launch& P, long long idx, doub
 // every trajectory of a call: t0, the trap phase at t0, the initial step's cap
 // min(hmax, tf - t0) and floor 16 eps(t0), AbsTol/RelTol, 0.8 RelTol^(1/5).
 struct StartConst {
-  double t0, cph0, sph0, hcap, hmin0, thr, hinit_den;
+  double t0, cph0, sph0, hcap, hmin0, thr, inv_hinit;  // inv_hinit = 1 / (0.8 rtol^(1/5))
 };
 
 __device__ __forceinline__ StartConst start_const(const Launch& P) {
@@ -354,7 +354,7 @@ __device__ __forceinline__ StartConst start_const(const Launch& P) {
   S.hcap = fmin(P.hmax, P.tf - P.t0);
   S.hmin0 = 16.0 * spacing(P.t0);
   S.thr = P.thr;
-  S.hinit_den = P.hinit_den;
+  S.inv_hinit = 1.0 / P.hinit_den;
   return S;
 }
 
@@ -376,32 +376,39 @@ __device__ __forceinline__ void start(const Force& Fc, const StartConst& S, cons
   L.t = S.t0;
   L.nsteps = L.bounces = 0;
   L.nfailed = 0;
-  L.status = 0;
   L.fresh = true;
   L.done = false;
   L.nofailed = true;
 
   // initial step: the weighted first-order increment h f(t0, y0) equals
   // 0.8 rtol^(1/5); position derivatives are the velocities.  The largest
-  // |f_c| / max(|y_c|, thr) is found by cross-multiplication.
+  // |f_c| / max(|y_c|, thr) is found by cross-multiplication along two chains
+  // (the six position and the six velocity components) merged at the end,
+  // which keeps both the registers and the dependency chain short, then one
+  // reciprocal.
   bool finite = true;
-  double num = 0.0, den = 1.0;
+  double num[2] = {0.0, 0.0}, den[2] = {1.0, 1.0};
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
+    const int g = c < 6 ? 0 : 1;
     const double f = c < 6 ? L.v[c] : L.F1[c - 6];
     const double y = c < 6 ? L.x[c] : L.v[c - 6];
     finite = finite && isfinite(f) && isfinite(y);
-    const double nc = fabs(f), dc = fmax(fabs(y), S.thr);
-    if (nc * den > num * dc) {
-      num = nc;
-      den = dc;
+    const double dc = max_abs(y, S.thr);
+    if (fabs(f) * den[g] > fabs(num[g]) * dc) {
+      num[g] = f;
+      den[g] = dc;
     }
   }
-  const double rh = num / den / S.hinit_den;
+  if (fabs(num[1]) * den[0] > fabs(num[0]) * den[1]) {
+    num[0] = num[1];
+    den[0] = den[1];
+  }
+  const double rh = fabs(num[0]) * recip(den[0]) * S.inv_hinit;
   double absh = S.hcap;
-  if (absh * rh > 1.0) absh = 1.0 / rh;
+  if (absh * rh > 1.0) absh = recip(rh);
   L.absh = fmax(absh, S.hmin0);
-  if (!finite) L.status = AI_ST_NONFINITE;
+  L.status = finite ? 0 : AI_ST_NONFINITE;
 
   const double w = fma(dz, L.v[2] - L.v[5], fma(dy, L.v[1] - L.v[4], dx * (L.v[0] - L.v[3])));
   L.approached = (w >= 0.0);
@@ -760,7 +767,6 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
   const Force Fc = lane_force(P);
   Lane L;
   long long idx = (long long)blockIdx.x * BLOCK + lane;
-  float mykey = 0.0f;
   int busy = 0;                             // integrating, or ended and not yet stored
   bool critical = false;                    // wave-uniform
   bool drained = P.first_dynamic >= P.n;    // wave-uniform: no more claims succeed
@@ -787,31 +793,29 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
     S.hcap = q->hcap;
     S.hmin0 = q->hmin0;
     S.thr = q->thr;
-    S.hinit_den = q->hinit_den;
+    S.inv_hinit = q->inv_hinit;
     start(Fc, S, y, L);
     busy = 1;
   };
-  auto update_priority = [&]() {
-    // priority of the longest trajectory the wave holds; a wave holding one
-    // predicted to last at least half as long as the longest carries the
-    // critical path and refills only once all its lanes are free
-    if (top > 0.0f) {
-      float m = busy ? mykey : 0.0f;
-      for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, WAVE));
-      const float frac = wave_uniform(m / top);
-      set_wave_priority(frac);
-      critical = frac >= 0.5f;
-    }
+  // priority from the wave's longest predicted trajectory (as a fraction of
+  // the longest overall); a wave holding one predicted to last at least half
+  // as long carries the critical path and refills only once all its lanes are
+  // free.  Positions are handed out in decreasing order of predicted
+  // duration, so the wave's first position is its longest, and after a
+  // critical wave drains, the first of its new ones is.
+  auto set_priority = [&](float k) {
+    const float frac = top > 0.0f ? k / top : 0.0f;
+    set_wave_priority(frac);
+    critical = frac >= 0.5f;
   };
 
+  if (P.key) set_priority(P.key[(long long)blockIdx.x * BLOCK]);  // the grid never exceeds n
   if (idx < P.n) {
-    mykey = P.key ? P.key[idx] : 0.0f;
     idx = P.order ? (long long)P.order[idx] : idx;
     double y[12];
     load_column(P, idx, y);
     begin(y);
   }
-  update_priority();
 
   for (;;) {
     // integrate until enough lanes are free for a refill: refill_min of them
@@ -830,10 +834,10 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
       const LdsLaunch Q = launch();
       finish(Q->yf, Q->obs, Q->ld, L, idx, lane_va0[0][lane], lane_va0[1][lane], lane_va0[2][lane]);
       busy = 0;
-      mykey = 0.0f;
     }
+    const bool was_drained = __ballot(busy) == 0ull;
+    float first_key = -1.0f;  // key of the first entry taken
     // free lanes take staged entries; a new chunk is claimed when none are left
-    bool started = false;
     for (;;) {
       const unsigned long long idle = __ballot(!busy);
       if (idle == 0ull) break;
@@ -870,10 +874,10 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
         head = 0;
         if (avail == 0) break;
       }
+      if (first_key < 0.0f) first_key = stage_key[head];
       const int e = head + (int)lanes_below(idle);
       if (!busy && e < avail) {
         idx = stage_idx[e];
-        mykey = stage_key[e];
         double y[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) y[c] = stage_y[c][e];
@@ -881,10 +885,9 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
       }
       const int took = __popcll(idle);
       head = head + took < avail ? head + took : avail;
-      started = true;
     }
     if (__ballot(busy) == 0ull) break;  // nothing running and nothing left to start
-    if (started) update_priority();
+    if (critical && was_drained && first_key >= 0.0f) set_priority(first_key);
   }
 }
 
