@@ -199,6 +199,52 @@ def test_kernels_and_schedules_agree_bitwise(ai, torch, kernel, schedule, refill
     assert np.all(b[0][:, 1000:] == -7.0) and np.all(b[1][:, 1000:] == -7.0)
 
 
+@pytest.fixture(scope="module")
+def queue_ensemble(ai, torch):
+    """Initial states for sizes past the persistent grid's lane count, where
+    the device queue hands out the remaining positions in chunks."""
+    lanes = ai.ai_get_kernel_info("persistent")["persistent_blocks"] * 64
+    wl = W.full_ensemble()
+    return wl, lanes, wl.initial_states(3 * lanes + 5)
+
+
+@pytest.mark.parametrize("extra", [1, 7, 8, 31, 32, 33, 1000, "3x"])
+def test_queue_chunks_agree_bitwise(ai, torch, queue_ensemble, extra):
+    """Sizes just past the statically assigned lanes, around chunk boundaries
+    and through the small chunks near the queue's end: the persistent kernel
+    (refill thresholds 1 and 64, with and without the schedule) matches the
+    plain kernel bit for bit, and writes nothing past n."""
+    wl, lanes, y0all = queue_ensemble
+    n = 3 * lanes + 5 if extra == "3x" else lanes + extra
+    y0 = y0all[:, :n]
+    ld = n + 3
+    a = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "plain", ld=ld)
+    for schedule, refill in ((None, 1), ("longest-first", 1), ("longest-first", 64)):
+        b = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "persistent",
+                    ld=ld, schedule=schedule, refill_min=refill)
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+        assert np.all(b[0][:, n:] == -7.0) and np.all(b[1][:, n:] == -7.0)
+    # every trajectory ran: statuses are all set
+    assert np.all(a[1][O["status"], :n] > 0)
+
+
+def test_queue_in_place_final_state(ai, torch, queue_ensemble):
+    """final_state == y0 through the queue path: each column is read when its
+    chunk is claimed and written when its own trajectory ends."""
+    wl, lanes, y0all = queue_ensemble
+    n = lanes + 777
+    y0 = np.ascontiguousarray(y0all[:, :n])
+    ref = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
+    d = torch.from_numpy(y0.copy()).cuda()
+    obs = torch.empty((13, n), dtype=torch.float64, device="cuda")
+    ai.ai_integrate(wl.system, d, wl.t0, wl.tmax, wl.rtol, wl.atol, d, obs, "persistent",
+                    schedule="longest-first", refill_min=1)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(d.cpu().numpy(), ref[0])
+    np.testing.assert_array_equal(obs.cpu().numpy(), ref[1])
+
+
 def test_run_to_run_determinism(ai, torch):
     wl = W.small_ensemble()
     y0 = wl.initial_states(4096)
