@@ -122,7 +122,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=None, help="ensemble size (default 2^20)")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 20,
+                    help="trajectories the oracle baseline integrates (default: the whole ensemble)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -168,14 +169,15 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    def call(kernel, schedule, refill):
+    def call(kernel, schedule, refill, precision="fp64"):
         return binding.ai_integrate_async(wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, fin,
                                           obs, kernel=kernel, stream=stream, schedule=schedule,
-                                          refill_min=refill)
+                                          refill_min=refill, precision=precision)
 
-    def timed(kernel, steps, warmup, schedule=args.schedule, refill=args.refill_min):
+    def timed(kernel, steps, warmup, schedule=args.schedule, refill=args.refill_min,
+              precision="fp64"):
         for _ in range(warmup):
-            call(kernel, schedule, refill)
+            call(kernel, schedule, refill, precision)
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
@@ -186,7 +188,7 @@ def main() -> int:
         t_start.record(stream)
         for a, b in ev:
             a.record(stream)
-            call(kernel, schedule, refill)
+            call(kernel, schedule, refill, precision)
             b.record(stream)
         t_end.record(stream)
         torch.cuda.synchronize()
@@ -219,8 +221,16 @@ def main() -> int:
                 other.append({"kernel": okernel, "schedule": osched, "ms_per_step": o_ms,
                               "steps_per_s": nsteps / (o_ms / 1e3),
                               "timed_kernel_speedup": o_ms / ms_per_step})
+        # the precision variant: single-precision stages (plain kernel)
+        k = max(1, min(args.steps, 5))
+        o_total, _, _ = timed("plain", k, 1, "longest-first", 0, "fp32-stages")
+        o_ms = o_total / k
+        other.append({"kernel": "plain", "schedule": "longest-first",
+                      "precision": "fp32-stages", "ms_per_step": o_ms,
+                      "accepted_steps_per_call": float(obs[W.OBS["nsteps"]].sum().item()),
+                      "timed_kernel_speedup": o_ms / ms_per_step})
         if args.sweep_refill:
-            for k_ in (8, 16, 32, 48, 64):
+            for k_ in (1, 8, 16, 32, 64):
                 o_total, _, _ = timed("persistent", 3, 1, "longest-first", k_)
                 other.append({"kernel": "persistent", "schedule": "longest-first",
                               "refill_min": k_, "ms_per_step": o_total / 3})

@@ -86,7 +86,16 @@ enum ai_kernel {
    * lane integrates which trajectory, never a result.  Takes 16 n bytes plus
    * sort scratch from the stream-ordered allocator for the call; ignored for
    * n >= 2^32. */
-  AI_SCHEDULE_LONGEST_FIRST = 16
+  AI_SCHEDULE_LONGEST_FIRST = 16,
+  /* flag, plain kernel only (AI_EUNSUPPORTED with the persistent kernel): the
+   * precision variant.  Stage increments, forces and the error estimate's
+   * sums run in single precision; the state accumulation, t, h, the trap
+   * phase and the error norm stay double.  Stage positions are the double
+   * state plus single-precision increments, and the ion-atom separation is
+   * formed in double before narrowing.  Results differ from the double
+   * kernels by the single-precision rounding of the stage arithmetic (each
+   * observable's difference is stated with the tests). */
+  AI_FP32_STAGES = 32
 };
 
 /* Persistent kernel only, OR-ed into the kernel argument: a wave draws new
@@ -117,7 +126,9 @@ enum ai_rc {
  *   the latest.  rtol > 0 and atol > 0 are ode45's RelTol and scalar AbsTol.
  * kernel: AI_KERNEL_PLAIN or AI_KERNEL_PERSISTENT, optionally OR
  *   AI_SCHEDULE_LONGEST_FIRST and (persistent) AI_REFILL_MIN(k); every
- *   combination gives bitwise-identical per-trajectory results.
+ *   combination gives bitwise-identical per-trajectory results.  Or
+ *   AI_KERNEL_PLAIN | AI_FP32_STAGES (schedule optional): the precision
+ *   variant, deterministic but not bitwise equal to the double kernels.
  * The caller owns every buffer.  Returns AI_OK, AI_WRTOL or a negative
  * ai_rc; a failing call leaves the outputs unspecified. */
 int ai_integrate(const ai_params *p, const double *y0, int64_t n, int64_t ld, double t0,
@@ -144,7 +155,8 @@ typedef struct ai_kernel_info {
   int64_t persistent_blocks;  /* grid of the persistent kernel */
 } ai_kernel_info;
 
-/* Fill *info for AI_KERNEL_PLAIN or AI_KERNEL_PERSISTENT (schedule flag
+/* Fill *info for AI_KERNEL_PLAIN or AI_KERNEL_PERSISTENT, with AI_FP32_STAGES
+ * for the single-precision-stage plain kernel (schedule and refill bits
  * ignored).  Returns AI_OK or a negative ai_rc. */
 int ai_get_kernel_info(int32_t kernel, ai_kernel_info *info);
 

@@ -20,6 +20,8 @@ NOBS = 13
 KERNELS = {"plain": 0, "persistent": 1}
 SCHEDULE_LONGEST_FIRST = 16
 SCHEDULES = {None: 0, "index": 0, "longest-first": SCHEDULE_LONGEST_FIRST}
+FP32_STAGES = 32                      # AI_FP32_STAGES
+PRECISIONS = {"fp64": 0, "fp32-stages": FP32_STAGES}
 OK, WRTOL, EINVAL, EHIP, ENOMEM, EUNSUPPORTED = 0, 1, -1, -2, -3, -4
 
 # exported symbols of the C ABI, in declaration order
@@ -114,12 +116,13 @@ def _planes(t, rows: int, name: str):
     return t.data_ptr(), t.shape[1]
 
 
-def kernel_code(kernel, schedule=None, refill_min=0) -> int:
+def kernel_code(kernel, schedule=None, refill_min=0, precision="fp64") -> int:
     """ai_integrate's kernel argument: "plain" or "persistent" (or an int),
-    with schedule "longest-first" adding AI_SCHEDULE_LONGEST_FIRST and
-    refill_min adding AI_REFILL_MIN(refill_min)."""
+    with schedule "longest-first" adding AI_SCHEDULE_LONGEST_FIRST,
+    refill_min adding AI_REFILL_MIN(refill_min) and precision "fp32-stages"
+    adding AI_FP32_STAGES."""
     k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
-    return k | SCHEDULES[schedule] | (int(refill_min) << 8)
+    return k | SCHEDULES[schedule] | (int(refill_min) << 8) | PRECISIONS[precision]
 
 
 def _args(system, y0, n, t0, tmax, rtol, atol, final_state, obs, kernel):
@@ -141,28 +144,29 @@ def _check(rc: int) -> int:
 
 
 def ai_integrate(system, y0, t0, tmax, rtol, atol, final_state, obs, kernel="plain", n=None,
-                 schedule=None, refill_min=0):
+                 schedule=None, refill_min=0, precision="fp64"):
     """Blocking ai_integrate.  Returns AI_OK or AI_WRTOL; raises on errors."""
-    k = kernel_code(kernel, schedule, refill_min)
+    k = kernel_code(kernel, schedule, refill_min, precision)
     return _check(load().ai_integrate(*_args(system, y0, n, t0, tmax, rtol, atol, final_state,
                                              obs, k)))
 
 
 def ai_integrate_async(system, y0, t0, tmax, rtol, atol, final_state, obs, kernel="plain",
-                       n=None, stream=None, schedule=None, refill_min=0):
+                       n=None, stream=None, schedule=None, refill_min=0, precision="fp64"):
     """ai_integrate_async on `stream` (a torch.cuda.Stream; default: torch's
     current stream)."""
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
-    k = kernel_code(kernel, schedule, refill_min)
+    k = kernel_code(kernel, schedule, refill_min, precision)
     return _check(load().ai_integrate_async(*_args(system, y0, n, t0, tmax, rtol, atol,
                                                    final_state, obs, k),
                                             C.c_void_p(s.cuda_stream)))
 
 
-def ai_get_kernel_info(kernel="plain") -> dict:
+def ai_get_kernel_info(kernel="plain", precision="fp64") -> dict:
     info = AiKernelInfo()
-    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel) & 0xf
+    k = (KERNELS[kernel] | PRECISIONS[precision] if isinstance(kernel, str)
+         else int(kernel) & (0xf | FP32_STAGES))
     _check(load().ai_get_kernel_info(k, C.byref(info)))
     return info.as_dict()
 

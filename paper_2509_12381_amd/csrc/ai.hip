@@ -92,6 +92,8 @@ struct Launch {
   int max_steps;
   int exit_on;               // r_exit > 0
   int refill_min;            // persistent kernel: idle lanes a wave gathers before drawing work
+  double near2;              // single-precision stages: squared distance below which a wave
+                             // integrates in double
   const double* y0;          // n x 12 initial states (planes of ld)
   double* yf;                // n x 12 final states (may alias y0)
   double* obs;               // n x AI_NOBS observables
@@ -107,8 +109,10 @@ struct Launch {
 // two doubles), so they follow the rounded time t as a direct evaluation
 // would.  The step size h always equals absh here
 // (integration runs forward), and the step floor 16 eps(t) is recomputed.
-struct Lane {
-  double x[6], v[6], F1[6];
+template <class R>
+struct LaneT {
+  double x[6], v[6];
+  R F1[6];                   // in the stage precision R
   double t, absh;
   double cph, sph;           // cos and sin of omega t
   double w_prev, t_first, t_last, position, rmin2;
@@ -118,6 +122,8 @@ struct Lane {
   // mask in scalar registers, an int in one vector register
   int done, nofailed, fresh, approached;
 };
+using Lane = LaneT<double>;
+using Lane32 = LaneT<float>;
 
 // The integration loop's constants other than the force constants, one copy
 // per lane in vector registers.  A wave has about 100 scalar registers; the
@@ -153,6 +159,26 @@ __device__ __forceinline__ Force lane_force(const Launch& P) {
   for (int k = 0; k < 3; ++k) {
     f.ka[k] = in_vgpr(P.ka[k]);
     f.kq[k] = in_vgpr(P.kq[k]);
+  }
+  return f;
+}
+
+// The force constants in single precision, for the single-precision-stage
+// variant.
+struct Force32 {
+  float inv_mi, inv_ma, nCn, mCm, ka[3], kq[3];
+};
+
+__device__ __forceinline__ Force32 lane_force32(const Launch& P) {
+  Force32 f;
+  f.inv_mi = (float)P.inv_mi;
+  f.inv_ma = (float)P.inv_ma;
+  f.nCn = (float)P.nCn;
+  f.mCm = (float)P.mCm;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    f.ka[k] = in_vgpr((float)P.ka[k]);
+    f.kq[k] = in_vgpr((float)P.kq[k]);
   }
   return f;
 }
@@ -340,6 +366,31 @@ __device__ __forceinline__ void load_column(const Launch& P, long long idx, doub
   for (int c = 0; c < 12; ++c) y[c] = P.y0[c * P.ld + idx];
 }
 
+// 1/a in single precision: hardware estimate and one Newton step.
+__device__ __forceinline__ float recipf(float a) {
+  const float r = __builtin_amdgcn_rcpf(a);
+  return fmaf(r, fmaf(-a, r, 1.0f), r);
+}
+
+// The accelerations of accel() in single precision, from the separation
+// d = x_ion - x_atom and the ion position xi, both formed by the caller from
+// the double-precision state plus single-precision stage increments.
+// Returns r^2.
+__device__ __forceinline__ float accel32(const Force32& P, float cosrf, const float* d,
+                                         const float* xi, float* F) {
+  const float r2 = fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0]));
+  const float s = recipf(r2);
+  const float s2 = s * s;
+  const float g = (s2 * s) * fmaf(-P.mCm, s2, P.nCn);
+  const float gi = g * P.inv_mi, ga = g * P.inv_ma;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    F[k] = -fmaf(gi, d[k], fmaf(P.kq[k], cosrf, P.ka[k]) * xi[k]);
+    F[3 + k] = ga * d[k];
+  }
+  return r2;
+}
+
 // What starting a trajectory needs besides its initial state, the same for
 // every trajectory of a call: t0, the trap phase at t0, the initial step's cap
 // min(hmax, tf - t0) and floor 16 eps(t0), AbsTol/RelTol, 0.8 RelTol^(1/5).
@@ -419,7 +470,8 @@ __device__ __forceinline__ void start(const Force& Fc, const StartConst& S, cons
 
 // Step set-up of ode45: floor and cap the step, stretch it onto tf when within
 // 10% of the remaining span.
-__device__ __forceinline__ void begin_step(const Ctl& K, Lane& L) {
+template <class R>
+__device__ __forceinline__ void begin_step(const Ctl& K, LaneT<R>& L) {
   const double hmin = 16.0 * spacing(L.t);
   L.absh = vmin(K.hmax, vmax(hmin, L.absh));
   L.done = false;
@@ -430,18 +482,11 @@ __device__ __forceinline__ void begin_step(const Ctl& K, Lane& L) {
   L.nofailed = true;
 }
 
-// One Dormand-Prince attempt of size h = absh from (t, x, v), the error test
-// and the controller; on acceptance the state advances and the observables
-// and exits are updated.
-__device__ __forceinline__ void attempt(const Force& P, const Ctl& K, Lane& L) {
-  const double t = L.t, h = L.absh, hh = h * h;
-  const double tnew = L.done ? K.tf : t + h;  // t + h is also tn below
-  const double* x = L.x;
-  const double* v = L.v;
-  const double* F1 = L.F1;
-  double X[6], F2[6], F3[6], F4[6], F5[6], F6[6], F7[6];
-  double dx, dy, dz;
-
+// Trap phase at the stage times t + c h, c = 1/5, 3/10, 4/5, 8/9, 1: cos for
+// each and sin for the last, from the tracked (cos, sin)(omega t).
+__device__ __forceinline__ void stage_phases(const Ctl& K, double cph, double sph, double t,
+                                             double h, double& cs2, double& cs3, double& cs4,
+                                             double& cs5, double& cs6, double& sn6) {
   // trap phase at the stage times: rotations of (cos, sin)(omega t) by
   // c omega (t_new - t), the exact step span of the double t_new (it differs
   // from h by the rounding of t + h, a stage-time shift no larger than the
@@ -453,12 +498,11 @@ __device__ __forceinline__ void attempt(const Force& P, const Ctl& K, Lane& L) {
   const double tn = t + h;
   const double omega = K.omega;
   const double d6 = omega * (tn - t);
-  double cs2, cs3, cs4, cs5, cs6, sn6;
   {
     const Rot r1 = rot_small(0.1 * d6), phi = rot_small((1.0 / 9.0) * d6);
     const Rot r2 = rot_twice(r1), r3 = rot_add(r2, r1), r4 = rot_twice(r2);
     const Rot r8 = rot_twice(r4), r10 = rot_add(r8, r2), r89 = rot_sub(r10, phi);
-    const double C = L.cph, S = L.sph;
+    const double C = cph, S = sph;
     cs2 = fma(C, r2.c, -(S * r2.s));
     cs3 = fma(C, r3.c, -(S * r3.s));
     cs4 = fma(C, r8.c, -(S * r8.s));
@@ -473,6 +517,90 @@ __device__ __forceinline__ void attempt(const Force& P, const Ctl& K, Lane& L) {
       sincos_rf(omega * tn, cs6, sn6);
     }
   }
+}
+
+// The rest of an attempt, the same in both stage precisions: the error test
+// and ode45's step-size control; on acceptance the state advances (xn, vn,
+// F7 at tnew, the phase rotated to tnew) and the observables and exits are
+// updated from the separation d = (dx, dy, dz) and r2n = |d|^2 at tnew.
+template <class R, class R7>
+__device__ __forceinline__ void conclude(const Ctl& K, LaneT<R>& L, double t, double h,
+                                         double tnew, double err, const double* xn,
+                                         const double* vn, const R7* F7, double cs6,
+                                         double sn6, double dx, double dy, double dz,
+                                         double r2n) {
+  if (!isfinite(err)) {
+    L.status = AI_ST_NONFINITE;
+    return;
+  }
+  const double w5 = inv_fifth_root(err * K.inv_rtol);  // (err/rtol)^(-1/5)
+  if (err > K.rtol) {
+    L.nfailed += 1;
+    const double hmin = 16.0 * spacing(t);
+    if (h <= hmin) {
+      L.status = AI_ST_HMIN;
+      return;
+    }
+    L.absh = L.nofailed ? fmax(hmin, h * fmax(0.1, 0.8 * w5)) : fmax(hmin, 0.5 * h);
+    L.nofailed = false;
+    L.done = false;
+    L.fresh = false;
+    return;
+  }
+
+  // accepted
+  L.nsteps += 1;
+  L.t = tnew;
+  L.cph = cs6;
+  L.sph = sn6;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    L.x[c] = xn[c];
+    L.v[c] = vn[c];
+    L.F1[c] = (R)F7[c];
+  }
+  // growth 1/(1.25 (err/rtol)^(1/5)), at most 5x
+  if (L.nofailed) L.absh = (w5 < 6.25) ? h * (0.8 * w5) : 5.0 * h;
+  L.fresh = true;
+
+  // observables: closest approach = sign change of r r' from - to +
+  const double w = fma(dz, vn[2] - vn[5], fma(dy, vn[1] - vn[4], dx * (vn[0] - vn[3])));
+  if (L.w_prev < 0.0 && w >= 0.0) {
+    L.approached = true;
+    if (r2n < K.r_bounce2) {
+      L.bounces += 1;
+      if (L.bounces == 1) {
+        L.t_first = tnew;
+        L.position = sqrt(fma(xn[2], xn[2], fma(xn[1], xn[1], xn[0] * xn[0])));
+      }
+      L.t_last = tnew;
+    }
+  }
+  L.w_prev = w;
+  L.rmin2 = vmin(L.rmin2, r2n);
+
+  if (L.approached && K.exit_on && r2n > K.r_exit2)
+    L.status = AI_ST_ESCAPED;
+  else if (L.done)
+    L.status = AI_ST_TMAX;
+  else if (L.nsteps >= K.max_steps)
+    L.status = AI_ST_MAXSTEPS;
+}
+
+// One Dormand-Prince attempt of size h = absh from (t, x, v), the error test
+// and the controller; on acceptance the state advances and the observables
+// and exits are updated.
+__device__ __forceinline__ void attempt(const Force& P, const Ctl& K, Lane& L) {
+  const double t = L.t, h = L.absh, hh = h * h;
+  const double tnew = L.done ? K.tf : t + h;  // t + h is also tn below
+  const double* x = L.x;
+  const double* v = L.v;
+  const double* F1 = L.F1;
+  double X[6], F2[6], F3[6], F4[6], F5[6], F6[6], F7[6];
+  double dx, dy, dz;
+
+  double cs2, cs3, cs4, cs5, cs6, sn6;
+  stage_phases(K, L.cph, L.sph, t, h, cs2, cs3, cs4, cs5, cs6, sn6);
   {
     const double a = C2 * h;
 #pragma unroll
@@ -520,7 +648,7 @@ __device__ __forceinline__ void attempt(const Force& P, const Ctl& K, Lane& L) {
     }
   }
   // stage 7 at tnew; tnew == t + h unless the step was stretched onto tf
-  const double cos7 = L.done ? cos_rf(omega * tnew) : cs6;
+  const double cos7 = L.done ? cos_rf(K.omega * tnew) : cs6;
   const double r2n = accel(P, cos7, xn, F7, dx, dy, dz);
 
   // err = |h| max_c |eps_c| / max(|y_c|, |ynew_c|, AbsTol/RelTol): the
@@ -549,62 +677,140 @@ __device__ __forceinline__ void attempt(const Force& P, const Ctl& K, Lane& L) {
     }
   }
   const double err = nan_seen ? __builtin_nan("") : h * fabs(num[0]) * recip(den[0]);
-  if (!isfinite(err)) {
-    L.status = AI_ST_NONFINITE;
-    return;
-  }
-  const double w5 = inv_fifth_root(err * K.inv_rtol);  // (err/rtol)^(-1/5)
-  if (err > K.rtol) {
-    L.nfailed += 1;
-    const double hmin = 16.0 * spacing(t);
-    if (h <= hmin) {
-      L.status = AI_ST_HMIN;
-      return;
-    }
-    L.absh = L.nofailed ? fmax(hmin, h * fmax(0.1, 0.8 * w5)) : fmax(hmin, 0.5 * h);
-    L.nofailed = false;
-    L.done = false;
-    L.fresh = false;
-    return;
-  }
+  conclude(K, L, t, h, tnew, err, xn, vn, F7, cs6, sn6, dx, dy, dz, r2n);
+}
 
-  // accepted
-  L.nsteps += 1;
-  L.t = tnew;
-  L.cph = cs6;
-  L.sph = sn6;
+// Dormand-Prince coefficients in single precision for the variant below.
+constexpr float C2f = (float)C2, C3f = (float)C3, C4f = (float)C4, C5f = (float)C5;
+constexpr float B1f = (float)B1, B3f = (float)B3, B4f = (float)B4, B5f = (float)B5,
+                B6f = (float)B6;
+constexpr float E1f = (float)E1, E3f = (float)E3, E4f = (float)E4, E5f = (float)E5,
+                E6f = (float)E6, E7f = (float)E7;
+constexpr float Q31f = (float)Q31, Q41f = (float)Q41, Q42f = (float)Q42, Q51f = (float)Q51,
+                Q52f = (float)Q52, Q53f = (float)Q53, Q61f = (float)Q61, Q62f = (float)Q62,
+                Q63f = (float)Q63, Q64f = (float)Q64, Q71f = (float)Q71, Q73f = (float)Q73,
+                Q74f = (float)Q74, Q75f = (float)Q75;
+constexpr float P1f = (float)P1, P3f = (float)P3, P4f = (float)P4, P5f = (float)P5,
+                P6f = (float)P6;
+
+// One attempt with single-precision stages: the stage increments, forces and
+// error sums are float; the state, t, h, the trap phase and the error norm
+// stay double, as does the h v term of every stage position and of the new
+// position.  A stage position is the double state plus a float increment
+// D_s = h^2 sum_l (A^2)_sl F_l (+ c_s h v, narrowed); the ion-atom separation
+// is x_ion - x_atom formed in double once per attempt, narrowed, plus
+// D_s(ion) - D_s(atom), so r keeps its precision at short range.  The error
+// estimate's float rounding (a relative 6e-8 of the cancelling sums) stays far
+// below RelTol for the configured tolerances.
+__device__ __forceinline__ void attempt32(const Force32& P, const Ctl& K, Lane& L) {
+  const double t = L.t, h = L.absh, hh = h * h;
+  const double tnew = L.done ? K.tf : t + h;
+  const double* x = L.x;
+  const double* v = L.v;
+  float F1[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    L.x[c] = xn[c];
-    L.v[c] = vn[c];
-    L.F1[c] = F7[c];
-  }
-  // growth 1/(1.25 (err/rtol)^(1/5)), at most 5x
-  if (L.nofailed) L.absh = (w5 < 6.25) ? h * (0.8 * w5) : 5.0 * h;
-  L.fresh = true;
+  for (int c = 0; c < 6; ++c) F1[c] = (float)L.F1[c];
+  double cs2, cs3, cs4, cs5, cs6, sn6;
+  stage_phases(K, L.cph, L.sph, t, h, cs2, cs3, cs4, cs5, cs6, sn6);
 
-  // observables: closest approach = sign change of r r' from - to +
-  const double w = fma(dz, vn[2] - vn[5], fma(dy, vn[1] - vn[4], dx * (vn[0] - vn[3])));
-  if (L.w_prev < 0.0 && w >= 0.0) {
-    L.approached = true;
-    if (r2n < K.r_bounce2) {
-      L.bounces += 1;
-      if (L.bounces == 1) {
-        L.t_first = tnew;
-        L.position = sqrt(fma(xn[2], xn[2], fma(xn[1], xn[1], xn[0] * xn[0])));
-      }
-      L.t_last = tnew;
+  float d0[3], xi[3], hv[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    d0[k] = (float)(x[k] - x[3 + k]);
+    xi[k] = (float)x[k];
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) hv[c] = (float)(h * v[c]);
+  const float hf = (float)h, hhf = (float)hh;
+  float D[6], d[3], Xi[3], F2[6], F3[6], F4[6], F5[6], F6[6], F7[6];
+  auto stage = [&](double cs, float* F) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      d[k] = d0[k] + (D[k] - D[3 + k]);
+      Xi[k] = xi[k] + D[k];
+    }
+    accel32(P, (float)cs, d, Xi, F);
+  };
+#pragma unroll
+  for (int c = 0; c < 6; ++c) D[c] = C2f * hv[c];
+  stage(cs2, F2);
+  {
+    const float q1 = Q31f * hhf;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) D[c] = fmaf(q1, F1[c], C3f * hv[c]);
+    stage(cs3, F3);
+  }
+  {
+    const float q1 = Q41f * hhf, q2 = Q42f * hhf;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) D[c] = fmaf(q2, F2[c], fmaf(q1, F1[c], C4f * hv[c]));
+    stage(cs4, F4);
+  }
+  {
+    const float q1 = Q51f * hhf, q2 = Q52f * hhf, q3 = Q53f * hhf;
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      D[c] = fmaf(q3, F3[c], fmaf(q2, F2[c], fmaf(q1, F1[c], C5f * hv[c])));
+    stage(cs5, F5);
+  }
+  {
+    const float q1 = Q61f * hhf, q2 = Q62f * hhf, q3 = Q63f * hhf, q4 = Q64f * hhf;
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      D[c] = fmaf(q4, F4[c], fmaf(q3, F3[c], fmaf(q2, F2[c], fmaf(q1, F1[c], hv[c]))));
+    stage(cs6, F6);
+  }
+  // new solution (double state plus float sums), error sums without F7
+  double xn[6], vn[6];
+  float ex[6], ev[6];
+  {
+    const float q1 = Q71f * hhf, q3 = Q73f * hhf, q4 = Q74f * hhf, q5 = Q75f * hhf;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const float G = fmaf(q5, F5[c], fmaf(q4, F4[c], fmaf(q3, F3[c], q1 * F1[c])));
+      const float B =
+          fmaf(B6f, F6[c], fmaf(B5f, F5[c], fmaf(B4f, F4[c], fmaf(B3f, F3[c], B1f * F1[c]))));
+      xn[c] = fma(h, v[c], x[c]) + (double)G;
+      vn[c] = fma(h, (double)B, v[c]);
+      ex[c] = hf * fmaf(P6f, F6[c], fmaf(P5f, F5[c], fmaf(P4f, F4[c], fmaf(P3f, F3[c], P1f * F1[c]))));
+      ev[c] = fmaf(E6f, F6[c], fmaf(E5f, F5[c], fmaf(E4f, F4[c], fmaf(E3f, F3[c], E1f * F1[c]))));
     }
   }
-  L.w_prev = w;
-  L.rmin2 = vmin(L.rmin2, r2n);
+  // stage 7 at tnew from the new double state
+  const double cos7 = L.done ? cos_rf(K.omega * tnew) : cs6;
+  const double dx = xn[0] - xn[3], dy = xn[1] - xn[4], dz = xn[2] - xn[5];
+  {
+    const float dn[3] = {(float)dx, (float)dy, (float)dz};
+    const float xin[3] = {(float)xn[0], (float)xn[1], (float)xn[2]};
+    accel32(P, (float)cos7, dn, xin, F7);
+  }
+  const double r2n = fma(dz, dz, fma(dy, dy, dx * dx));
 
-  if (L.approached && K.exit_on && r2n > K.r_exit2)
-    L.status = AI_ST_ESCAPED;
-  else if (L.done)
-    L.status = AI_ST_TMAX;
-  else if (L.nsteps >= K.max_steps)
-    L.status = AI_ST_MAXSTEPS;
+  // error norm in double, as in attempt()
+  double num[12], den[12];
+  bool nan_seen = false;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const int k = c % 6;
+    const double e = c < 6 ? (double)ex[k] : (double)fmaf(E7f, F7[k], ev[k]);
+    const double y_ = c < 6 ? x[k] : v[k];
+    const double yn_ = c < 6 ? xn[k] : vn[k];
+    num[c] = e;
+    den[c] = max_abs(max_abs(y_, yn_), K.thr);
+    nan_seen = nan_seen || (e != e);
+  }
+#pragma unroll
+  for (int w = 1; w < 12; w *= 2) {
+#pragma unroll
+    for (int c = 0; c + w < 12; c += 2 * w) {
+      if (fabs(num[c + w]) * den[c] > fabs(num[c]) * den[c + w]) {
+        num[c] = num[c + w];
+        den[c] = den[c + w];
+      }
+    }
+  }
+  const double err = nan_seen ? __builtin_nan("") : h * fabs(num[0]) * recip(den[0]);
+  conclude(K, L, t, h, tnew, err, xn, vn, F7, cs6, sn6, dx, dy, dz, r2n);
 }
 
 // End of trajectory idx: store the final state and the raw accumulators.
@@ -614,7 +820,8 @@ __device__ __forceinline__ void attempt(const Force& P, const Ctl& K, Lane& L) {
 // t_last, the atom's initial velocity (3 planes) and rmin^2.
 // va0 is the atom's initial velocity (kept by the caller: final_state may be
 // the y0 buffer itself).
-__device__ __forceinline__ void finish(double* yf, double* obs, long long ld, const Lane& L,
+template <class R>
+__device__ __forceinline__ void finish(double* yf, double* obs, long long ld, const LaneT<R>& L,
                                        long long idx, double va0x, double va0y, double va0z) {
   double o[AI_NOBS];
   o[AI_OBS_TEND] = L.t;
@@ -695,7 +902,8 @@ __device__ __forceinline__ float wave_uniform(float v) {
 // One trajectory per lane; the grid covers n.  Lane g integrates trajectory
 // order[g] (g itself when order is null); with the schedule's keys the wave
 // takes the priority of its first (longest) trajectory.
-__global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P) {
+template <class R>
+__device__ __forceinline__ void plain_body(const Launch& P) {
   const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
   const float* key = P.key;
   if (key) {
@@ -707,19 +915,40 @@ __global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P) {
   const Ctl K = lane_ctl(P);
   const Force Fc = lane_force(P);
   Lane L;
-  {
-    double y[12];
-    load_column(P, idx, y);
-    start(Fc, start_const(P), y, L);
-  }
-  while (L.status == 0) {
-    if (L.fresh) begin_step(K, L);
-    attempt(Fc, K, L);
+  double y[12];
+  load_column(P, idx, y);
+  start(Fc, start_const(P), y, L);
+  if constexpr (sizeof(R) == sizeof(double)) {
+    while (L.status == 0) {
+      if (L.fresh) begin_step(K, L);
+      attempt(Fc, K, L);
+    }
+  } else {
+    // single-precision stages while the lane's atom is farther than r_near
+    // from its ion, the double attempt closer, so collisions are integrated in
+    // double.  The choice is the lane's own (a wave with lanes on both sides
+    // runs both branches), so results do not depend on which trajectories
+    // share a wave.
+    const Force32 F32 = lane_force32(P);
+    const double near2 = in_vgpr(P.near2);
+    while (L.status == 0) {
+      if (L.fresh) begin_step(K, L);
+      const double dx = L.x[0] - L.x[3], dy = L.x[1] - L.x[4], dz = L.x[2] - L.x[5];
+      if (fma(dz, dz, fma(dy, dy, dx * dx)) < near2)
+        attempt(Fc, K, L);
+      else
+        attempt32(F32, K, L);
+    }
   }
   // the initial atom velocity is read before final_state (possibly y0) is written
   const double* va0 = P.y0 + 9 * P.ld + idx;
   finish(P.yf, P.obs, P.ld, L, idx, va0[0], va0[P.ld], va0[2 * P.ld]);
 }
+
+__global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P) { plain_body<double>(P); }
+
+// The same with single-precision stages (AI_FP32_STAGES).
+__global__ __launch_bounds__(BLOCK) void ai_plain32_kernel(Launch P) { plain_body<float>(P); }
 
 __global__ void ai_queue_reset_kernel(unsigned long long* queue) { *queue = 0ull; }
 
@@ -934,8 +1163,10 @@ bool on_current_device(const void* ptr, int dev) {
 struct DeviceFacts {
   int cus = 0;
   int plain_blocks_per_cu = 0;
+  int plain32_blocks_per_cu = 0;
   int persistent_blocks_per_cu = 0;
   hipFuncAttributes plain_attr{};
+  hipFuncAttributes plain32_attr{};
   hipFuncAttributes persistent_attr{};
   bool ready = false;
 };
@@ -953,11 +1184,16 @@ int device_facts(int dev, DeviceFacts** out) {
       return hip_fail(e, "hipDeviceGetAttribute");
     if ((e = hipFuncGetAttributes(&f.plain_attr, (const void*)ai_plain_kernel)) != hipSuccess)
       return hip_fail(e, "hipFuncGetAttributes(plain)");
+    if ((e = hipFuncGetAttributes(&f.plain32_attr, (const void*)ai_plain32_kernel)) != hipSuccess)
+      return hip_fail(e, "hipFuncGetAttributes(plain32)");
     if ((e = hipFuncGetAttributes(&f.persistent_attr, (const void*)ai_persistent_kernel)) != hipSuccess)
       return hip_fail(e, "hipFuncGetAttributes(persistent)");
     if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&f.plain_blocks_per_cu,
                                                           ai_plain_kernel, BLOCK, 0)) != hipSuccess)
       return hip_fail(e, "occupancy(plain)");
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&f.plain32_blocks_per_cu,
+                                                          ai_plain32_kernel, BLOCK, 0)) != hipSuccess)
+      return hip_fail(e, "occupancy(plain32)");
     if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&f.persistent_blocks_per_cu,
                                                           ai_persistent_kernel, BLOCK, 0)) != hipSuccess)
       return hip_fail(e, "occupancy(persistent)");
@@ -976,9 +1212,11 @@ int validate(const ai_params* p, const double* y0, int64_t n, int64_t ld, double
   if (ld < n) return fail(AI_EINVAL, "ld = %lld < n = %lld", (long long)ld, (long long)n);
   const int32_t base_kernel = kernel & 0xf;
   if ((base_kernel != AI_KERNEL_PLAIN && base_kernel != AI_KERNEL_PERSISTENT) ||
-      (kernel & ~(0xf | AI_SCHEDULE_LONGEST_FIRST | (0x7f << 8))) != 0 ||
+      (kernel & ~(0xf | AI_SCHEDULE_LONGEST_FIRST | AI_FP32_STAGES | (0x7f << 8))) != 0 ||
       ((kernel >> 8) & 0x7f) > 64)
     return fail(AI_EINVAL, "unknown kernel argument 0x%x", (unsigned)kernel);
+  if ((kernel & AI_FP32_STAGES) && base_kernel != AI_KERNEL_PLAIN)
+    return fail(AI_EUNSUPPORTED, "single-precision stages run in the plain kernel only");
   if (!finite_params(p)) return fail(AI_EINVAL, "non-finite system constant");
   if (!(p->m_ion > 0.0) || !(p->m_atom > 0.0)) return fail(AI_EINVAL, "masses must be > 0");
   if (p->n < 1 || p->n >= p->m) return fail(AI_EINVAL, "need 1 <= n < m");
@@ -1047,6 +1285,16 @@ Launch launch_constants(const ai_params* p, int64_t n, int64_t ld, double t0, do
   P.ld = ld;
   P.first_dynamic = 0;
   P.exit_on = p->r_exit > 0.0;
+  // single-precision stages: waves integrate in double within 100 R_e of the
+  // ion, R_e = (m Cm / (n Cn))^(1/(m-n)) the minimum of V (10 a0 for Li +
+  // Yb+); the potential's length scale is unknown otherwise, so double
+  // throughout, unless there is no interaction at all
+  if (p->Cn > 0.0 && p->Cm > 0.0) {
+    const double re = std::pow(p->m * p->Cm / (p->n * p->Cn), 1.0 / (p->m - p->n));
+    P.near2 = (100.0 * re) * (100.0 * re);
+  } else {
+    P.near2 = (p->Cn == 0.0 && p->Cm == 0.0) ? 0.0 : INFINITY;
+  }
   P.refill_min = 1;
   P.y0 = nullptr;
   P.yf = nullptr;
@@ -1075,17 +1323,24 @@ const char* ai_last_error(void) { return g_error.c_str(); }
 
 int ai_get_kernel_info(int32_t kernel, ai_kernel_info* info) {
   if (!info) return fail(AI_EINVAL, "info is NULL");
+  const bool fp32 = (kernel & AI_FP32_STAGES) != 0;
   kernel &= 0xf;
   if (kernel != AI_KERNEL_PLAIN && kernel != AI_KERNEL_PERSISTENT)
     return fail(AI_EINVAL, "unknown kernel %d", kernel);
+  if (fp32 && kernel != AI_KERNEL_PLAIN)
+    return fail(AI_EUNSUPPORTED, "single-precision stages run in the plain kernel only");
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   DeviceFacts* f = nullptr;
   int rc = device_facts(dev, &f);
   if (rc != AI_OK) return rc;
-  const hipFuncAttributes& a = kernel == AI_KERNEL_PLAIN ? f->plain_attr : f->persistent_attr;
-  const int bpc = kernel == AI_KERNEL_PLAIN ? f->plain_blocks_per_cu : f->persistent_blocks_per_cu;
+  const hipFuncAttributes& a = kernel == AI_KERNEL_PERSISTENT ? f->persistent_attr
+                               : fp32                            ? f->plain32_attr
+                                                                 : f->plain_attr;
+  const int bpc = kernel == AI_KERNEL_PERSISTENT ? f->persistent_blocks_per_cu
+                  : fp32                         ? f->plain32_blocks_per_cu
+                                                 : f->plain_blocks_per_cu;
   info->block_threads = BLOCK;
   info->vgprs = a.numRegs;
   info->spill_bytes = (int32_t)a.localSizeBytes;
@@ -1157,7 +1412,10 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
       release();
       return fail(AI_EINVAL, "n too large for one launch");
     }
-    hipLaunchKernelGGL(ai_plain_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
+    if (kernel & AI_FP32_STAGES)
+      hipLaunchKernelGGL(ai_plain32_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
+    else
+      hipLaunchKernelGGL(ai_plain_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
     if ((e = hipGetLastError()) != hipSuccess) {
       release();
       return hip_fail(e, "launch(plain)");
