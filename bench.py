@@ -92,6 +92,56 @@ def write_traffic(fetch_dir: str, write_dir: str, copy_mib: int) -> dict:
     return rec
 
 
+def batched_grid(binding, W, flops, torch, reps: int = 3) -> dict:
+    """The batched configuration: 64 uneven ensembles (collision temperature x
+    trap q) in one longest-first launch of ai_integrate_batch, against the
+    same ensembles as 64 separate longest-first launches on the stream."""
+    grid = W.batch_grid()
+    dev = []
+    for wl in grid:
+        d = torch.from_numpy(wl.initial_states()).cuda()
+        dev.append((wl, d, torch.empty_like(d),
+                    torch.empty((W.NOBS, wl.n), dtype=torch.float64, device="cuda")))
+    items = [(wl.system, d, f, o, wl.t0, wl.tmax, wl.rtol, wl.atol) for wl, d, f, o in dev]
+
+    def batched():
+        binding.ai_integrate_batch_async(items, schedule="longest-first")
+
+    def separate():
+        for wl, d, f, o in dev:
+            binding.ai_integrate_async(wl.system, d, wl.t0, wl.tmax, wl.rtol, wl.atol, f, o,
+                                       "plain", schedule="longest-first")
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            out.append(a.elapsed_time(b))
+        return min(out)
+
+    t_batch = best(batched)
+    obs = [o.cpu().numpy() for *_, o in dev]
+    t_sep = best(separate)
+    n = sum(wl.n for wl, *_ in dev)
+    steps = float(sum(o[W.OBS["nsteps"]].sum() for o in obs))
+    flop = float(sum(flops.algorithmic_flops(o) for o in obs))
+    achieved = flop / (t_batch / 1e3) / 1e12
+    return {"workload": "batch-grid-64", "ensembles": len(dev), "trajectories": n,
+            "ms_per_call": t_batch, "ms_separate_launches": t_sep,
+            "trajectories_per_s": n / (t_batch / 1e3), "accepted_steps_per_s": steps / (t_batch / 1e3),
+            "speedup_vs_separate": t_sep / t_batch,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                         "kernel": "ai_plain_batch_kernel"}}
+
+
 def cpu_baseline(wl, y0_host, sample: int):
     """The oracle as it stands, on the first `sample` trajectories of the same
     ensemble, with the host threads of this process's CPU share."""
@@ -122,6 +172,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=None, help="ensemble size (default 2^20)")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip timing the batched 64-ensemble grid")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="trajectories the oracle baseline integrates (default: the whole ensemble)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -235,6 +287,10 @@ def main() -> int:
                 other.append({"kernel": "persistent", "schedule": "longest-first",
                               "refill_min": k_, "ms_per_step": o_total / 3})
 
+    batched = None
+    if not args.no_batch and args.n is None:
+        batched = batched_grid(binding, W, flops, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, y0_host, min(args.cpu_sample, wl.n))
@@ -271,6 +327,7 @@ def main() -> int:
                      "flop_per_launch": flop, "launch_ms": launch_ms},
         "kernel_info": info,
         "other_variants": other,
+        "batched_grid": batched,
         "cpu_baseline": cpu,
         "wall_s_timed_region": wall,
     }

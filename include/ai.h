@@ -144,6 +144,41 @@ int ai_integrate_async(const ai_params *p, const double *y0, int64_t n, int64_t 
                        double tmax, double rtol, double atol, double *final_state, double *obs,
                        int32_t kernel, void *stream);
 
+/* One ensemble of a batched call: its system, buffers, span and tolerances,
+ * each with the meaning and constraints it has in ai_integrate. */
+typedef struct ai_batch_item {
+  ai_params params;
+  const double *y0;           /* device, 12 planes of ld doubles */
+  int64_t n, ld;
+  double t0, tmax, rtol, atol;
+  double *final_state;        /* device, 12 planes (may equal y0) */
+  double *obs;                /* device, AI_NOBS planes */
+} ai_batch_item;
+
+/* Integrate `count` ensembles of possibly different systems, sizes, spans and
+ * tolerances in one launch of the plain kernel: the trajectories of all items
+ * form one index space (and, with AI_SCHEDULE_LONGEST_FIRST, are handed out by
+ * decreasing predicted duration across items).  This is the batched form of
+ * the paper's ode45gpu call (Sec. 3.3) for uneven ensembles (Sec. 4.2 sweeps
+ * collision energy and trap parameters).
+ *
+ * items: host array of count >= 0 entries (read during the call only).
+ * kernel: AI_KERNEL_PLAIN, optionally OR AI_SCHEDULE_LONGEST_FIRST; other
+ *   flags give AI_EUNSUPPORTED.
+ * Every item is validated as ai_integrate validates its arguments; an invalid
+ * item fails the whole call with AI_EINVAL before anything is launched (the
+ * error text names the item).  Items with n = 0 are skipped.  Output buffers
+ * of different items must not overlap.  Each trajectory's result is bitwise
+ * the one ai_integrate gives for its item alone.  The call takes the items'
+ * launch table (about 350 bytes per item) and, with the schedule, 16 bytes
+ * per trajectory plus sort scratch from the stream-ordered allocator.
+ * Returns AI_OK, AI_WRTOL if any item's rtol was raised, or a negative ai_rc. */
+int ai_integrate_batch_async(const ai_batch_item *items, int32_t count, int32_t kernel,
+                             void *stream);
+
+/* As ai_integrate_batch_async on the null stream, waiting for the result. */
+int ai_integrate_batch(const ai_batch_item *items, int32_t count, int32_t kernel);
+
 /* Launch facts of one kernel on the current device. */
 typedef struct ai_kernel_info {
   int32_t block_threads;      /* threads per workgroup */

@@ -25,8 +25,9 @@ PRECISIONS = {"fp64": 0, "fp32-stages": FP32_STAGES}
 OK, WRTOL, EINVAL, EHIP, ENOMEM, EUNSUPPORTED = 0, 1, -1, -2, -3, -4
 
 # exported symbols of the C ABI, in declaration order
-SYMBOLS = ("ai_integrate", "ai_integrate_async", "ai_get_kernel_info", "ai_last_error",
-           "ai_nobs", "ai_version")
+SYMBOLS = ("ai_integrate", "ai_integrate_async", "ai_integrate_batch",
+           "ai_integrate_batch_async", "ai_get_kernel_info", "ai_last_error", "ai_nobs",
+           "ai_version")
 
 
 class AiParams(C.Structure):
@@ -37,6 +38,15 @@ class AiParams(C.Structure):
         ("a", C.c_double * 3), ("q", C.c_double * 3),
         ("omega_rf", C.c_double), ("r_exit", C.c_double), ("r_bounce", C.c_double),
         ("max_steps", C.c_int64), ("hmax", C.c_double),
+    ]
+
+
+class AiBatchItem(C.Structure):
+    """ai_batch_item: one ensemble of a batched call."""
+    _fields_ = [
+        ("params", AiParams), ("y0", C.c_void_p), ("n", C.c_int64), ("ld", C.c_int64),
+        ("t0", C.c_double), ("tmax", C.c_double), ("rtol", C.c_double), ("atol", C.c_double),
+        ("final_state", C.c_void_p), ("obs", C.c_void_p),
     ]
 
 
@@ -79,6 +89,11 @@ def load(path: str = LIB_PATH):
         lib.ai_integrate.restype = C.c_int
         lib.ai_integrate_async.argtypes = args + [C.c_void_p]
         lib.ai_integrate_async.restype = C.c_int
+        lib.ai_integrate_batch.argtypes = [C.POINTER(AiBatchItem), C.c_int32, C.c_int32]
+        lib.ai_integrate_batch.restype = C.c_int
+        lib.ai_integrate_batch_async.argtypes = [C.POINTER(AiBatchItem), C.c_int32, C.c_int32,
+                                                 C.c_void_p]
+        lib.ai_integrate_batch_async.restype = C.c_int
         lib.ai_get_kernel_info.argtypes = [C.c_int32, C.POINTER(AiKernelInfo)]
         lib.ai_get_kernel_info.restype = C.c_int
         lib.ai_last_error.restype = C.c_char_p
@@ -161,6 +176,41 @@ def ai_integrate_async(system, y0, t0, tmax, rtol, atol, final_state, obs, kerne
     return _check(load().ai_integrate_async(*_args(system, y0, n, t0, tmax, rtol, atol,
                                                    final_state, obs, k),
                                             C.c_void_p(s.cuda_stream)))
+
+
+def batch_items(items) -> "C.Array":
+    """ai_batch_item array from (system, y0, final_state, obs, t0, tmax, rtol,
+    atol[, n]) tuples; the tensors are (12, ld), (12, ld) and (AI_NOBS, ld)."""
+    arr = (AiBatchItem * max(len(items), 1))()
+    for b, it in enumerate(items):
+        system, y0, final_state, obs, t0, tmax, rtol, atol = it[:8]
+        p0, ld = _planes(y0, NSTATE, "y0")
+        p1, ld1 = _planes(final_state, NSTATE, "final_state")
+        p2, ld2 = _planes(obs, NOBS, "obs")
+        if not (ld == ld1 == ld2):
+            raise ValueError("y0, final_state and obs must share the leading dimension")
+        e = arr[b]
+        e.params = system if isinstance(system, AiParams) else params(system)
+        e.y0, e.final_state, e.obs = p0, p1, p2
+        e.n = ld if len(it) < 9 or it[8] is None else int(it[8])
+        e.ld = ld
+        e.t0, e.tmax, e.rtol, e.atol = float(t0), float(tmax), float(rtol), float(atol)
+    return arr
+
+
+def ai_integrate_batch(items, schedule=None):
+    """Blocking ai_integrate_batch over batch_items(items)."""
+    arr = batch_items(items)
+    return _check(load().ai_integrate_batch(arr, len(items), SCHEDULES[schedule]))
+
+
+def ai_integrate_batch_async(items, schedule=None, stream=None):
+    """ai_integrate_batch_async on `stream` (default: torch's current stream)."""
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    arr = batch_items(items)
+    return _check(load().ai_integrate_batch_async(arr, len(items), SCHEDULES[schedule],
+                                                  C.c_void_p(s.cuda_stream)))
 
 
 def ai_get_kernel_info(kernel="plain", precision="fp64") -> dict:

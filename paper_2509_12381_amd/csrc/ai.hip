@@ -36,6 +36,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "ai.h"
 #include "schedule.h"
@@ -852,10 +853,8 @@ __device__ __forceinline__ void finish(double* yf, double* obs, long long ld, co
 // lifetime = t_last - t_first for two or more bounces, scattering angle
 // between the atom's initial and final velocity, momentum transfer
 // m_atom |v - v0|, final distance, final ion kinetic energy, smallest distance.
-__global__ __launch_bounds__(256) void ai_finalize_kernel(Launch P, const double* __restrict__ yf,
-                                                          double* __restrict__ obs) {
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= P.n) return;
+__device__ __forceinline__ void finalize_one(const Launch& P, const double* __restrict__ yf,
+                                             double* __restrict__ obs, long long i) {
   const long long ld = P.ld;
   const double t_first = obs[AI_OBS_LIFETIME * ld + i], t_last = obs[AI_OBS_ANGLE * ld + i];
   const double va0x = obs[AI_OBS_TRANSFER * ld + i], va0y = obs[AI_OBS_DIST * ld + i],
@@ -877,6 +876,50 @@ __global__ __launch_bounds__(256) void ai_finalize_kernel(Launch P, const double
   obs[AI_OBS_DIST * ld + i] = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
   obs[AI_OBS_KE * ld + i] = P.half_mi * fma(y[5], y[5], fma(y[4], y[4], y[3] * y[3]));
   obs[AI_OBS_RMIN * ld + i] = sqrt(rmin2);
+}
+
+__global__ __launch_bounds__(256) void ai_finalize_kernel(Launch P, const double* __restrict__ yf,
+                                                          double* __restrict__ obs) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= P.n) return;
+  finalize_one(P, yf, obs, i);
+}
+
+// One ensemble of a batched call and the global index of its first
+// trajectory; a batch lists them with increasing offsets.
+struct BatchEntry {
+  Launch P;
+  long long offset;
+};
+
+// A batched call: its ensembles (device memory), their total trajectory
+// count and the optional longest-first order over global indices.
+struct BatchLaunch {
+  const BatchEntry* entries;
+  int count;
+  long long total;
+  const unsigned* order;
+  const float* key;
+};
+
+// The ensemble holding global index j: the last entry with offset <= j.
+__device__ __forceinline__ int batch_entry(const BatchEntry* E, int count, long long j) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (E[mid].offset <= j)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void ai_finalize_batch_kernel(BatchLaunch B) {
+  const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (j >= B.total) return;
+  const BatchEntry& E = B.entries[batch_entry(B.entries, B.count, j)];
+  finalize_one(E.P, E.P.yf, E.P.obs, j - E.offset);
 }
 
 // Wave priority from the predicted duration of the wave's longest trajectory
@@ -902,16 +945,9 @@ __device__ __forceinline__ float wave_uniform(float v) {
 // One trajectory per lane; the grid covers n.  Lane g integrates trajectory
 // order[g] (g itself when order is null); with the schedule's keys the wave
 // takes the priority of its first (longest) trajectory.
+// Trajectory idx of the ensemble P, start to end, by one lane.
 template <class R>
-__device__ __forceinline__ void plain_body(const Launch& P) {
-  const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  const float* key = P.key;
-  if (key) {
-    const float top = key[0], mine = key[(long long)blockIdx.x * BLOCK];
-    set_wave_priority(wave_uniform(top > 0.0f ? mine / top : 0.0f));
-  }
-  if (g >= P.n) return;
-  const long long idx = P.order ? (long long)P.order[g] : g;
+__device__ __forceinline__ void integrate_one(const Launch& P, long long idx) {
   const Ctl K = lane_ctl(P);
   const Force Fc = lane_force(P);
   Lane L;
@@ -945,10 +981,39 @@ __device__ __forceinline__ void plain_body(const Launch& P) {
   finish(P.yf, P.obs, P.ld, L, idx, va0[0], va0[P.ld], va0[2 * P.ld]);
 }
 
+// With the schedule's keys a wave takes the priority of its first (longest)
+// trajectory.
+__device__ __forceinline__ void wave_priority_from_keys(const float* key) {
+  if (key) {
+    const float top = key[0], mine = key[(long long)blockIdx.x * BLOCK];
+    set_wave_priority(wave_uniform(top > 0.0f ? mine / top : 0.0f));
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void plain_body(const Launch& P) {
+  const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  wave_priority_from_keys(P.key);
+  if (g >= P.n) return;
+  integrate_one<R>(P, P.order ? (long long)P.order[g] : g);
+}
+
 __global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P) { plain_body<double>(P); }
 
 // The same with single-precision stages (AI_FP32_STAGES).
 __global__ __launch_bounds__(BLOCK) void ai_plain32_kernel(Launch P) { plain_body<float>(P); }
+
+// A batch of ensembles in one index space: lane g integrates global index
+// order[g] (g without a schedule) of the ensemble that holds it, with that
+// ensemble's constants, buffers and tolerances.
+__global__ __launch_bounds__(BLOCK) void ai_plain_batch_kernel(BatchLaunch B) {
+  const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  wave_priority_from_keys(B.key);
+  if (g >= B.total) return;
+  const long long j = B.order ? (long long)B.order[g] : g;
+  const BatchEntry& E = B.entries[batch_entry(B.entries, B.count, j)];
+  integrate_one<double>(E.P, j - E.offset);
+}
 
 __global__ void ai_queue_reset_kernel(unsigned long long* queue) { *queue = 0ull; }
 
@@ -1305,6 +1370,14 @@ Launch launch_constants(const ai_params* p, int64_t n, int64_t ld, double t0, do
   return P;
 }
 
+// Secular angular frequencies of the trap, (Omega/2) sqrt(a_k + q_k^2 / 2)
+// (zero where the expression under the root is negative), for the schedule.
+void secular_omegas(const ai_params* p, double out[3]) {
+  for (int k = 0; k < 3; ++k)
+    out[k] = 0.5 * std::fabs(p->omega_rf) *
+             std::sqrt(std::fmax(p->a[k] + 0.5 * p->q[k] * p->q[k], 0.0));
+}
+
 int launch_finalize(const Launch& P, double* final_state, double* obs, hipStream_t s) {
   const long long blocks = (P.n + 255) / 256;
   hipLaunchKernelGGL(ai_finalize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, P, final_state,
@@ -1382,11 +1455,8 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
   float* key = nullptr;
   void* order_ws = nullptr;
   if ((kernel & AI_SCHEDULE_LONGEST_FIRST) && n <= 0xffffffffLL) {
-    // secular frequencies of the trap, (Omega/2) sqrt(a_k + q_k^2 / 2)
     double secular[3];
-    for (int k = 0; k < 3; ++k)
-      secular[k] = 0.5 * std::fabs(p->omega_rf) *
-                   std::sqrt(std::fmax(p->a[k] + 0.5 * p->q[k] * p->q[k], 0.0));
+    secular_omegas(p, secular);
     e = ai_longest_first_order(y0, n, ld, tmax - t0, p->r_exit, secular, &order, &key,
                                &order_ws, s);
     if (e != hipSuccess) {
@@ -1466,6 +1536,127 @@ int ai_integrate(const ai_params* p, const double* y0, int64_t n, int64_t ld, do
                  int32_t kernel) {
   int rc = ai_integrate_async(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs, kernel,
                               nullptr);
+  if (rc < 0) return rc;
+  hipError_t e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return rc;
+}
+
+int ai_integrate_batch_async(const ai_batch_item* items, int32_t count, int32_t kernel,
+                             void* stream) {
+  g_error.clear();
+  if (count < 0) return fail(AI_EINVAL, "count = %d < 0", count);
+  if (count > 0 && !items) return fail(AI_EINVAL, "items is NULL");
+  if ((kernel & ~AI_SCHEDULE_LONGEST_FIRST) != AI_KERNEL_PLAIN)
+    return fail(AI_EUNSUPPORTED, "a batch runs the plain double kernel (kernel 0x%x)",
+                (unsigned)kernel);
+  int warn = AI_OK;
+  std::vector<BatchEntry> entries;
+  std::vector<ai_order_item> keys;
+  long long total = 0;
+  for (int32_t b = 0; b < count; ++b) {
+    const ai_batch_item& it = items[b];
+    int rc = validate(&it.params, it.y0, it.n, it.ld, it.t0, it.tmax, it.rtol, it.atol,
+                      it.final_state, it.obs, AI_KERNEL_PLAIN);
+    if (rc != AI_OK) {
+      const std::string why = g_error;
+      return fail(rc, "item %d: %s", b, why.c_str());
+    }
+    if (it.n == 0) continue;
+    double rtol = it.rtol;
+    if (rtol < 100.0 * 2.220446049250313e-16) {
+      rtol = 100.0 * 2.220446049250313e-16;
+      warn = AI_WRTOL;
+    }
+    BatchEntry E;
+    E.P = launch_constants(&it.params, it.n, it.ld, it.t0, it.tmax, rtol, it.atol);
+    E.P.y0 = it.y0;
+    E.P.yf = it.final_state;
+    E.P.obs = it.obs;
+    E.offset = total;
+    entries.push_back(E);
+    ai_order_item K;
+    K.y0 = it.y0;
+    K.ld = it.ld;
+    K.offset = total;
+    K.n = it.n;
+    K.horizon = it.tmax - it.t0;
+    K.r_exit = it.params.r_exit;
+    secular_omegas(&it.params, K.secular_omega);
+    keys.push_back(K);
+    total += it.n;
+  }
+  if (total == 0) return warn;
+  if ((total + BLOCK - 1) / BLOCK > 0x7fffffffLL)
+    return fail(AI_EINVAL, "%lld trajectories are too many for one launch", total);
+
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  // the launch table: entries, then the schedule's items, in one allocation;
+  // the copy from pageable host memory is staged before hipMemcpyAsync returns
+  const int E = (int)entries.size();
+  const size_t ebytes = (sizeof(BatchEntry) * E + 255) & ~size_t(255);
+  const size_t kbytes = sizeof(ai_order_item) * E;
+  std::vector<char> host(ebytes + kbytes);
+  std::memcpy(host.data(), entries.data(), sizeof(BatchEntry) * E);
+  std::memcpy(host.data() + ebytes, keys.data(), kbytes);
+  char* table = nullptr;
+  if ((e = hipMallocAsync((void**)&table, host.size(), s)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(AI_ENOMEM, "hipMallocAsync(batch table): %s", hipGetErrorString(e));
+  }
+  if ((e = hipMemcpyAsync(table, host.data(), host.size(), hipMemcpyHostToDevice, s)) !=
+      hipSuccess) {
+    (void)hipFreeAsync(table, s);
+    return hip_fail(e, "hipMemcpyAsync(batch table)");
+  }
+  BatchLaunch B;
+  B.entries = (const BatchEntry*)table;
+  B.count = E;
+  B.total = total;
+  B.order = nullptr;
+  B.key = nullptr;
+  void* order_ws = nullptr;
+  auto release = [&]() -> int {
+    hipError_t fe = hipFreeAsync(table, s);
+    if (order_ws && fe == hipSuccess) fe = hipFreeAsync(order_ws, s);
+    return fe == hipSuccess ? AI_OK : hip_fail(fe, "hipFreeAsync(batch)");
+  };
+  if ((kernel & AI_SCHEDULE_LONGEST_FIRST) && total <= 0xffffffffLL) {
+    unsigned* order = nullptr;
+    float* key = nullptr;
+    e = ai_longest_first_order_batch((const ai_order_item*)(table + ebytes), E, total, &order,
+                                     &key, &order_ws, s);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      release();
+      return e == hipErrorOutOfMemory ? fail(AI_ENOMEM, "schedule workspace: %s",
+                                             hipGetErrorString(e))
+                                      : hip_fail(e, "schedule(batch)");
+    }
+    B.order = order;
+    B.key = key;
+  }
+  hipLaunchKernelGGL(ai_plain_batch_kernel, dim3((unsigned)((total + BLOCK - 1) / BLOCK)),
+                     dim3(BLOCK), 0, s, B);
+  if ((e = hipGetLastError()) != hipSuccess) {
+    release();
+    return hip_fail(e, "launch(batch)");
+  }
+  hipLaunchKernelGGL(ai_finalize_batch_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
+                     0, s, B);
+  if ((e = hipGetLastError()) != hipSuccess) {
+    release();
+    return hip_fail(e, "launch(finalize batch)");
+  }
+  const int rc = release();
+  return rc != AI_OK ? rc : warn;
+}
+
+int ai_integrate_batch(const ai_batch_item* items, int32_t count, int32_t kernel) {
+  int rc = ai_integrate_batch_async(items, count, kernel, nullptr);
   if (rc < 0) return rc;
   hipError_t e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");

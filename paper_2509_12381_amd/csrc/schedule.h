@@ -20,3 +20,20 @@ hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld, doubl
                                   double r_exit, const double secular_omega[3],
                                   unsigned** order, float** key,
                                   void** workspace, hipStream_t stream);
+
+// One ensemble of a batched ordering: its initial states and what the
+// prediction needs; its trajectories hold the global indices
+// offset .. offset + n - 1 (offsets increasing with the item).
+struct ai_order_item {
+  const double* y0;
+  long long ld, offset, n;
+  double horizon, r_exit;
+  double secular_omega[3];
+};
+
+// As ai_longest_first_order over the concatenation of `count` ensembles
+// (items: device memory, read by the enqueued work; total = sum of n); the
+// permutation lists global indices.
+hipError_t ai_longest_first_order_batch(const ai_order_item* items, int count, int64_t total,
+                                        unsigned** order, float** key, void** workspace,
+                                        hipStream_t stream);

@@ -32,11 +32,9 @@ __device__ __forceinline__ void ion_secular(const SecularTrap& T, const double* 
   }
 }
 
-__global__ void ai_cost_key_kernel(const double* __restrict__ y0, long long n, long long ld,
-                                   float horizon, double r_exit, SecularTrap trap,
-                                   float* __restrict__ key, unsigned* __restrict__ idx) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Predicted duration of trajectory i of an ensemble (see schedule.h).
+__device__ float predicted_duration(const double* __restrict__ y0, long long ld, long long i,
+                                    float horizon, double r_exit, const SecularTrap& trap) {
   float d = horizon;
   if (r_exit > 0.0) {
     double xi[3], vi[3], xa[3], va[3];
@@ -86,18 +84,51 @@ __global__ void ai_cost_key_kernel(const double* __restrict__ y0, long long n, l
     const float tf = (float)t;  // inf for an atom at rest; NaN sorts anywhere
     d = tf < horizon ? (tf > 0.0f ? tf : 0.0f) : horizon;
   }
-  key[i] = d;
+  return d;
+}
+
+__global__ void ai_cost_key_kernel(const double* __restrict__ y0, long long n, long long ld,
+                                   float horizon, double r_exit, SecularTrap trap,
+                                   float* __restrict__ key, unsigned* __restrict__ idx) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = predicted_duration(y0, ld, i, horizon, r_exit, trap);
   idx[i] = (unsigned)i;
+}
+
+// Global index j of a batch: its item by binary search over the items'
+// offsets (increasing), then the item's prediction.
+__global__ void ai_cost_key_batch_kernel(const ai_order_item* __restrict__ items, int count,
+                                         long long total, float* __restrict__ key,
+                                         unsigned* __restrict__ idx) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= total) return;
+  int lo = 0, hi = count - 1;  // last item with offset <= j
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (items[mid].offset <= j)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const ai_order_item& it = items[lo];
+  SecularTrap trap;
+  for (int k = 0; k < 3; ++k) trap.w[k] = it.secular_omega[k];
+  key[j] = predicted_duration(it.y0, it.ld, j - it.offset, (float)it.horizon, it.r_exit, trap);
+  idx[j] = (unsigned)j;
 }
 
 constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
 
-hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld, double horizon,
-                                  double r_exit, const double secular_omega[3],
-                                  unsigned** order, float** key,
-                                  void** workspace, hipStream_t stream) {
+namespace {
+
+// Workspace for n keys: the cost kernel's output, the sorted copy, and the
+// radix sort's scratch; `launch` enqueues the cost kernel into key_in/idx_in.
+template <class Launch>
+hipError_t sort_by_key(int64_t n, unsigned** order, float** key, void** workspace,
+                       hipStream_t stream, Launch launch) {
   *order = nullptr;
   *key = nullptr;
   *workspace = nullptr;
@@ -118,12 +149,7 @@ hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld, doubl
   unsigned* idx_in = (unsigned*)(base + 2 * fbytes);
   unsigned* idx_out = (unsigned*)(base + 2 * fbytes + ubytes);
   void* temp = base + 2 * fbytes + 2 * ubytes;
-  const unsigned threads = 256;
-  const unsigned blocks = (unsigned)((n + threads - 1) / threads);
-  SecularTrap trap;
-  for (int k = 0; k < 3; ++k) trap.w[k] = secular_omega[k];
-  hipLaunchKernelGGL(ai_cost_key_kernel, dim3(blocks), dim3(threads), 0, stream, y0,
-                     (long long)n, (long long)ld, (float)horizon, r_exit, trap, key_in, idx_in);
+  launch(key_in, idx_in);
   if ((e = hipGetLastError()) == hipSuccess)
     e = rocprim::radix_sort_pairs_desc(temp, temp_bytes, key_in, key_out, idx_in, idx_out, size,
                                        0, 32, stream);
@@ -135,4 +161,33 @@ hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld, doubl
   *key = key_out;
   *workspace = base;
   return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld, double horizon,
+                                  double r_exit, const double secular_omega[3],
+                                  unsigned** order, float** key,
+                                  void** workspace, hipStream_t stream) {
+  SecularTrap trap;
+  for (int k = 0; k < 3; ++k) trap.w[k] = secular_omega[k];
+  const unsigned threads = 256;
+  const unsigned blocks = (unsigned)((n + threads - 1) / threads);
+  return sort_by_key(n, order, key, workspace, stream, [&](float* key_in, unsigned* idx_in) {
+    hipLaunchKernelGGL(ai_cost_key_kernel, dim3(blocks), dim3(threads), 0, stream, y0,
+                       (long long)n, (long long)ld, (float)horizon, r_exit, trap, key_in,
+                       idx_in);
+  });
+}
+
+hipError_t ai_longest_first_order_batch(const ai_order_item* items, int count, int64_t total,
+                                        unsigned** order, float** key, void** workspace,
+                                        hipStream_t stream) {
+  if (count <= 0) return hipErrorInvalidValue;
+  const unsigned threads = 256;
+  const unsigned blocks = (unsigned)((total + threads - 1) / threads);
+  return sort_by_key(total, order, key, workspace, stream, [&](float* key_in, unsigned* idx_in) {
+    hipLaunchKernelGGL(ai_cost_key_batch_kernel, dim3(blocks), dim3(threads), 0, stream, items,
+                       count, (long long)total, key_in, idx_in);
+  });
 }

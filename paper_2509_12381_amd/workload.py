@@ -161,6 +161,34 @@ def full_ensemble() -> Workload:
     return thermal_workload(1 << 20, 0, name="liyb-thermal-1M")
 
 
+# The batched grid: collision (atom) temperatures log-spaced over 10 uK .. 10 mK
+# and Paul-trap q values (a = 0); ensemble sizes log-uniform in [1024, 262144].
+BATCH_T_ATOM = tuple(float(t) for t in np.logspace(-5.0, -2.0, 8))
+BATCH_Q = (0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7)
+BATCH_SIZE_SEED = 1
+BATCH_IC_SEED0 = 100
+
+
+def batch_grid(scale: float = 1.0) -> list[Workload]:
+    """The 64 ensembles of the batched configuration, T_atom-major (ensemble
+    k = 8 iT + iq).  Size of ensemble k: floor(1024 * 256**U_k) with U_k the
+    k-th uniform of a PCG64 stream of seed 1 (``scale`` shrinks every size, at
+    least 1, for tests); initial states of ensemble k come from seed 100 + k.
+    Everything else is the 1,024-trajectory configuration's: masses,
+    potential, 0.5 mK ion, R0, b_max, 200 RF periods, RelTol 1e-8, AbsTol 1e-10.
+    For q >= 0.5 the ion's z motion is Mathieu-unstable (|tr M_z| > 2)."""
+    u = np.random.Generator(np.random.PCG64(BATCH_SIZE_SEED)).random(len(BATCH_T_ATOM) * len(BATCH_Q))
+    out = []
+    for it, T in enumerate(BATCH_T_ATOM):
+        for iq, q in enumerate(BATCH_Q):
+            k = it * len(BATCH_Q) + iq
+            n = int(math.floor(1024.0 * 256.0 ** u[k]))
+            n = max(1, int(n * scale))
+            out.append(thermal_workload(n, BATCH_IC_SEED0 + k, T_atom=T, q=q,
+                                        name=f"batch-T{T:.2e}-q{q:g}"))
+    return out
+
+
 def _uniform_rows(n: int, seed: int, ncols: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.random((n, ncols))

@@ -26,7 +26,8 @@ def lib():
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    assert names == sorted(["ai_integrate", "ai_integrate_async", "ai_get_kernel_info",
+    assert names == sorted(["ai_integrate", "ai_integrate_async", "ai_integrate_batch",
+                            "ai_integrate_batch_async", "ai_get_kernel_info",
                             "ai_last_error", "ai_nobs", "ai_version"])
 
 
@@ -48,6 +49,8 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(binding.AiParams) == 8 * 2 + 4 * 2 + 8 * 2 + 8 * 6 + 8 * 3 + 8 + 8
     assert binding.AiParams.max_steps.offset == 8 * 2 + 4 * 2 + 8 * 2 + 8 * 6 + 8 * 3
     assert ctypes.sizeof(binding.AiKernelInfo) == 6 * 4 + 8
+    # ai_batch_item: ai_params, pointer, 2 int64, 4 doubles, 2 pointers
+    assert ctypes.sizeof(binding.AiBatchItem) == ctypes.sizeof(binding.AiParams) + 8 * 9
 
 
 def test_constants_without_gpu(lib):
@@ -70,3 +73,16 @@ def test_invalid_arguments_are_refused_before_any_device_call(lib):
     assert rc == binding.EINVAL
     rc = b.ai_integrate(ctypes.byref(p), None, 0, 0, 0.0, 1.0, 1e-8, 1e-10, None, None, 7)
     assert rc == binding.EINVAL
+    # batches: a negative count, a NULL item array, an unsupported kernel, and an
+    # invalid item (named in the message) are refused before any device call
+    assert b.ai_integrate_batch(None, -1, 0) == binding.EINVAL
+    assert b.ai_integrate_batch(None, 2, 0) == binding.EINVAL
+    items = (binding.AiBatchItem * 2)()
+    assert b.ai_integrate_batch(items, 2, 1) == binding.EUNSUPPORTED
+    for it in items:
+        it.params = p
+        it.n, it.ld, it.t0, it.tmax, it.rtol, it.atol = 0, 0, 0.0, 1.0, 1e-8, 1e-10
+    items[1].tmax = -1.0
+    assert b.ai_integrate_batch(items, 2, 0) == binding.EINVAL
+    assert binding.ai_last_error().startswith("item 1:")
+    assert b.ai_integrate_batch_async(items, 0, 0, None) == binding.OK  # nothing enqueued

@@ -502,3 +502,96 @@ def test_fp32_stages_deterministic_and_plain_only(ai, torch):
         run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "persistent",
                 precision="fp32-stages")
     assert e.value.rc == -4
+
+
+# Batched uneven ensembles (ai_integrate_batch): one launch over several
+# ensembles of different systems, sizes, spans and tolerances.
+def _batch_case():
+    grid = W.batch_grid(scale=1.0 / 64)          # 64 ensembles, 16 .. 3,700 trajectories
+    pick = [0, 7, 12, 21, 30, 45, 54, 63]         # T from 10 uK to 10 mK, q from 0.05 to 0.7
+    items = []
+    for k in pick:
+        wl = grid[k]
+        items.append(dict(wl=wl, y0=wl.initial_states(), t0=wl.t0, tmax=wl.tmax,
+                          rtol=wl.rtol, atol=wl.atol, ld=wl.n + 3))
+    # other spans and tolerances, and an empty item
+    items[2].update(rtol=1e-10, atol=1e-12)
+    items[3].update(t0=0.25 * items[3]["wl"].tmax)
+    items[4].update(tmax=0.3 * items[4]["wl"].tmax)
+    items.append(dict(wl=grid[5], y0=grid[5].initial_states(1)[:, :0], t0=0.0,
+                      tmax=grid[5].tmax, rtol=1e-8, atol=1e-10, ld=4))
+    return items
+
+
+def _device_item(torch, it):
+    n = it["y0"].shape[1]
+    y0p = np.zeros((12, it["ld"]))
+    y0p[:, :n] = it["y0"]
+    d = torch.from_numpy(y0p).cuda()
+    fin = torch.full((12, it["ld"]), -7.0, dtype=torch.float64, device="cuda")
+    obs = torch.full((13, it["ld"]), -7.0, dtype=torch.float64, device="cuda")
+    return d, fin, obs, n
+
+
+@pytest.mark.parametrize("schedule", [None, "longest-first"])
+def test_batch_matches_single_calls(ai, torch, schedule):
+    items = _batch_case()
+    dev = [_device_item(torch, it) for it in items]
+    rc = ai.ai_integrate_batch([(it["wl"].system, d, fin, obs, it["t0"], it["tmax"], it["rtol"],
+                                 it["atol"], n) for it, (d, fin, obs, n) in zip(items, dev)],
+                               schedule=schedule)
+    assert rc == 0
+    for it, (d, fin, obs, n) in zip(items, dev):
+        ref = run_gpu(ai, torch, it["wl"].system, it["y0"], it["t0"], it["tmax"], it["rtol"],
+                      it["atol"], "plain", ld=it["ld"], n=n)
+        np.testing.assert_array_equal(fin.cpu().numpy(), ref[0])
+        np.testing.assert_array_equal(obs.cpu().numpy(), ref[1])
+        assert np.all(obs.cpu().numpy()[:, n:] == -7.0)
+
+
+def test_batch_oracle_parity(ai, torch, aio):
+    """Samples of three contrasting ensembles of the batched grid (10 uK at
+    q = 0.05, 0.5 mK at q = 0.4, 10 mK at the Mathieu-unstable q = 0.7) through
+    one batched launch, against the oracle."""
+    grid = W.batch_grid()
+    items = []
+    for k in (0, 36, 63):
+        wl = grid[k]
+        items.append((wl, wl.initial_states(96)))
+    dev = [(torch.from_numpy(np.ascontiguousarray(y)).cuda(),) for _, y in items]
+    outs = [(torch.empty((12, 96), dtype=torch.float64, device="cuda"),
+             torch.empty((13, 96), dtype=torch.float64, device="cuda")) for _ in items]
+    ai.ai_integrate_batch([(wl.system, d[0], f, o, wl.t0, wl.tmax, wl.rtol, wl.atol)
+                           for (wl, _), d, (f, o) in zip(items, dev, outs)],
+                          schedule="longest-first")
+    for (wl, y0), (f, o) in zip(items, outs):
+        gfin, gob = f.cpu().numpy(), o.cpu().numpy()
+        ofin, oob, _ = run_oracle(aio, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
+        np.testing.assert_array_equal(gob[O["status"]], oob[O["status"]])
+        calm, _ = non_chaotic(aio, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, ofin, oob)
+        al = aligned_oracle_state(aio, wl.system, ofin, oob, gob)
+        rel = S.block_relative_difference(gfin[:, calm], al[:, calm])
+        same = float((gob[O["nsteps"]][calm] == oob[O["nsteps"]][calm]).mean())
+        print(f"[batch {wl.name}] calm {int(calm.sum())}/96, max rel {rel.max():.2e}, "
+              f"identical steps {same:.3f}", flush=True)
+        assert rel.max() <= 1e-6 and same >= 0.99
+
+
+def test_batch_full_grid_runs(ai, torch):
+    """All 64 ensembles of the batched configuration (3.2 M trajectories) in
+    one launch: every trajectory ends with a status, and the Mathieu-unstable
+    ensembles (q >= 0.5) end by escape."""
+    grid = W.batch_grid()
+    dev = []
+    for wl in grid:
+        d = torch.from_numpy(wl.initial_states()).cuda()
+        dev.append((wl, d, torch.empty_like(d),
+                    torch.empty((13, wl.n), dtype=torch.float64, device="cuda")))
+    rc = ai.ai_integrate_batch([(wl.system, d, f, o, wl.t0, wl.tmax, wl.rtol, wl.atol)
+                                for wl, d, f, o in dev], schedule="longest-first")
+    assert rc == 0
+    for k, (wl, _, _, o) in enumerate(dev):
+        st = o[O["status"]].cpu().numpy()
+        assert np.all((st >= 1) & (st <= 5)), wl.name
+        if W.BATCH_Q[k % len(W.BATCH_Q)] >= 0.5:
+            assert np.mean(st == W.ST_ESCAPED) > 0.99, wl.name
