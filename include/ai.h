@@ -82,10 +82,10 @@ enum ai_kernel {
   /* flag, OR-ed into either kernel: hand out trajectories by decreasing
    * predicted duration (the time at which the atom, on a straight line, is
    * r_exit away from the ion on its secular trap motion; capped at
-   * tmax - t0; uniform when r_exit = 0), computed and sorted on the device.  Changes only which
-   * lane integrates which trajectory, never a result.  Takes 16 n bytes plus
-   * sort scratch from the stream-ordered allocator for the call; ignored for
-   * n >= 2^32. */
+   * tmax - t0; uniform when r_exit = 0), computed and sorted on the device.
+   * Changes only which lane integrates which trajectory, never a result.
+   * Takes 16 n bytes plus sort scratch from the stream-ordered allocator for
+   * the call; ignored for n >= 2^32. */
   AI_SCHEDULE_LONGEST_FIRST = 16,
   /* flag, plain kernel only (AI_EUNSUPPORTED with the persistent kernel): the
    * precision variant.  Stage increments, forces and the error estimate's
@@ -158,7 +158,9 @@ typedef struct ai_batch_item {
 /* Integrate `count` ensembles of possibly different systems, sizes, spans and
  * tolerances in one launch of the plain kernel: the trajectories of all items
  * form one index space (and, with AI_SCHEDULE_LONGEST_FIRST, are handed out by
- * decreasing predicted duration across items).  This is the batched form of
+ * decreasing predicted cost across items: the exit rule evaluated on samples
+ * of the trap's exact linear motion with the atom in straight flight, times an
+ * attempt rate for the item's trap frequency, q and rtol).  This is the batched form of
  * the paper's ode45gpu call (Sec. 3.3) for uneven ensembles (Sec. 4.2 sweeps
  * collision energy and trap parameters).
  *

@@ -99,7 +99,7 @@ struct Launch {
   double* yf;                // n x 12 final states (may alias y0)
   double* obs;               // n x AI_NOBS observables
   const unsigned* order;     // schedule: trajectory at each position (null: identity)
-  const float* key;          // schedule: predicted duration at each position (null: none)
+  const unsigned* key;       // schedule: predicted cost code at each position (null: none)
   unsigned long long* queue; // persistent kernel: dynamic positions handed out so far
 };
 
@@ -899,7 +899,7 @@ struct BatchLaunch {
   int count;
   long long total;
   const unsigned* order;
-  const float* key;
+  const unsigned* key;
 };
 
 // The ensemble holding global index j: the last entry with offset <= j.
@@ -983,9 +983,9 @@ __device__ __forceinline__ void integrate_one(const Launch& P, long long idx) {
 
 // With the schedule's keys a wave takes the priority of its first (longest)
 // trajectory.
-__device__ __forceinline__ void wave_priority_from_keys(const float* key) {
+__device__ __forceinline__ void wave_priority_from_keys(const unsigned* key) {
   if (key) {
-    const float top = key[0], mine = key[(long long)blockIdx.x * BLOCK];
+    const float top = (float)key[0], mine = (float)key[(long long)blockIdx.x * BLOCK];
     set_wave_priority(wave_uniform(top > 0.0f ? mine / top : 0.0f));
   }
 }
@@ -1055,7 +1055,7 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
     lds_S = start_const(P);
   }
   __syncthreads();
-  const float top = P.key ? P.key[0] : 0.0f;
+  const float top = P.key ? (float)P.key[0] : 0.0f;
   const int refill_min = in_vgpr(P.refill_min);
   const Ctl K = lane_ctl(P);
   const Force Fc = lane_force(P);
@@ -1154,12 +1154,12 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
         if (lane < cnt) {
           const long long pos = first + lane;
           const unsigned* order = Q->order;
-          const float* key = Q->key;
+          const unsigned* key = Q->key;
           const double* y0 = Q->y0;
           const long long ld = Q->ld;
           const long long t = order ? (long long)order[pos] : pos;
           stage_idx[lane] = t;
-          stage_key[lane] = key ? key[pos] : 0.0f;
+          stage_key[lane] = key ? (float)key[pos] : 0.0f;
 #pragma unroll
           for (int c = 0; c < 12; ++c) stage_y[c][lane] = y0[c * ld + t];
         }
@@ -1370,12 +1370,8 @@ Launch launch_constants(const ai_params* p, int64_t n, int64_t ld, double t0, do
   return P;
 }
 
-// Secular angular frequencies of the trap, (Omega/2) sqrt(a_k + q_k^2 / 2)
-// (zero where the expression under the root is negative), for the schedule.
-void secular_omegas(const ai_params* p, double out[3]) {
-  for (int k = 0; k < 3; ++k)
-    out[k] = 0.5 * std::fabs(p->omega_rf) *
-             std::sqrt(std::fmax(p->a[k] + 0.5 * p->q[k] * p->q[k], 0.0));
+ai_order_model order_model(const ai_params* p, double t0, double tmax, double rtol, bool sampled) {
+  return ai_make_order_model(p->a, p->q, p->omega_rf, p->r_exit, t0, tmax, rtol, sampled);
 }
 
 int launch_finalize(const Launch& P, double* final_state, double* obs, hipStream_t s) {
@@ -1452,12 +1448,10 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
 
   // optional schedule: longest predicted trajectories first
   unsigned* order = nullptr;
-  float* key = nullptr;
+  unsigned* key = nullptr;
   void* order_ws = nullptr;
   if ((kernel & AI_SCHEDULE_LONGEST_FIRST) && n <= 0xffffffffLL) {
-    double secular[3];
-    secular_omegas(p, secular);
-    e = ai_longest_first_order(y0, n, ld, tmax - t0, p->r_exit, secular, &order, &key,
+    e = ai_longest_first_order(y0, n, ld, order_model(p, t0, tmax, rtol, false), &order, &key,
                                &order_ws, s);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -1475,6 +1469,12 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
     }
     return AI_OK;
   };
+  auto conclude = [&]() -> int {
+    const int frc = launch_finalize(P, final_state, obs, s);
+    const int rrc = release();
+    if (frc != AI_OK) return frc;
+    return rrc != AI_OK ? rrc : warn;
+  };
 
   if ((kernel & 0xf) == AI_KERNEL_PLAIN) {
     const long long blocks = (n + BLOCK - 1) / BLOCK;
@@ -1490,10 +1490,7 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
       release();
       return hip_fail(e, "launch(plain)");
     }
-    rc = release();
-    if (rc != AI_OK) return rc;
-    rc = launch_finalize(P, final_state, obs, s);
-    return rc != AI_OK ? rc : warn;
+    return conclude();
   }
 
   const int refill_min = (kernel >> 8) & 0x7f;
@@ -1525,10 +1522,7 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
     release();
     return hip_fail(e, "hipFreeAsync(queue)");
   }
-  rc = release();
-  if (rc != AI_OK) return rc;
-  rc = launch_finalize(P, final_state, obs, s);
-  return rc != AI_OK ? rc : warn;
+  return conclude();
 }
 
 int ai_integrate(const ai_params* p, const double* y0, int64_t n, int64_t ld, double t0,
@@ -1554,6 +1548,7 @@ int ai_integrate_batch_async(const ai_batch_item* items, int32_t count, int32_t 
   std::vector<BatchEntry> entries;
   std::vector<ai_order_item> keys;
   long long total = 0;
+  double cost_max = 0.0;
   for (int32_t b = 0; b < count; ++b) {
     const ai_batch_item& it = items[b];
     int rc = validate(&it.params, it.y0, it.n, it.ld, it.t0, it.tmax, it.rtol, it.atol,
@@ -1580,9 +1575,8 @@ int ai_integrate_batch_async(const ai_batch_item* items, int32_t count, int32_t 
     K.ld = it.ld;
     K.offset = total;
     K.n = it.n;
-    K.horizon = it.tmax - it.t0;
-    K.r_exit = it.params.r_exit;
-    secular_omegas(&it.params, K.secular_omega);
+    K.model = order_model(&it.params, it.t0, it.tmax, rtol, true);
+    cost_max = std::fmax(cost_max, (double)K.model.horizon * K.model.rate);
     keys.push_back(K);
     total += it.n;
   }
@@ -1626,9 +1620,9 @@ int ai_integrate_batch_async(const ai_batch_item* items, int32_t count, int32_t 
   };
   if ((kernel & AI_SCHEDULE_LONGEST_FIRST) && total <= 0xffffffffLL) {
     unsigned* order = nullptr;
-    float* key = nullptr;
-    e = ai_longest_first_order_batch((const ai_order_item*)(table + ebytes), E, total, &order,
-                                     &key, &order_ws, s);
+    unsigned* key = nullptr;
+    e = ai_longest_first_order_batch((const ai_order_item*)(table + ebytes), E, total, cost_max,
+                                     &order, &key, &order_ws, s);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       release();

@@ -9,17 +9,19 @@
 
 #include <rocprim/device/device_radix_sort.hpp>
 
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
 namespace {
 
-struct SecularTrap {
-  double w[3];  // secular angular frequency per axis, (Omega/2) sqrt(a_k + q_k^2/2)
-};
-
-__device__ __forceinline__ void ion_secular(const SecularTrap& T, const double* x0,
+// The ion on its secular orbit: per axis a harmonic oscillation at the
+// secular frequency w (free flight where w = 0) from (x0, v0) at t0.
+__device__ __forceinline__ void ion_secular(const ai_order_model& M, const double* x0,
                                             const double* v0, double t, double* x, double* v) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const double w = T.w[k];
+    const double w = M.secular_omega[k];
     if (w > 0.0) {
       double s, c;
       sincos(w * t, &s, &c);
@@ -32,75 +34,169 @@ __device__ __forceinline__ void ion_secular(const SecularTrap& T, const double* 
   }
 }
 
-// Predicted duration of trajectory i of an ensemble (see schedule.h).
-__device__ float predicted_duration(const double* __restrict__ y0, long long ld, long long i,
-                                    float horizon, double r_exit, const SecularTrap& trap) {
-  float d = horizon;
-  if (r_exit > 0.0) {
-    double xi[3], vi[3], xa[3], va[3];
+// Analytic duration (see schedule.h): the straight-line exit of the atom from
+// the sphere of radius r_exit about the trap centre, refined by Newton steps
+// against the ion's secular orbit.
+__device__ float analytic_duration(const double* __restrict__ y0, long long ld, long long i,
+                                   const ai_order_model& M) {
+  const float horizon = M.horizon;
+  double xi[3], vi[3], xa[3], va[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    xi[k] = y0[k * ld + i];
+    vi[k] = y0[(3 + k) * ld + i];
+    xa[k] = y0[(6 + k) * ld + i];
+    va[k] = y0[(9 + k) * ld + i];
+  }
+  const double R2 = M.r_exit * M.r_exit;
+  // start: the larger root of |x_a + v_a t| = r_exit, or 2 r / |v_a|
+  const double vv = va[0] * va[0] + va[1] * va[1] + va[2] * va[2];
+  const double xv = xa[0] * va[0] + xa[1] * va[1] + xa[2] * va[2];
+  const double disc = xv * xv - vv * (xa[0] * xa[0] + xa[1] * xa[1] + xa[2] * xa[2] - R2);
+  double t;
+  if (disc > 0.0) {
+    t = (sqrt(disc) - xv) / vv;
+  } else {
+    const double dx = xa[0] - xi[0], dy = xa[1] - xi[1], dz = xa[2] - xi[2];
+    t = 2.0 * sqrt((dx * dx + dy * dy + dz * dz) / vv);
+  }
+  // refine on g(t) = |x_a + v_a t - x_ion(t)|^2 - r_exit^2, keeping a step
+  // only within a factor 2 of the straight-line value: an underestimated
+  // trajectory starts late and can end after everything else, so a step that
+  // leaves that range (an overshoot, or a root on the wrong side) is dropped
+  const double ts = t;
+  for (int it = 0; it < 3; ++it) {
+    if (!(t > 0.0) || !(t < (double)horizon)) break;
+    double x[3], v[3];
+    ion_secular(M, xi, vi, t, x, v);
+    double g = -R2, gp = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      xi[k] = y0[k * ld + i];
-      vi[k] = y0[(3 + k) * ld + i];
-      xa[k] = y0[(6 + k) * ld + i];
-      va[k] = y0[(9 + k) * ld + i];
+      const double dk = xa[k] + va[k] * t - x[k];
+      g += dk * dk;
+      gp += 2.0 * dk * (va[k] - v[k]);
     }
-    const double R2 = r_exit * r_exit;
-    // start: straight-line exit from the sphere of radius r_exit about the
-    // trap centre (larger root of |x_a + v_a t| = r_exit), or 2 r / |v_a|
-    const double vv = va[0] * va[0] + va[1] * va[1] + va[2] * va[2];
-    const double xv = xa[0] * va[0] + xa[1] * va[1] + xa[2] * va[2];
-    const double disc = xv * xv - vv * (xa[0] * xa[0] + xa[1] * xa[1] + xa[2] * xa[2] - R2);
-    double t;
-    if (disc > 0.0) {
-      t = (sqrt(disc) - xv) / vv;
-    } else {
-      const double dx = xa[0] - xi[0], dy = xa[1] - xi[1], dz = xa[2] - xi[2];
-      t = 2.0 * sqrt((dx * dx + dy * dy + dz * dz) / vv);
+    if (gp > 0.0) {
+      const double tn = t - g / gp;
+      if (tn > 0.5 * ts && tn < 2.0 * ts) t = tn;
     }
-    // refine: the ion follows its secular motion; Newton steps on
-    // g(t) = |x_a + v_a t - x_ion(t)|^2 - r_exit^2, each kept only if it stays
-    // within a factor 2 of the straight-line value.  A trajectory whose
-    // duration is underestimated starts late and can end after everything
-    // else, so a step that leaves that range (an overshoot, or a root on the
-    // wrong side) is discarded.
-    const double ts = t;
-    for (int it = 0; it < 3; ++it) {
-      if (!(t > 0.0) || !(t < (double)horizon)) break;
-      double x[3], v[3];
-      ion_secular(trap, xi, vi, t, x, v);
-      double g = -R2, gp = 0.0;
+  }
+  const float tf = (float)t;  // inf for an atom at rest; NaN sorts anywhere
+  return tf < horizon ? (tf > 0.0f ? tf : 0.0f) : horizon;
+}
+
+// Sampled duration (see schedule.h): the exit rule on samples of the exact
+// linear trap motion.
+__device__ float sampled_duration(const double* __restrict__ y0, long long ld, long long i,
+                                  const ai_order_model& M) {
+  const float horizon = M.horizon;
+  double xi[3], vi[3], xa[3], va[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    xi[k] = y0[k * ld + i];
+    vi[k] = y0[(3 + k) * ld + i];
+    xa[k] = y0[(6 + k) * ld + i];
+    va[k] = y0[(9 + k) * ld + i];
+  }
+  // t0: a pair that is not closing in counts as past its closest approach
+  double dot = 0.0, r2_0 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double rel = xi[k] - xa[k];
+    dot += rel * (vi[k] - va[k]);
+    r2_0 += rel * rel;
+  }
+  float s0[3], s1[3], pa[3], wa[3];  // ion (x, v) at the current period's start; atom
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    s0[k] = (float)xi[k];
+    s1[k] = (float)vi[k];
+    pa[k] = (float)xa[k];
+    wa[k] = (float)va[k];
+  }
+  bool approached = dot >= 0.0;
+  bool falling = dot < 0.0;
+  float prev = (float)r2_0;
+  const float far2 = 1e4f * M.r_exit2;  // the ion has left the trap (unstable axis)
+  float t_exit = -1.0f;
+  for (int P = 0; P < M.periods; ++P) {
+    const float base = (float)(P * AI_ORDER_SAMPLES);
+    float hit = -1.0f;
+#pragma unroll
+    for (int j = 0; j < AI_ORDER_SAMPLES; ++j) {
+      const float t = (base + (float)(j + 1)) * M.dt;
+      float r2 = 0.0f;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const double dk = xa[k] + va[k] * t - x[k];
-        g += dk * dk;
-        gp += 2.0 * dk * (va[k] - v[k]);
+        const float x = fmaf(M.phi[k][j][0], s0[k], M.phi[k][j][1] * s1[k]);
+        const float dk = x - fmaf(wa[k], t, pa[k]);
+        r2 = fmaf(dk, dk, r2);
       }
-      if (gp > 0.0) {
-        const double tn = t - g / gp;
-        if (tn > 0.5 * ts && tn < 2.0 * ts) t = tn;
-      }
+      // a local minimum of the distance between two samples is a closest approach
+      const bool rising = r2 >= prev;
+      approached = approached || (falling && rising);
+      falling = !rising;
+      prev = r2;
+      if (hit < 0.0f && ((approached && r2 > M.r_exit2) || !(r2 < far2))) hit = t;
     }
-    const float tf = (float)t;  // inf for an atom at rest; NaN sorts anywhere
-    d = tf < horizon ? (tf > 0.0f ? tf : 0.0f) : horizon;
+    if (hit >= 0.0f) {
+      t_exit = hit;
+      break;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float x = fmaf(M.mono[k][0], s0[k], M.mono[k][1] * s1[k]);
+      const float v = fmaf(M.mono[k][2], s0[k], M.mono[k][3] * s1[k]);
+      s0[k] = x;
+      s1[k] = v;
+    }
   }
-  return d;
+  if (t_exit < 0.0f) {
+    // still inside after the searched span: the straight-line exit from the
+    // sphere of radius r_exit about the ion's start, but not before the span's end
+    const float span = (float)(M.periods * AI_ORDER_SAMPLES) * M.dt;
+    double vv = 0.0, xv = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      vv += va[k] * va[k];
+      xv += (xa[k] - xi[k]) * va[k];
+    }
+    const double disc = xv * xv - vv * (r2_0 - (double)M.r_exit2);
+    const float line = disc > 0.0 && vv > 0.0 ? (float)((sqrt(disc) - xv) / vv) : horizon;
+    t_exit = fmaxf(span, line);
+  }
+  return t_exit < horizon ? t_exit : horizon;  // NaN sorts anywhere
+}
+
+// Predicted cost of trajectory i of an ensemble (see schedule.h).
+__device__ float predicted_cost(const double* __restrict__ y0, long long ld, long long i,
+                                const ai_order_model& M) {
+  if (!(M.r_exit > 0.0)) return M.horizon * M.rate;
+  return (M.sampled ? sampled_duration(y0, ld, i, M) : analytic_duration(y0, ld, i, M)) * M.rate;
+}
+
+// The sort key: the cost on AI_ORDER_CODES levels from 0 to the largest
+// possible cost (a non-finite prediction, from a non-finite initial state,
+// takes the lowest).
+__device__ __forceinline__ unsigned cost_code(float cost, float scale) {
+  const float c = cost * scale;
+  return c > 0.0f ? (unsigned)fminf(c, (float)(AI_ORDER_CODES - 1)) : 0u;
 }
 
 __global__ void ai_cost_key_kernel(const double* __restrict__ y0, long long n, long long ld,
-                                   float horizon, double r_exit, SecularTrap trap,
-                                   float* __restrict__ key, unsigned* __restrict__ idx) {
+                                   ai_order_model model, float scale,
+                                   unsigned* __restrict__ key, unsigned* __restrict__ idx) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  key[i] = predicted_duration(y0, ld, i, horizon, r_exit, trap);
+  key[i] = cost_code(predicted_cost(y0, ld, i, model), scale);
   idx[i] = (unsigned)i;
 }
 
 // Global index j of a batch: its item by binary search over the items'
 // offsets (increasing), then the item's prediction.
 __global__ void ai_cost_key_batch_kernel(const ai_order_item* __restrict__ items, int count,
-                                         long long total, float* __restrict__ key,
-                                         unsigned* __restrict__ idx) {
+                                         long long total, float scale,
+                                         unsigned* __restrict__ key, unsigned* __restrict__ idx) {
   const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= total) return;
   int lo = 0, hi = count - 1;  // last item with offset <= j
@@ -112,9 +208,7 @@ __global__ void ai_cost_key_batch_kernel(const ai_order_item* __restrict__ items
       hi = mid - 1;
   }
   const ai_order_item& it = items[lo];
-  SecularTrap trap;
-  for (int k = 0; k < 3; ++k) trap.w[k] = it.secular_omega[k];
-  key[j] = predicted_duration(it.y0, it.ld, j - it.offset, (float)it.horizon, it.r_exit, trap);
+  key[j] = cost_code(predicted_cost(it.y0, it.ld, j - it.offset, it.model), scale);
   idx[j] = (unsigned)j;
 }
 
@@ -126,8 +220,16 @@ namespace {
 
 // Workspace for n keys: the cost kernel's output, the sorted copy, and the
 // radix sort's scratch; `launch` enqueues the cost kernel into key_in/idx_in.
+// The keys have AI_ORDER_CODE_BITS significant bits, which is all the sort
+// looks at.
+// rocPRIM's radix sort with the onesweep algorithm from 4,096 items up (its
+// default sorts up to 2^20 items by merging, about twenty passes; onesweep
+// needs a histogram and one pass per 8 key bits).
+using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                              rocprim::default_config, 4096>;
+
 template <class Launch>
-hipError_t sort_by_key(int64_t n, unsigned** order, float** key, void** workspace,
+hipError_t sort_by_key(int64_t n, unsigned** order, unsigned** key, void** workspace,
                        hipStream_t stream, Launch launch) {
   *order = nullptr;
   *key = nullptr;
@@ -135,24 +237,24 @@ hipError_t sort_by_key(int64_t n, unsigned** order, float** key, void** workspac
   if (n <= 0 || n > 0xffffffffLL) return hipErrorInvalidValue;
   const unsigned size = (unsigned)n;
   size_t temp_bytes = 0;
-  hipError_t e = rocprim::radix_sort_pairs_desc(nullptr, temp_bytes, (float*)nullptr,
-                                                (float*)nullptr, (unsigned*)nullptr,
-                                                (unsigned*)nullptr, size, 0, 32, stream);
+  hipError_t e = rocprim::radix_sort_pairs_desc<SortConfig>(nullptr, temp_bytes, (unsigned*)nullptr,
+                                                (unsigned*)nullptr, (unsigned*)nullptr,
+                                                (unsigned*)nullptr, size, 0, AI_ORDER_CODE_BITS,
+                                                stream);
   if (e != hipSuccess) return e;
-  const size_t fbytes = align256(sizeof(float) * (size_t)n);
   const size_t ubytes = align256(sizeof(unsigned) * (size_t)n);
-  const size_t total = 2 * fbytes + 2 * ubytes + align256(temp_bytes);
+  const size_t total = 4 * ubytes + align256(temp_bytes);
   char* base = nullptr;
   if ((e = hipMallocAsync((void**)&base, total, stream)) != hipSuccess) return e;
-  float* key_in = (float*)base;
-  float* key_out = (float*)(base + fbytes);
-  unsigned* idx_in = (unsigned*)(base + 2 * fbytes);
-  unsigned* idx_out = (unsigned*)(base + 2 * fbytes + ubytes);
-  void* temp = base + 2 * fbytes + 2 * ubytes;
+  unsigned* key_in = (unsigned*)base;
+  unsigned* key_out = (unsigned*)(base + ubytes);
+  unsigned* idx_in = (unsigned*)(base + 2 * ubytes);
+  unsigned* idx_out = (unsigned*)(base + 3 * ubytes);
+  void* temp = base + 4 * ubytes;
   launch(key_in, idx_in);
   if ((e = hipGetLastError()) == hipSuccess)
-    e = rocprim::radix_sort_pairs_desc(temp, temp_bytes, key_in, key_out, idx_in, idx_out, size,
-                                       0, 32, stream);
+    e = rocprim::radix_sort_pairs_desc<SortConfig>(temp, temp_bytes, key_in, key_out, idx_in,
+                                                   idx_out, size, 0, AI_ORDER_CODE_BITS, stream);
   if (e != hipSuccess) {
     (void)hipFreeAsync(base, stream);
     return e;
@@ -163,31 +265,150 @@ hipError_t sort_by_key(int64_t n, unsigned** order, float** key, void** workspac
   return hipSuccess;
 }
 
+// Scale from costs to codes for costs up to cost_max.
+float code_scale(double cost_max) {
+  return cost_max > 0.0 && std::isfinite(cost_max) ? (float)(AI_ORDER_CODES / cost_max) : 0.0f;
+}
+
 }  // namespace
 
-hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld, double horizon,
-                                  double r_exit, const double secular_omega[3],
-                                  unsigned** order, float** key,
+namespace {
+
+// The per-axis matrices of ai_order_model, which depend on the trap alone.
+struct TrapTables {
+  double a[3], q[3], omega_rf, t0;
+  float phi[3][AI_ORDER_SAMPLES][2];
+  float mono[3][4];
+};
+
+// Fundamental solutions of x'' = -(a_k + 2 q_k cos(omega_rf t)) omega_rf^2 / 4 x
+// from t0 over one period, classical RK4 with SUB steps per sample; the trap's
+// cosine on the half-step grid is shared by all axes.
+void trap_tables(TrapTables& T, double period) {
+  constexpr int SUB = 32;
+  constexpr int STEPS = AI_ORDER_SAMPLES * SUB;
+  const double h = period / STEPS;
+  double cosine[2 * STEPS + 1];
+  for (int i = 0; i <= 2 * STEPS; ++i) cosine[i] = std::cos(T.omega_rf * (T.t0 + 0.5 * h * i));
+  const double c = 0.25 * T.omega_rf * T.omega_rf;
+  for (int k = 0; k < 3; ++k) {
+    if (k > 0 && T.a[k] == T.a[k - 1] && T.q[k] == T.q[k - 1]) {  // the previous axis's equation
+      for (int j = 0; j < AI_ORDER_SAMPLES; ++j)
+        for (int col = 0; col < 2; ++col) T.phi[k][j][col] = T.phi[k - 1][j][col];
+      for (int e = 0; e < 4; ++e) T.mono[k][e] = T.mono[k - 1][e];
+      continue;
+    }
+    auto acc = [&](int half_steps, double x) {
+      return -(T.a[k] + 2.0 * T.q[k] * cosine[half_steps]) * c * x;
+    };
+    for (int col = 0; col < 2; ++col) {
+      double x = col == 0 ? 1.0 : 0.0, v = col == 0 ? 0.0 : 1.0;
+      for (int i = 0; i < STEPS; ++i) {
+        const double k1x = v, k1v = acc(2 * i, x);
+        const double k2x = v + 0.5 * h * k1v, k2v = acc(2 * i + 1, x + 0.5 * h * k1x);
+        const double k3x = v + 0.5 * h * k2v, k3v = acc(2 * i + 1, x + 0.5 * h * k2x);
+        const double k4x = v + h * k3v, k4v = acc(2 * i + 2, x + h * k3x);
+        x += h / 6.0 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x);
+        v += h / 6.0 * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
+        if ((i + 1) % SUB == 0) T.phi[k][(i + 1) / SUB - 1][col] = (float)x;
+      }
+      T.mono[k][col] = (float)x;      // x row
+      T.mono[k][2 + col] = (float)v;  // v row
+    }
+  }
+}
+
+// Recently built tables (a batch repeats traps; a serving loop repeats calls).
+constexpr int TABLE_CACHE = 16;
+std::mutex table_mutex;
+TrapTables table_cache[TABLE_CACHE];
+int table_count = 0, table_next = 0;
+
+bool same_trap(const TrapTables& T, const double a[3], const double q[3], double omega_rf,
+               double t0) {
+  for (int k = 0; k < 3; ++k)
+    if (T.a[k] != a[k] || T.q[k] != q[k]) return false;
+  return T.omega_rf == omega_rf && T.t0 == t0;
+}
+
+}  // namespace
+
+ai_order_model ai_make_order_model(const double a[3], const double q[3], double omega_rf,
+                                   double r_exit, double t0, double tmax, double rtol,
+                                   bool sampled) {
+  ai_order_model m{};
+  m.sampled = sampled ? 1 : 0;
+  m.r_exit = r_exit;
+  for (int k = 0; k < 3; ++k)
+    m.secular_omega[k] = 0.5 * std::fabs(omega_rf) * std::sqrt(std::fmax(a[k] + 0.5 * q[k] * q[k], 0.0));
+  const double horizon = tmax - t0;
+  const double w = std::fabs(omega_rf);
+  // one RF period (any interval for a static trap, whose equation is autonomous)
+  const double period = w > 0.0 ? 6.283185307179586 / w : horizon / AI_ORDER_MAX_PERIODS;
+  m.horizon = (float)horizon;
+  m.r_exit2 = (float)(r_exit * r_exit * (1.0 + 0x1p-12));
+  m.dt = (float)(period / AI_ORDER_SAMPLES);
+  m.periods = (int)std::fmin(std::ceil(horizon / period), (double)AI_ORDER_MAX_PERIODS);
+  double qmax = 0.0;
+  for (int k = 0; k < 3; ++k) qmax = std::fmax(qmax, std::fabs(q[k]));
+  // ode45's attempts per unit time grow with the RF frequency, slowly with q
+  // (exponent fitted to measured attempt counts) and as rtol^(-1/5)
+  m.rate = (float)((w > 0.0 ? w : 1.0 / horizon) * std::pow(std::fmax(qmax, 1e-3), 0.3) *
+                   std::pow(rtol, -0.2));
+
+  if (!sampled) return m;
+  TrapTables T;
+  bool found = false;
+  {
+    std::lock_guard<std::mutex> lock(table_mutex);
+    for (int i = 0; i < table_count && !found; ++i)
+      if (same_trap(table_cache[i], a, q, omega_rf, t0)) {
+        T = table_cache[i];
+        found = true;
+      }
+  }
+  if (!found) {
+    for (int k = 0; k < 3; ++k) {
+      T.a[k] = a[k];
+      T.q[k] = q[k];
+    }
+    T.omega_rf = omega_rf;
+    T.t0 = t0;
+    // the static trap's interval depends on the horizon: not cached
+    trap_tables(T, period);
+    if (w > 0.0) {
+      std::lock_guard<std::mutex> lock(table_mutex);
+      table_cache[table_next] = T;
+      table_next = (table_next + 1) % TABLE_CACHE;
+      if (table_count < TABLE_CACHE) ++table_count;
+    }
+  }
+  std::memcpy(m.phi, T.phi, sizeof m.phi);
+  std::memcpy(m.mono, T.mono, sizeof m.mono);
+  return m;
+}
+
+hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld,
+                                  const ai_order_model& model, unsigned** order, unsigned** key,
                                   void** workspace, hipStream_t stream) {
-  SecularTrap trap;
-  for (int k = 0; k < 3; ++k) trap.w[k] = secular_omega[k];
+  const float scale = code_scale((double)model.horizon * model.rate);
   const unsigned threads = 256;
   const unsigned blocks = (unsigned)((n + threads - 1) / threads);
-  return sort_by_key(n, order, key, workspace, stream, [&](float* key_in, unsigned* idx_in) {
+  return sort_by_key(n, order, key, workspace, stream, [&](unsigned* key_in, unsigned* idx_in) {
     hipLaunchKernelGGL(ai_cost_key_kernel, dim3(blocks), dim3(threads), 0, stream, y0,
-                       (long long)n, (long long)ld, (float)horizon, r_exit, trap, key_in,
-                       idx_in);
+                       (long long)n, (long long)ld, model, scale, key_in, idx_in);
   });
 }
 
 hipError_t ai_longest_first_order_batch(const ai_order_item* items, int count, int64_t total,
-                                        unsigned** order, float** key, void** workspace,
-                                        hipStream_t stream) {
+                                        double cost_max, unsigned** order, unsigned** key,
+                                        void** workspace, hipStream_t stream) {
+  const float scale = code_scale(cost_max);
   if (count <= 0) return hipErrorInvalidValue;
   const unsigned threads = 256;
   const unsigned blocks = (unsigned)((total + threads - 1) / threads);
-  return sort_by_key(total, order, key, workspace, stream, [&](float* key_in, unsigned* idx_in) {
+  return sort_by_key(total, order, key, workspace, stream, [&](unsigned* key_in, unsigned* idx_in) {
     hipLaunchKernelGGL(ai_cost_key_batch_kernel, dim3(blocks), dim3(threads), 0, stream, items,
-                       count, (long long)total, key_in, idx_in);
+                       count, (long long)total, scale, key_in, idx_in);
   });
 }
