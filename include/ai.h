@@ -111,7 +111,8 @@ enum ai_rc {
   AI_EINVAL = -1,        /* invalid argument; nothing was launched */
   AI_EHIP = -2,          /* HIP runtime error; text in ai_last_error() */
   AI_ENOMEM = -3,        /* device allocation failed */
-  AI_EUNSUPPORTED = -4   /* valid request this build does not run (exponents other than 4, 8) */
+  AI_EUNSUPPORTED = -4,  /* valid request this build does not run (exponents other than 4, 8) */
+  AI_EAGAIN = -5         /* ai_server_wait: the request has not finished within the timeout */
 };
 
 /* Integrate trajectories i = 0 .. n-1 and wait for the result.
@@ -180,6 +181,63 @@ int ai_integrate_batch_async(const ai_batch_item *items, int32_t count, int32_t 
 
 /* As ai_integrate_batch_async on the null stream, waiting for the result. */
 int ai_integrate_batch(const ai_batch_item *items, int32_t count, int32_t kernel);
+
+/* ---- Serving: a stream of integration requests ------------------------------
+ *
+ * The paper's ensemble call (Sec. 3.3) offered as a service: requests of
+ * different systems, sizes and tolerances arrive over time and each is
+ * answered as soon as its launch completes.  A server owns one stream on the
+ * device that is current when it is
+ * created and one worker thread.  Requests are validated when submitted and
+ * queued in arrival order; whenever its previous launch has finished, the
+ * worker takes every queued request (in order, up to max_batch trajectories;
+ * at least one) into one ai_integrate_batch_async launch, so requests that
+ * arrive while the GPU is busy share the next launch.  A request with
+ * AI_FP32_STAGES runs alone (ai_integrate_async).  A request's results are
+ * bitwise those of ai_integrate on it alone, whatever it shares a launch with.
+ * The caller owns every buffer and keeps it allocated until ai_server_wait has
+ * returned the request's completion. */
+typedef struct ai_server ai_server;
+
+typedef struct ai_server_config {
+  int64_t max_batch;  /* trajectories per launch, >= 0; 0 selects 2^22 */
+  int32_t schedule;   /* AI_SCHEDULE_LONGEST_FIRST or 0, for every launch */
+  int32_t reserved;   /* 0 */
+} ai_server_config;
+
+/* Completion record of a request.  Times are seconds of the host's monotonic
+ * clock (CLOCK_MONOTONIC): submitted, taken into a launch, launch completed. */
+typedef struct ai_request_info {
+  int32_t rc;          /* AI_OK, AI_WRTOL, or a negative ai_rc of its launch */
+  int32_t batch_size;  /* requests in its launch */
+  int64_t batch_id;    /* launches are numbered 0, 1, ... per server */
+  int64_t batch_trajectories; /* trajectories in its launch */
+  double submit_s, start_s, end_s;
+  char error[128];     /* ai_last_error() text of a failed launch, else "" */
+} ai_request_info;
+
+/* Create a server (cfg may be NULL for the defaults).  Returns AI_OK,
+ * AI_EINVAL, AI_EHIP or AI_ENOMEM; *out is NULL on failure. */
+int ai_server_create(const ai_server_config *cfg, ai_server **out);
+
+/* Queue one request: item as in ai_integrate_batch (device buffers on the
+ * server's device), kernel AI_KERNEL_PLAIN or AI_KERNEL_PLAIN |
+ * AI_FP32_STAGES.  Validates it as ai_integrate does and returns its error
+ * without queueing it, else AI_OK (or AI_WRTOL if its rtol will be raised)
+ * and a ticket, unique per server.  Thread-safe. */
+int ai_server_submit(ai_server *srv, const ai_batch_item *item, int32_t kernel,
+                     uint64_t *ticket);
+
+/* Wait up to timeout_s seconds (< 0: without limit) for the request of
+ * `ticket` and fill *info.  Returns AI_OK once it has completed (its own
+ * outcome is info->rc) and forgets the ticket; AI_EAGAIN if it has not
+ * completed yet (wait again); AI_EINVAL for a ticket it does not hold. */
+int ai_server_wait(ai_server *srv, uint64_t ticket, double timeout_s, ai_request_info *info);
+
+/* Finish every queued request, stop the worker and release the server.
+ * Requests not yet waited for are forgotten (their outputs are complete).  No
+ * other call on the server may be in progress or follow. */
+int ai_server_destroy(ai_server *srv);
 
 /* Launch facts of one kernel on the current device. */
 typedef struct ai_kernel_info {

@@ -22,12 +22,12 @@ SCHEDULE_LONGEST_FIRST = 16
 SCHEDULES = {None: 0, "index": 0, "longest-first": SCHEDULE_LONGEST_FIRST}
 FP32_STAGES = 32                      # AI_FP32_STAGES
 PRECISIONS = {"fp64": 0, "fp32-stages": FP32_STAGES}
-OK, WRTOL, EINVAL, EHIP, ENOMEM, EUNSUPPORTED = 0, 1, -1, -2, -3, -4
+OK, WRTOL, EINVAL, EHIP, ENOMEM, EUNSUPPORTED, EAGAIN = 0, 1, -1, -2, -3, -4, -5
 
 # exported symbols of the C ABI, in declaration order
 SYMBOLS = ("ai_integrate", "ai_integrate_async", "ai_integrate_batch",
-           "ai_integrate_batch_async", "ai_get_kernel_info", "ai_last_error", "ai_nobs",
-           "ai_version")
+           "ai_integrate_batch_async", "ai_server_create", "ai_server_submit", "ai_server_wait",
+           "ai_server_destroy", "ai_get_kernel_info", "ai_last_error", "ai_nobs", "ai_version")
 
 
 class AiParams(C.Structure):
@@ -48,6 +48,25 @@ class AiBatchItem(C.Structure):
         ("t0", C.c_double), ("tmax", C.c_double), ("rtol", C.c_double), ("atol", C.c_double),
         ("final_state", C.c_void_p), ("obs", C.c_void_p),
     ]
+
+
+class AiServerConfig(C.Structure):
+    _fields_ = [("max_batch", C.c_int64), ("schedule", C.c_int32), ("reserved", C.c_int32)]
+
+
+class AiRequestInfo(C.Structure):
+    """ai_request_info: completion record of a served request."""
+    _fields_ = [
+        ("rc", C.c_int32), ("batch_size", C.c_int32), ("batch_id", C.c_int64),
+        ("batch_trajectories", C.c_int64),
+        ("submit_s", C.c_double), ("start_s", C.c_double), ("end_s", C.c_double),
+        ("error", C.c_char * 128),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["error"] = self.error.decode()
+        return d
 
 
 class AiKernelInfo(C.Structure):
@@ -94,6 +113,16 @@ def load(path: str = LIB_PATH):
         lib.ai_integrate_batch_async.argtypes = [C.POINTER(AiBatchItem), C.c_int32, C.c_int32,
                                                  C.c_void_p]
         lib.ai_integrate_batch_async.restype = C.c_int
+        lib.ai_server_create.argtypes = [C.POINTER(AiServerConfig), C.POINTER(C.c_void_p)]
+        lib.ai_server_create.restype = C.c_int
+        lib.ai_server_submit.argtypes = [C.c_void_p, C.POINTER(AiBatchItem), C.c_int32,
+                                         C.POINTER(C.c_uint64)]
+        lib.ai_server_submit.restype = C.c_int
+        lib.ai_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_double,
+                                       C.POINTER(AiRequestInfo)]
+        lib.ai_server_wait.restype = C.c_int
+        lib.ai_server_destroy.argtypes = [C.c_void_p]
+        lib.ai_server_destroy.restype = C.c_int
         lib.ai_get_kernel_info.argtypes = [C.c_int32, C.POINTER(AiKernelInfo)]
         lib.ai_get_kernel_info.restype = C.c_int
         lib.ai_last_error.restype = C.c_char_p
@@ -211,6 +240,63 @@ def ai_integrate_batch_async(items, schedule=None, stream=None):
     arr = batch_items(items)
     return _check(load().ai_integrate_batch_async(arr, len(items), SCHEDULES[schedule],
                                                   C.c_void_p(s.cuda_stream)))
+
+
+def ai_server_create(max_batch: int = 0, schedule="longest-first") -> C.c_void_p:
+    cfg = AiServerConfig(int(max_batch), SCHEDULES[schedule], 0)
+    h = C.c_void_p()
+    _check(load().ai_server_create(C.byref(cfg), C.byref(h)))
+    return h
+
+
+def ai_server_submit(server, item, precision="fp64") -> int:
+    """Queue one request (a batch_items tuple); returns its ticket."""
+    arr = batch_items([item])
+    ticket = C.c_uint64()
+    _check(load().ai_server_submit(server, arr, PRECISIONS[precision], C.byref(ticket)))
+    return ticket.value
+
+
+def ai_server_wait(server, ticket: int, timeout=None):
+    """The request's completion record (a dict), or None if it has not
+    completed within `timeout` seconds (None: wait without limit)."""
+    info = AiRequestInfo()
+    rc = load().ai_server_wait(server, C.c_uint64(ticket),
+                               -1.0 if timeout is None else float(timeout), C.byref(info))
+    if rc == EAGAIN:
+        return None
+    _check(rc)
+    return info.as_dict()
+
+
+def ai_server_destroy(server) -> int:
+    return _check(load().ai_server_destroy(server))
+
+
+class Server:
+    """ai_server: requests (batch_items tuples) queued and served by batched
+    launches on the server's own stream.  The tensors of a request must stay
+    alive until wait() has returned its completion."""
+
+    def __init__(self, max_batch: int = 0, schedule="longest-first"):
+        self._h = ai_server_create(max_batch, schedule)
+
+    def submit(self, item, precision="fp64") -> int:
+        return ai_server_submit(self._h, item, precision)
+
+    def wait(self, ticket: int, timeout=None):
+        return ai_server_wait(self._h, ticket, timeout)
+
+    def close(self):
+        if self._h:
+            h, self._h = self._h, None
+            ai_server_destroy(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def ai_get_kernel_info(kernel="plain", precision="fp64") -> dict:

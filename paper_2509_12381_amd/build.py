@@ -18,8 +18,10 @@ from concurrent.futures import ThreadPoolExecutor
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
-SOURCES = [os.path.join(CSRC, "ai.hip"), os.path.join(CSRC, "schedule.hip")]
-HEADERS = [os.path.join(ROOT, "include", "ai.h"), os.path.join(CSRC, "schedule.h")]
+SOURCES = [os.path.join(CSRC, "ai.hip"), os.path.join(CSRC, "schedule.hip"),
+           os.path.join(CSRC, "server.hip")]
+HEADERS = [os.path.join(ROOT, "include", "ai.h"), os.path.join(CSRC, "schedule.h"),
+           os.path.join(CSRC, "internal.h")]
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libai.so")
 ARCH = "gfx950"

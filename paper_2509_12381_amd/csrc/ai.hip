@@ -39,6 +39,7 @@
 #include <vector>
 
 #include "ai.h"
+#include "internal.h"
 #include "schedule.h"
 
 namespace {
@@ -1383,6 +1384,20 @@ int launch_finalize(const Launch& P, double* final_state, double* obs, hipStream
 }
 
 }  // namespace
+
+int ai_fail(int rc, const char* msg) { return fail(rc, "%s", msg); }
+
+int ai_check_request(const ai_batch_item* item, int32_t kernel) {
+  g_error.clear();
+  if (!item) return fail(AI_EINVAL, "item is NULL");
+  if ((kernel & ~AI_FP32_STAGES) != AI_KERNEL_PLAIN)
+    return fail(AI_EUNSUPPORTED, "a request runs the plain kernel (kernel 0x%x)",
+                (unsigned)kernel);
+  const int rc = validate(&item->params, item->y0, item->n, item->ld, item->t0, item->tmax,
+                          item->rtol, item->atol, item->final_state, item->obs, kernel);
+  if (rc != AI_OK) return rc;
+  return item->rtol < 100.0 * 2.220446049250313e-16 ? AI_WRTOL : AI_OK;
+}
 
 extern "C" {
 

@@ -27,7 +27,8 @@ def lib():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     assert names == sorted(["ai_integrate", "ai_integrate_async", "ai_integrate_batch",
-                            "ai_integrate_batch_async", "ai_get_kernel_info",
+                            "ai_integrate_batch_async", "ai_server_create", "ai_server_submit",
+                            "ai_server_wait", "ai_server_destroy", "ai_get_kernel_info",
                             "ai_last_error", "ai_nobs", "ai_version"])
 
 
@@ -51,6 +52,63 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(binding.AiKernelInfo) == 6 * 4 + 8
     # ai_batch_item: ai_params, pointer, 2 int64, 4 doubles, 2 pointers
     assert ctypes.sizeof(binding.AiBatchItem) == ctypes.sizeof(binding.AiParams) + 8 * 9
+
+
+def test_struct_layout_against_the_c_compiler(tmp_path):
+    """sizeof and field offsets of every ABI struct as gcc lays them out from
+    include/ai.h, against the binding's ctypes declarations."""
+    from paper_2509_12381_amd import binding
+    structs = {"ai_params": binding.AiParams, "ai_batch_item": binding.AiBatchItem,
+               "ai_server_config": binding.AiServerConfig,
+               "ai_request_info": binding.AiRequestInfo, "ai_kernel_info": binding.AiKernelInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ai.h"', 'int main(void) {']
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    for line in out.splitlines():
+        cname, what, value = line.split()
+        cls = structs[cname]
+        got = ctypes.sizeof(cls) if what == "sizeof" else getattr(cls, what).offset
+        assert got == int(value), (cname, what, got, value)
+
+
+def test_server_argument_errors_without_gpu(lib):
+    """Null handles and bad configurations are refused before any device call;
+    creating a server on a host without a GPU reports the HIP error."""
+    from paper_2509_12381_amd import binding
+    L = binding.load()
+    h = ctypes.c_void_p()
+    assert L.ai_server_create(None, None) == binding.EINVAL
+    bad = binding.AiServerConfig(-1, 0, 0)
+    assert L.ai_server_create(ctypes.byref(bad), ctypes.byref(h)) == binding.EINVAL
+    bad = binding.AiServerConfig(0, 1, 0)
+    assert L.ai_server_create(ctypes.byref(bad), ctypes.byref(h)) == binding.EINVAL
+    assert h.value is None
+    t = ctypes.c_uint64()
+    info = binding.AiRequestInfo()
+    assert L.ai_server_submit(None, None, 0, ctypes.byref(t)) == binding.EINVAL
+    assert L.ai_server_wait(None, 1, 0.0, ctypes.byref(info)) == binding.EINVAL
+    assert L.ai_server_destroy(None) == binding.EINVAL
+    if not _gpu_visible():
+        rc = L.ai_server_create(None, ctypes.byref(h))
+        assert rc == binding.EHIP and h.value is None
+
+
+def _gpu_visible():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
 
 
 def test_constants_without_gpu(lib):
