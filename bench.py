@@ -142,6 +142,61 @@ def batched_grid(binding, W, flops, torch, reps: int = 3) -> dict:
                          "kernel": "ai_plain_batch_kernel"}}
 
 
+def serving(binding, W, torch, count: int, workers: int = 0) -> dict:
+    """The serving stream: `count` requests of the Poisson stream submitted to
+    an ai_server at their arrival times (from a thread of their own), each
+    integrating its slice of the pool; latency = completion - submission of
+    each request, on the host's monotonic clock."""
+    import queue as queue_mod
+    import threading
+
+    import numpy as np
+    stream = W.serving_stream(count)
+    pool = torch.from_numpy(W.serving_pool().initial_states()).cuda()
+    reqs = []
+    for r in stream:
+        y0 = pool[:, r.offset:r.offset + r.n].contiguous()
+        reqs.append((r, y0, torch.empty_like(y0),
+                     torch.empty((W.NOBS, r.n), dtype=torch.float64, device="cuda")))
+    system = W.serving_pool(1).system
+    t_end = W.serving_pool(1).tmax
+    torch.cuda.synchronize()
+    srv = binding.Server(schedule="longest-first", workers=workers)
+    tickets = queue_mod.Queue()
+
+    def submit_all():
+        t0 = time.perf_counter()
+        for r, y0, f, o in reqs:
+            delay = t0 + r.arrival_s - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.put(srv.submit((system, y0, f, o, 0.0, t_end, r.rtol, r.atol), r.precision))
+
+    th = threading.Thread(target=submit_all)
+    th.start()
+    infos = [srv.wait(tickets.get()) for _ in reqs]
+    th.join()
+    srv.close()
+    lat = np.array([i["end_s"] - i["submit_s"] for i in infos]) * 1e3
+    wall = max(i["end_s"] for i in infos) - min(i["submit_s"] for i in infos)
+    n = sum(r.n for r, *_ in reqs)
+    steps = float(sum(o[W.OBS["nsteps"]].sum().item() for *_, o in reqs))
+    launches = {i["batch_id"]: (i["start_s"], i["end_s"]) for i in infos}
+    in_flight = sum(e - s for s, e in launches.values())
+    bad = [i["rc"] for i in infos if i["rc"] < 0]
+    return {"workload": f"poisson-{W.SERVING_RATE_HZ:g}rps", "requests": len(reqs),
+            "workers": workers or 3,
+            "seed": W.SERVING_SEED, "stream_s": stream[-1].arrival_s,
+            "trajectories": n, "fp32_stage_requests": sum(r.precision != "fp64" for r, *_ in reqs),
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "mean": float(lat.mean()), "max": float(lat.max()),
+                           "what": "request submit to completion, host monotonic clock"},
+            "trajectories_per_s": n / wall, "accepted_steps_per_s": steps / wall,
+            "offered_trajectories_per_s": n / stream[-1].arrival_s,
+            "launches": len(launches), "mean_requests_per_launch": len(reqs) / len(launches),
+            "mean_launches_in_flight": in_flight / wall, "failed_requests": len(bad)}
+
+
 def cpu_baseline(wl, y0_host, sample: int):
     """The oracle as it stands, on the first `sample` trajectories of the same
     ensemble, with the host threads of this process's CPU share."""
@@ -174,6 +229,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip timing the batched 64-ensemble grid")
+    ap.add_argument("--serving-requests", type=int, default=200,
+                    help="requests of the serving stream to run (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="trajectories the oracle baseline integrates (default: the whole ensemble)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -291,6 +348,10 @@ def main() -> int:
     if not args.no_batch and args.n is None:
         batched = batched_grid(binding, W, flops, torch)
 
+    served = None
+    if args.serving_requests > 0 and args.n is None:
+        served = serving(binding, W, torch, args.serving_requests)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, y0_host, min(args.cpu_sample, wl.n))
@@ -328,6 +389,7 @@ def main() -> int:
         "kernel_info": info,
         "other_variants": other,
         "batched_grid": batched,
+        "serving": served,
         "cpu_baseline": cpu,
         "wall_s_timed_region": wall,
     }

@@ -186,14 +186,16 @@ int ai_integrate_batch(const ai_batch_item *items, int32_t count, int32_t kernel
  *
  * The paper's ensemble call (Sec. 3.3) offered as a service: requests of
  * different systems, sizes and tolerances arrive over time and each is
- * answered as soon as its launch completes.  A server owns one stream on the
- * device that is current when it is
- * created and one worker thread.  Requests are validated when submitted and
- * queued in arrival order; whenever its previous launch has finished, the
- * worker takes every queued request (in order, up to max_batch trajectories;
- * at least one) into one ai_integrate_batch_async launch, so requests that
- * arrive while the GPU is busy share the next launch.  A request with
- * AI_FP32_STAGES runs alone (ai_integrate_async).  A request's results are
+ * answered as soon as its launch completes.  A server works on the device
+ * that is current when it is created, with one or more workers, each a thread
+ * with a stream of its own.
+ * Requests are validated when submitted and queued in arrival order; whenever
+ * its previous launch has finished, a worker takes every queued request (in
+ * order, up to max_batch trajectories; at least one) into one
+ * ai_integrate_batch_async launch, so requests that arrive while launches run
+ * share the next one, and several workers keep launches overlapping (a
+ * launch's last, longest trajectories leave most of the GPU idle).  A request
+ * with AI_FP32_STAGES runs alone (ai_integrate_async).  A request's results are
  * bitwise those of ai_integrate on it alone, whatever it shares a launch with.
  * The caller owns every buffer and keeps it allocated until ai_server_wait has
  * returned the request's completion. */
@@ -202,7 +204,7 @@ typedef struct ai_server ai_server;
 typedef struct ai_server_config {
   int64_t max_batch;  /* trajectories per launch, >= 0; 0 selects 2^22 */
   int32_t schedule;   /* AI_SCHEDULE_LONGEST_FIRST or 0, for every launch */
-  int32_t reserved;   /* 0 */
+  int32_t workers;    /* launches in flight at once, 0 .. 16; 0 selects 3 */
 } ai_server_config;
 
 /* Completion record of a request.  Times are seconds of the host's monotonic

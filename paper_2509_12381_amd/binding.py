@@ -51,7 +51,7 @@ class AiBatchItem(C.Structure):
 
 
 class AiServerConfig(C.Structure):
-    _fields_ = [("max_batch", C.c_int64), ("schedule", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("max_batch", C.c_int64), ("schedule", C.c_int32), ("workers", C.c_int32)]
 
 
 class AiRequestInfo(C.Structure):
@@ -242,8 +242,8 @@ def ai_integrate_batch_async(items, schedule=None, stream=None):
                                                   C.c_void_p(s.cuda_stream)))
 
 
-def ai_server_create(max_batch: int = 0, schedule="longest-first") -> C.c_void_p:
-    cfg = AiServerConfig(int(max_batch), SCHEDULES[schedule], 0)
+def ai_server_create(max_batch: int = 0, schedule="longest-first", workers: int = 0) -> C.c_void_p:
+    cfg = AiServerConfig(int(max_batch), SCHEDULES[schedule], int(workers))
     h = C.c_void_p()
     _check(load().ai_server_create(C.byref(cfg), C.byref(h)))
     return h
@@ -278,8 +278,8 @@ class Server:
     launches on the server's own stream.  The tensors of a request must stay
     alive until wait() has returned its completion."""
 
-    def __init__(self, max_batch: int = 0, schedule="longest-first"):
-        self._h = ai_server_create(max_batch, schedule)
+    def __init__(self, max_batch: int = 0, schedule="longest-first", workers: int = 0):
+        self._h = ai_server_create(max_batch, schedule, workers)
 
     def submit(self, item, precision="fp64") -> int:
         return ai_server_submit(self._h, item, precision)

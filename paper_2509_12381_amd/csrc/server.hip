@@ -1,11 +1,13 @@
 // server.hip -- a stream of integration requests served by batched launches
 // (the ai_server_* entry points of ai.h; host code only).
 //
-// One worker thread per server forms launches: whenever the previous launch
-// has completed it takes every queued request, in arrival order, up to
-// max_batch trajectories, into one ai_integrate_batch_async call on the
-// server's stream.  Requests that arrive while the GPU is busy therefore share
-// the next launch, and a launch never waits for more requests to arrive.
+// Each of the server's workers owns a stream and a thread.  A worker whose
+// previous launch has completed takes every queued request, in arrival order,
+// up to max_batch trajectories, into one ai_integrate_batch_async call on its
+// stream.  Requests that arrive while launches run therefore share the next
+// one, a launch never waits for more requests to arrive, and with several
+// workers a new launch fills the SIMDs that the tail of an earlier one (its
+// longest trajectories) leaves idle.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -43,9 +45,10 @@ using RequestPtr = std::shared_ptr<Request>;
 
 struct ai_server {
   int device = 0;
-  hipStream_t stream = nullptr;
   int64_t max_batch = 0;
   int32_t schedule = 0;
+  std::vector<hipStream_t> streams;  // one per worker
+  std::vector<std::thread> workers;
 
   std::mutex mu;
   std::condition_variable work;  // a request was queued, or stop
@@ -55,10 +58,10 @@ struct ai_server {
   uint64_t next_ticket = 1;
   int64_t next_batch = 0;
   bool stopping = false;
-  std::thread worker;
 
-  void run();
-  void serve(std::vector<RequestPtr>& batch);
+  void run(hipStream_t stream);
+  void serve(std::vector<RequestPtr>& batch, hipStream_t stream);
+  void stop();
 };
 
 namespace {
@@ -87,7 +90,7 @@ std::vector<RequestPtr> take_batch(std::deque<RequestPtr>& queue, int64_t max_ba
 
 }  // namespace
 
-void ai_server::serve(std::vector<RequestPtr>& batch) {
+void ai_server::serve(std::vector<RequestPtr>& batch, hipStream_t stream) {
   const double start = now_s();
   int64_t trajectories = 0;
   for (const RequestPtr& r : batch) trajectories += r->item.n;
@@ -130,18 +133,32 @@ void ai_server::serve(std::vector<RequestPtr>& batch) {
   done.notify_all();
 }
 
-void ai_server::run() {
+void ai_server::run(hipStream_t stream) {
   (void)hipSetDevice(device);
   for (;;) {
     std::vector<RequestPtr> batch;
     {
       std::unique_lock<std::mutex> lock(mu);
       work.wait(lock, [&] { return stopping || !queue.empty(); });
-      if (queue.empty()) return;  // stopping, and everything queued has been served
+      if (queue.empty()) return;  // stopping, and everything queued has been taken
       batch = take_batch(queue, max_batch);
     }
-    serve(batch);
+    serve(batch, stream);
   }
+}
+
+// Let the workers finish what is queued, join them and release the streams.
+void ai_server::stop() {
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    stopping = true;
+  }
+  work.notify_all();
+  for (std::thread& t : workers)
+    if (t.joinable()) t.join();
+  for (hipStream_t st : streams) (void)hipStreamDestroy(st);
+  workers.clear();
+  streams.clear();
 }
 
 extern "C" {
@@ -151,25 +168,33 @@ int ai_server_create(const ai_server_config* cfg, ai_server** out) {
   *out = nullptr;
   ai_server_config c{};
   if (cfg) c = *cfg;
-  if (c.max_batch < 0 || c.reserved != 0 ||
+  if (c.max_batch < 0 || c.workers < 0 || c.workers > 16 ||
       (c.schedule != 0 && c.schedule != AI_SCHEDULE_LONGEST_FIRST))
     return ai_fail(AI_EINVAL, "config: max_batch >= 0, schedule 0 or AI_SCHEDULE_LONGEST_FIRST, "
-                              "reserved 0");
+                              "workers 0 .. 16");
   std::unique_ptr<ai_server> s(new (std::nothrow) ai_server);
   if (!s) return ai_fail(AI_ENOMEM, "server");
   s->max_batch = c.max_batch > 0 ? c.max_batch : (int64_t)1 << 22;
   s->schedule = c.schedule;
   hipError_t e = hipGetDevice(&s->device);
   if (e != hipSuccess) return ai_fail(AI_EHIP, hipGetErrorString(e));
-  // default priority: the only stream priority these kernels are run with
-  e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-  if (e != hipSuccess) return ai_fail(AI_EHIP, hipGetErrorString(e));
-  ai_server* raw = s.get();
-  try {
-    s->worker = std::thread([raw] { raw->run(); });
-  } catch (...) {
-    (void)hipStreamDestroy(s->stream);
-    return ai_fail(AI_ENOMEM, "worker thread");
+  const int workers = c.workers > 0 ? c.workers : 3;
+  for (int w = 0; w < workers; ++w) {
+    // default priority: the only stream priority these kernels are run with
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      s->stop();
+      return ai_fail(AI_EHIP, hipGetErrorString(e));
+    }
+    s->streams.push_back(st);
+    ai_server* raw = s.get();
+    try {
+      s->workers.emplace_back([raw, st] { raw->run(st); });
+    } catch (...) {
+      s->stop();
+      return ai_fail(AI_ENOMEM, "worker thread");
+    }
   }
   *out = s.release();
   return AI_OK;
@@ -227,15 +252,9 @@ int ai_server_wait(ai_server* srv, uint64_t ticket, double timeout_s, ai_request
 
 int ai_server_destroy(ai_server* srv) {
   if (!srv) return ai_fail(AI_EINVAL, "server is NULL");
-  {
-    std::lock_guard<std::mutex> lock(srv->mu);
-    srv->stopping = true;
-  }
-  srv->work.notify_all();
-  if (srv->worker.joinable()) srv->worker.join();
-  const hipError_t e = hipStreamDestroy(srv->stream);
+  srv->stop();
   delete srv;
-  return e == hipSuccess ? AI_OK : AI_EHIP;
+  return AI_OK;
 }
 
 }  // extern "C"

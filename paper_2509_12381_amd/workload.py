@@ -189,6 +189,53 @@ def batch_grid(scale: float = 1.0) -> list[Workload]:
     return out
 
 
+# The serving stream: Poisson arrivals at 200 requests/s, sizes floor(256 *
+# 4096**U), RelTol from {1e-6, 1e-8, 1e-10} with AbsTol = RelTol / 100, a
+# quarter of the requests with single-precision stages; each request
+# integrates a slice of one pool of initial states of the 1,024-trajectory
+# configuration's physics.
+SERVING_SEED = 2
+SERVING_RATE_HZ = 200.0
+SERVING_RTOLS = (1e-6, 1e-8, 1e-10)
+SERVING_POOL = 1 << 21
+SERVING_POOL_SEED = 3
+
+
+@dataclasses.dataclass(frozen=True)
+class ServingRequest:
+    arrival_s: float      # seconds after the stream starts
+    n: int                # trajectories
+    offset: int           # first trajectory of its slice of the pool
+    rtol: float
+    atol: float
+    precision: str        # "fp64" or "fp32-stages"
+
+
+def serving_stream(count: int, seed: int = SERVING_SEED, rate_hz: float = SERVING_RATE_HZ,
+                   max_size: int = 256 * 4096) -> list[ServingRequest]:
+    """The first `count` requests of the serving stream.  From one PCG64
+    stream of `seed`, per request: an exponential gap (mean 1 / rate_hz), U for
+    the size, one uniform each for the tolerance, the precision and the slice
+    offset.  Sizes are capped at max_size (the stream's own maximum by
+    default, smaller for tests)."""
+    u = np.random.Generator(np.random.PCG64(seed)).random((count, 5))
+    t = np.cumsum(-np.log1p(-u[:, 0]) / rate_hz)
+    out = []
+    for k in range(count):
+        n = min(int(math.floor(256.0 * 4096.0 ** u[k, 1])), max_size)
+        rtol = SERVING_RTOLS[min(int(u[k, 2] * len(SERVING_RTOLS)), len(SERVING_RTOLS) - 1)]
+        precision = "fp32-stages" if u[k, 3] < 0.25 else "fp64"
+        offset = int(u[k, 4] * (SERVING_POOL - n + 1))
+        out.append(ServingRequest(float(t[k]), n, offset, rtol, rtol * 1e-2, precision))
+    return out
+
+
+def serving_pool(n: int = SERVING_POOL) -> Workload:
+    """The pool the serving stream's requests slice: the 1,024-trajectory
+    configuration's physics (200 RF periods), seed 3."""
+    return thermal_workload(n, SERVING_POOL_SEED, name=f"serving-pool-{n}")
+
+
 def _uniform_rows(n: int, seed: int, ncols: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.random((n, ncols))

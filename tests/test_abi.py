@@ -92,6 +92,8 @@ def test_server_argument_errors_without_gpu(lib):
     assert L.ai_server_create(ctypes.byref(bad), ctypes.byref(h)) == binding.EINVAL
     bad = binding.AiServerConfig(0, 1, 0)
     assert L.ai_server_create(ctypes.byref(bad), ctypes.byref(h)) == binding.EINVAL
+    bad = binding.AiServerConfig(0, 0, 17)
+    assert L.ai_server_create(ctypes.byref(bad), ctypes.byref(h)) == binding.EINVAL
     assert h.value is None
     t = ctypes.c_uint64()
     info = binding.AiRequestInfo()

@@ -107,7 +107,7 @@ def test_server_launch_cap_and_close_finishes_queued_work(ai, torch):
     y = wl.initial_states()
     reqs = [_request(torch, wl, y[:, i:i + 256]) for i in range(0, 1024, 256)]
     big = _request(torch, wl, y)
-    srv = ai.Server(max_batch=512)
+    srv = ai.Server(max_batch=512, workers=1)
     tickets = [srv.submit(r["item"]) for r in reqs + [big]]
     infos = [srv.wait(t) for t in tickets[:2]]
     srv.close()
