@@ -67,3 +67,25 @@ def test_units():
     s = W.liyb_system()
     assert W.rf_periods(s, 200.0) * W.T_AU == pytest.approx(100e-6, rel=1e-12)
     assert (2 * s.Cm / s.Cn) ** 0.25 == pytest.approx(10.0)
+
+
+def test_serving_stream():
+    """Poisson arrivals at 200/s, sizes floor(256 * 4096**U), the three
+    tolerances with AbsTol = RelTol / 100, a quarter single precision, slices
+    inside the pool; deterministic for its seed."""
+    st = W.serving_stream(4000)
+    assert st == W.serving_stream(4000)
+    t = np.array([r.arrival_s for r in st])
+    gaps = np.diff(np.concatenate([[0.0], t]))
+    assert np.all(gaps > 0)
+    assert stats.kstest(gaps * W.SERVING_RATE_HZ, "expon").pvalue > 1e-3
+    n = np.array([r.n for r in st])
+    assert n.min() >= 256 and n.max() <= 256 * 4096
+    # log4096(n / 256) is uniform on [0, 1)
+    assert stats.kstest(np.log(n / 256.0) / np.log(4096.0), "uniform").pvalue > 1e-3
+    assert {r.rtol for r in st} == set(W.SERVING_RTOLS)
+    assert all(r.atol == r.rtol * 1e-2 for r in st)
+    fp32 = np.mean([r.precision == "fp32-stages" for r in st])
+    assert abs(fp32 - 0.25) < 4 * math.sqrt(0.25 * 0.75 / len(st))
+    assert all(0 <= r.offset and r.offset + r.n <= W.SERVING_POOL for r in st)
+    assert all(r.n <= 1000 for r in W.serving_stream(50, max_size=1000))
