@@ -39,7 +39,8 @@ extern "C" {
  * accepted steps, or a non-negative value at t0); r_exit = 0 disables it. */
 typedef struct ai_params {
   double m_ion, m_atom;  /* masses (electron masses), > 0 */
-  int32_t n, m;          /* exponents of V(r) = -Cn/r^n + Cm/r^m; this build runs n=4, m=8 */
+  int32_t n, m;          /* exponents of V(r) = -Cn/r^n + Cm/r^m (Sec. 4.1), 1 <= n < m <= 16;
+                            n=4, m=8 in every kernel, others in the plain double kernel */
   double Cn, Cm;         /* coefficients (C4 and C8 for n=4, m=8) */
   double a[3], q[3];     /* Paul-trap parameters per axis, paper form */
   double omega_rf;       /* trap radio frequency (inverse atomic time) */
@@ -111,7 +112,7 @@ enum ai_rc {
   AI_EINVAL = -1,        /* invalid argument; nothing was launched */
   AI_EHIP = -2,          /* HIP runtime error; text in ai_last_error() */
   AI_ENOMEM = -3,        /* device allocation failed */
-  AI_EUNSUPPORTED = -4,  /* valid request this build does not run (exponents other than 4, 8) */
+  AI_EUNSUPPORTED = -4,  /* valid request this build does not run (see ai_params.n, m) */
   AI_EAGAIN = -5         /* ai_server_wait: the request has not finished within the timeout */
 };
 
@@ -168,7 +169,8 @@ typedef struct ai_batch_item {
  * items: host array of count >= 0 entries (read during the call only).
  * kernel: AI_KERNEL_PLAIN, optionally OR AI_SCHEDULE_LONGEST_FIRST; other
  *   flags give AI_EUNSUPPORTED.
- * Every item is validated as ai_integrate validates its arguments; an invalid
+ * Every item is validated as ai_integrate validates its arguments (and must
+ * have n=4, m=8, else AI_EUNSUPPORTED); an invalid
  * item fails the whole call with AI_EINVAL before anything is launched (the
  * error text names the item).  Items with n = 0 are skipped.  Output buffers
  * of different items must not overlap.  Each trajectory's result is bitwise
@@ -195,7 +197,8 @@ int ai_integrate_batch(const ai_batch_item *items, int32_t count, int32_t kernel
  * ai_integrate_batch_async launch, so requests that arrive while launches run
  * share the next one, and several workers keep launches overlapping (a
  * launch's last, longest trajectories leave most of the GPU idle).  A request
- * with AI_FP32_STAGES runs alone (ai_integrate_async).  A request's results are
+ * with AI_FP32_STAGES, or with exponents other than n=4, m=8, runs alone
+ * (ai_integrate_async).  A request's results are
  * bitwise those of ai_integrate on it alone, whatever it shares a launch with.
  * The caller owns every buffer and keeps it allocated until ai_server_wait has
  * returned the request's completion. */

@@ -82,7 +82,8 @@ constexpr int BLOCK = 64;  // one wave per workgroup: a finished wave frees its 
 // vector registers (Ctl below).
 struct Launch {
   double inv_mi, inv_ma;     // 1/m_ion, 1/m_atom
-  double nCn, mCm;           // 4 C4 and 8 C8: (dV/dr)/r = s^3 (4 C4 - 8 C8 s^2), s = 1/r^2
+  double nCn, mCm;           // n Cn and m Cm; for n=4, m=8 (dV/dr)/r = s^3 (4 C4 - 8 C8 s^2), s = 1/r^2
+  int pot_n, pot_m;          // the exponents n < m of V(r) = -Cn/r^n + Cm/r^m
   double ka[3], kq[3];       // kappa_k(t) = ka_k + kq_k cos(omega t) = (a_k + 2 q_k cos) omega^2/4
   double omega;
   double r_exit2, r_bounce2;
@@ -163,6 +164,35 @@ __device__ __forceinline__ Force lane_force(const Launch& P) {
     f.kq[k] = in_vgpr(P.kq[k]);
   }
   return f;
+}
+
+// The force constants of a potential with other exponents: g = (dV/dr)/r =
+// n Cn r^-(n+2) - m Cm r^-(m+2), powers of s = 1/r^2 (times sqrt(s) = 1/r
+// for an odd exponent).
+struct ForceNM {
+  double inv_mi, inv_ma, nCn, mCm, ka[3], kq[3];
+  int en, em;  // n + 2 and m + 2
+};
+
+__device__ __forceinline__ ForceNM lane_force_nm(const Launch& P) {
+  ForceNM f;
+  f.inv_mi = P.inv_mi;
+  f.inv_ma = P.inv_ma;
+  f.nCn = P.nCn;
+  f.mCm = P.mCm;
+  f.en = P.pot_n + 2;
+  f.em = P.pot_m + 2;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    f.ka[k] = in_vgpr(P.ka[k]);
+    f.kq[k] = in_vgpr(P.kq[k]);
+  }
+  return f;
+}
+
+__device__ __forceinline__ Force lane_force_of(const Launch& P, const Force*) { return lane_force(P); }
+__device__ __forceinline__ ForceNM lane_force_of(const Launch& P, const ForceNM*) {
+  return lane_force_nm(P);
 }
 
 // The force constants in single precision, for the single-precision-stage
@@ -338,6 +368,29 @@ __device__ __forceinline__ double inv_fifth_root(double q) {
   return fma(-0.2 * q, w3 * w3, 1.2 * w);
 }
 
+// g = (dV/dr)/r of V(r) = -Cn/r^n + Cm/r^m (Sec. 2.1; general n, m in Sec.
+// 4.1) from s = 1/r^2: for n = 4, m = 8, s^3 (4 C4 - 8 C8 s^2).
+__device__ __forceinline__ double force_g(const Force& P, double s) {
+  const double s2 = s * s;
+  return (s2 * s) * fma(-P.mCm, s2, P.nCn);
+}
+
+// r^-k = s^(k/2) for an exponent k the same across the launch: binary powers
+// of s, times 1/r for odd k.
+__device__ __forceinline__ double inv_rpow(double s, double rinv, int k) {
+  double p = (k & 1) ? rinv : 1.0, b = s;
+  for (int e = k >> 1; e > 0; e >>= 1) {
+    if (e & 1) p *= b;
+    b *= b;
+  }
+  return p;
+}
+
+__device__ __forceinline__ double force_g(const ForceNM& P, double s) {
+  const double rinv = ((P.en | P.em) & 1) ? sqrt(s) : 0.0;
+  return fma(P.nCn, inv_rpow(s, rinv, P.en), -P.mCm * inv_rpow(s, rinv, P.em));
+}
+
 // Accelerations F(t, X) of Sec. 2.1 for V(r) = -C4/r^4 + C8/r^8:
 // F_ion = -(g/m_ion) d - kappa(t) x_ion, F_atom = (g/m_atom) d with
 // d = x_ion - x_atom and g = (dV/dr)/r.  cosrf = cos(omega t).  Returns r^2
@@ -350,8 +403,7 @@ __device__ __forceinline__ double accel(const C& P, double cosrf, const double* 
   dz = X[2] - X[5];
   const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
   const double s = recip(r2);
-  const double s2 = s * s;
-  const double g = (s2 * s) * fma(-P.mCm, s2, P.nCn);
+  const double g = force_g(P, s);
   const double gi = g * P.inv_mi, ga = g * P.inv_ma;
   F[0] = -fma(gi, dx, fma(P.kq[0], cosrf, P.ka[0]) * X[0]);
   F[1] = -fma(gi, dy, fma(P.kq[1], cosrf, P.ka[1]) * X[1]);
@@ -413,7 +465,8 @@ __device__ __forceinline__ StartConst start_const(const Launch& P) {
 
 // Start of a trajectory from its initial state y: f(t0, y0), ode45's initial
 // step and the observables' initial values.
-__device__ __forceinline__ void start(const Force& Fc, const StartConst& S, const double* y,
+template <class F>
+__device__ __forceinline__ void start(const F& Fc, const StartConst& S, const double* y,
                                       Lane& L) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -592,7 +645,8 @@ __device__ __forceinline__ void conclude(const Ctl& K, LaneT<R>& L, double t, do
 // One Dormand-Prince attempt of size h = absh from (t, x, v), the error test
 // and the controller; on acceptance the state advances and the observables
 // and exits are updated.
-__device__ __forceinline__ void attempt(const Force& P, const Ctl& K, Lane& L) {
+template <class F>
+__device__ __forceinline__ void attempt(const F& P, const Ctl& K, Lane& L) {
   const double t = L.t, h = L.absh, hh = h * h;
   const double tnew = L.done ? K.tf : t + h;  // t + h is also tn below
   const double* x = L.x;
@@ -947,10 +1001,10 @@ __device__ __forceinline__ float wave_uniform(float v) {
 // order[g] (g itself when order is null); with the schedule's keys the wave
 // takes the priority of its first (longest) trajectory.
 // Trajectory idx of the ensemble P, start to end, by one lane.
-template <class R>
+template <class R, class F = Force>
 __device__ __forceinline__ void integrate_one(const Launch& P, long long idx) {
   const Ctl K = lane_ctl(P);
-  const Force Fc = lane_force(P);
+  const F Fc = lane_force_of(P, (const F*)nullptr);
   Lane L;
   double y[12];
   load_column(P, idx, y);
@@ -991,18 +1045,23 @@ __device__ __forceinline__ void wave_priority_from_keys(const unsigned* key) {
   }
 }
 
-template <class R>
+template <class R, class F = Force>
 __device__ __forceinline__ void plain_body(const Launch& P) {
   const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
   wave_priority_from_keys(P.key);
   if (g >= P.n) return;
-  integrate_one<R>(P, P.order ? (long long)P.order[g] : g);
+  integrate_one<R, F>(P, P.order ? (long long)P.order[g] : g);
 }
 
 __global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P) { plain_body<double>(P); }
 
 // The same with single-precision stages (AI_FP32_STAGES).
 __global__ __launch_bounds__(BLOCK) void ai_plain32_kernel(Launch P) { plain_body<float>(P); }
+
+// The same for potentials with exponents other than n = 4, m = 8.
+__global__ __launch_bounds__(BLOCK) void ai_plain_nm_kernel(Launch P) {
+  plain_body<double, ForceNM>(P);
+}
 
 // A batch of ensembles in one index space: lane g integrates global index
 // order[g] (g without a schedule) of the ensemble that holds it, with that
@@ -1294,9 +1353,14 @@ int validate(const ai_params* p, const double* y0, int64_t n, int64_t ld, double
     return fail(AI_EINVAL, "need finite t0 < tmax");
   if (!std::isfinite(rtol) || !(rtol > 0.0) || !std::isfinite(atol) || !(atol > 0.0))
     return fail(AI_EINVAL, "rtol and atol must be finite and > 0");
-  if (p->n != 4 || p->m != 8)
-    return fail(AI_EUNSUPPORTED, "exponents n=%d, m=%d: this build integrates n=4, m=8",
-                p->n, p->m);
+  if (p->n != 4 || p->m != 8) {
+    if (p->m > 16)
+      return fail(AI_EUNSUPPORTED, "exponents n=%d, m=%d: this build integrates m <= 16",
+                  p->n, p->m);
+    if (base_kernel != AI_KERNEL_PLAIN || (kernel & AI_FP32_STAGES))
+      return fail(AI_EUNSUPPORTED, "exponents other than n=4, m=8 run in the plain double "
+                  "kernel only");
+  }
   // the trap phase omega t is reduced with a two-part pi/2 valid below 2^31 pi/2
   if (std::fabs(p->omega_rf) * std::fmax(std::fabs(t0), std::fabs(tmax)) >= 3.0e9)
     return fail(AI_EUNSUPPORTED, "|omega_rf t| reaches %.3g rad; this build evaluates the trap "
@@ -1330,6 +1394,8 @@ Launch launch_constants(const ai_params* p, int64_t n, int64_t ld, double t0, do
   P.inv_ma = 1.0 / p->m_atom;
   P.nCn = p->n * p->Cn;
   P.mCm = p->m * p->Cm;
+  P.pot_n = p->n;
+  P.pot_m = p->m;
   for (int k = 0; k < 3; ++k) {
     P.ka[k] = p->a[k] * w2;
     P.kq[k] = 2.0 * p->q[k] * w2;
@@ -1499,6 +1565,8 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
     }
     if (kernel & AI_FP32_STAGES)
       hipLaunchKernelGGL(ai_plain32_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
+    else if (p->n != 4 || p->m != 8)
+      hipLaunchKernelGGL(ai_plain_nm_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
     else
       hipLaunchKernelGGL(ai_plain_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
     if ((e = hipGetLastError()) != hipSuccess) {
@@ -1572,6 +1640,8 @@ int ai_integrate_batch_async(const ai_batch_item* items, int32_t count, int32_t 
       const std::string why = g_error;
       return fail(rc, "item %d: %s", b, why.c_str());
     }
+    if (it.params.n != 4 || it.params.m != 8)
+      return fail(AI_EUNSUPPORTED, "item %d: a batch integrates n=4, m=8 potentials", b);
     if (it.n == 0) continue;
     double rtol = it.rtol;
     if (rtol < 100.0 * 2.220446049250313e-16) {

@@ -66,12 +66,18 @@ struct ai_server {
 
 namespace {
 
+// A request the batched kernel does not run: single-precision stages, or a
+// potential with exponents other than n = 4, m = 8.
+bool runs_alone(const Request& r) {
+  return (r.kernel & AI_FP32_STAGES) || r.item.params.n != 4 || r.item.params.m != 8;
+}
+
 // Take the next launch's requests from the front of the queue (lock held): a
-// single-precision request alone, else double requests in order while they fit.
+// request that runs alone, else batchable requests in order while they fit.
 std::vector<RequestPtr> take_batch(std::deque<RequestPtr>& queue, int64_t max_batch) {
   std::vector<RequestPtr> batch;
   if (queue.empty()) return batch;
-  if (queue.front()->kernel & AI_FP32_STAGES) {
+  if (runs_alone(*queue.front())) {
     batch.push_back(queue.front());
     queue.pop_front();
     return batch;
@@ -79,7 +85,7 @@ std::vector<RequestPtr> take_batch(std::deque<RequestPtr>& queue, int64_t max_ba
   int64_t total = 0;
   while (!queue.empty()) {
     const RequestPtr& r = queue.front();
-    if (r->kernel & AI_FP32_STAGES) break;
+    if (runs_alone(*r)) break;
     if (!batch.empty() && total + r->item.n > max_batch) break;
     total += r->item.n;
     batch.push_back(r);
@@ -95,7 +101,7 @@ void ai_server::serve(std::vector<RequestPtr>& batch, hipStream_t stream) {
   int64_t trajectories = 0;
   for (const RequestPtr& r : batch) trajectories += r->item.n;
   int rc;
-  if (batch.size() == 1 && (batch[0]->kernel & AI_FP32_STAGES)) {
+  if (batch.size() == 1 && runs_alone(*batch[0])) {
     const ai_batch_item& it = batch[0]->item;
     rc = ai_integrate_async(&it.params, it.y0, it.n, it.ld, it.t0, it.tmax, it.rtol, it.atol,
                             it.final_state, it.obs, batch[0]->kernel | schedule, stream);

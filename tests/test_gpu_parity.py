@@ -154,6 +154,61 @@ def test_small_ensemble_parity(ai, torch, aio, rtol, atol):
     np.testing.assert_allclose(gob[O["tend"], same_seq], oob[O["tend"], same_seq], rtol=1e-6)
 
 
+def _potential(n, m, r_e=10.0, depth=4.1e-3):
+    """Cn, Cm of V = -Cn/r^n + Cm/r^m with its minimum -depth at r_e (the
+    Li + Yb+ well of the C4/C8 configuration: 10 a0, 4.1e-3 E_h)."""
+    cn = depth * r_e ** n / (1.0 - n / m)
+    return cn, n * cn * r_e ** (m - n) / m
+
+
+@pytest.mark.parametrize("n,m", [(6, 12), (4, 6), (3, 7)])
+def test_general_potential_parity(ai, torch, aio, n, m):
+    """Exponents other than 4 and 8 (Sec. 4.1), with the same well position and
+    depth, through the plain kernel's general-exponent path (odd exponents use
+    1/r = sqrt(1/r^2)), against the oracle at the 1e-6 bar."""
+    import dataclasses
+    wl = W.small_ensemble()
+    cn, cm = _potential(n, m)
+    system = dataclasses.replace(wl.system, n=n, m=m, Cn=cn, Cm=cm)
+    y0 = wl.initial_states()[:, :512]
+    gfin, gob, grc = run_gpu(ai, torch, system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol,
+                             schedule="longest-first")
+    ofin, oob, orc = run_oracle(aio, system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
+    assert grc == orc == 0
+    calm, direct = non_chaotic(aio, system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, ofin, oob)
+    assert calm.mean() > 0.95
+    rel, raw, same = _report(f"n={n} m={m}", aio, system, gob, oob, gfin, ofin, calm)
+    assert rel.max() <= 1e-6
+    assert same >= 0.99
+    assert (gob[O["status"]] == oob[O["status"]]).mean() >= 0.99
+    # the potential matters: the same states under C4/C8 end differently
+    g48, _, _ = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
+    assert not np.array_equal(g48, gfin)
+
+
+def test_general_potential_restrictions(ai, torch):
+    """Other exponents run in the plain double kernel only, m up to 16, and not
+    in a batch."""
+    import dataclasses
+    wl = W.small_ensemble()
+    y0 = wl.initial_states()[:, :64]
+    cn, cm = _potential(6, 12)
+    system = dataclasses.replace(wl.system, n=6, m=12, Cn=cn, Cm=cm)
+    for kw in (dict(kernel="persistent"), dict(precision="fp32-stages")):
+        with pytest.raises(ai.AiError) as e:
+            run_gpu(ai, torch, system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, **kw)
+        assert e.value.rc == ai.EUNSUPPORTED
+    with pytest.raises(ai.AiError) as e:
+        run_gpu(ai, torch, dataclasses.replace(system, m=17), y0, wl.t0, wl.tmax, wl.rtol,
+                wl.atol)
+    assert e.value.rc == ai.EUNSUPPORTED
+    d = torch.from_numpy(np.ascontiguousarray(y0)).cuda()
+    f, o = torch.empty_like(d), torch.empty((13, 64), dtype=torch.float64, device="cuda")
+    with pytest.raises(ai.AiError) as e:
+        ai.ai_integrate_batch([(system, d, f, o, wl.t0, wl.tmax, wl.rtol, wl.atol)])
+    assert e.value.rc == ai.EUNSUPPORTED
+
+
 def test_fixed_end_time_parity(ai, torch, aio):
     """Exit switched off: every trajectory runs to the same tmax (20 RF
     periods) and final states compare without alignment.

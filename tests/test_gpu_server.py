@@ -83,17 +83,23 @@ def test_server_alone_equals_in_mix(ai, torch):
         assert np.all(r["obs"].cpu().numpy()[:, r["n"]:] == -7.0)
 
 
-def test_server_single_precision_request_runs_alone(ai, torch):
+def test_server_requests_that_run_alone(ai, torch):
+    """Single-precision stages and potentials with other exponents do not run
+    in the batched kernel: such a request gets a launch of its own."""
+    import dataclasses
     wl = W.small_ensemble()
+    wl612 = dataclasses.replace(wl, system=dataclasses.replace(
+        wl.system, n=6, m=12, Cn=8200.0 * 2.0, Cm=4.1e9))
     y = wl.initial_states()
     reqs = [_request(torch, wl, y[:, :300]), _request(torch, wl, y[:, 300:700]),
-            _request(torch, wl, y[:, 700:])]
-    precisions = ["fp64", "fp32-stages", "fp64"]
-    with ai.Server() as srv:
+            _request(torch, wl, y[:, 700:900]), _request(torch, wl612, y[:, 900:])]
+    precisions = ["fp64", "fp32-stages", "fp64", "fp64"]
+    with ai.Server(workers=1) as srv:
         tickets = [srv.submit(r["item"], p) for r, p in zip(reqs, precisions)]
         infos = [srv.wait(t) for t in tickets]
-    assert infos[1]["batch_size"] == 1
-    assert infos[1]["batch_id"] not in (infos[0]["batch_id"], infos[2]["batch_id"])
+    for k in (1, 3):
+        assert infos[k]["batch_size"] == 1
+        assert sum(i["batch_id"] == infos[k]["batch_id"] for i in infos) == 1
     for r, p in zip(reqs, precisions):
         fin, obs = _alone(ai, torch, r, p)
         np.testing.assert_array_equal(r["fin"].cpu().numpy(), fin)

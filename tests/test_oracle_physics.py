@@ -38,9 +38,13 @@ def _hamiltonian(s, t, y):
     return h
 
 
+@pytest.mark.parametrize("n,m", [(4, 8), (6, 12), (4, 6), (3, 7)])
 @pytest.mark.parametrize("r", [9.0, 40.0, 3000.0])
-def test_force_is_minus_gradient_of_hamiltonian(aio, r):
-    s = _liyb(a=(1e-3, 2e-3, -3e-3))
+def test_force_is_minus_gradient_of_hamiltonian(aio, r, n, m):
+    """For the configuration's C4/C8 and other exponents (Sec. 4.1), with the
+    well at 10 a0 and 4.1e-3 E_h deep."""
+    cn = 4.1e-3 * 10.0**n / (1.0 - n / m)
+    s = _liyb(a=(1e-3, 2e-3, -3e-3), n=n, m=m, Cn=cn, Cm=n * cn * 10.0 ** (m - n) / m)
     rng = np.random.default_rng(int(r))
     y = rng.standard_normal(12) * np.array([50, 50, 50, 1e-7, 1e-7, 1e-7] * 2)
     u = rng.standard_normal(3)
