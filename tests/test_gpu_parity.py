@@ -186,6 +186,55 @@ def test_general_potential_parity(ai, torch, aio, n, m):
     assert not np.array_equal(g48, gfin)
 
 
+@pytest.mark.parametrize("trap", ["harmonic", "untrapped"])
+def test_trap_modes_parity(ai, torch, aio, trap):
+    """The paper's other trap modes through the same kernels: a static
+    harmonic trap (q = 0, a_k = 4 w_k^2 / Omega^2 with the Paul trap's secular
+    frequencies w_k) and no trap at all (a = q = 0, Omega = 0), against the
+    oracle at the 1e-6 bar."""
+    import dataclasses
+    wl = W.small_ensemble()
+    s = wl.system
+    if trap == "harmonic":
+        w = [0.5 * abs(s.omega_rf) * math.sqrt(max(s.a[k] + 0.5 * s.q[k] ** 2, 0.0))
+             for k in range(3)]
+        system = dataclasses.replace(s, a=tuple(4.0 * wk**2 / s.omega_rf**2 for wk in w),
+                                     q=(0.0, 0.0, 0.0))
+    else:
+        system = dataclasses.replace(s, a=(0.0, 0.0, 0.0), q=(0.0, 0.0, 0.0), omega_rf=0.0)
+    y0 = wl.initial_states()[:, :512]
+    gfin, gob, grc = run_gpu(ai, torch, system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol,
+                             schedule="longest-first")
+    ofin, oob, orc = run_oracle(aio, system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
+    assert grc == orc == 0
+    calm, _ = non_chaotic(aio, system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, ofin, oob)
+    assert calm.mean() > 0.95
+    rel, _, same = _report(trap, aio, system, gob, oob, gfin, ofin, calm)
+    assert rel.max() <= 1e-6
+    assert same >= 0.99
+    assert (gob[O["status"]] == oob[O["status"]]).mean() >= 0.99
+
+
+def test_head_on_collisions(ai, torch, aio):
+    """Head-on initial conditions (ion at rest at the origin, atom aimed at it;
+    Sec. 2.1): every trajectory is a hard bounce in the C4/C8 well, where
+    rounding is amplified, so the bar is the loose one of chaotic trajectories:
+    the same statuses and bounce counts, and end states within 1e-4."""
+    wl = W.small_ensemble()
+    rng = np.random.default_rng(7)
+    th = np.arccos(rng.uniform(-1.0, 1.0, 64))
+    ph = rng.uniform(0.0, 2.0 * math.pi, 64)
+    y0 = np.stack([W.head_on_state(wl.system, 1e4, 1e-3, t, p) for t, p in zip(th, ph)], axis=1)
+    gfin, gob, _ = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
+    ofin, oob, _ = run_oracle(aio, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
+    np.testing.assert_array_equal(gob[O["status"]], oob[O["status"]])
+    assert np.all(oob[O["bounces"]] >= 1)
+    np.testing.assert_array_equal(gob[O["bounces"]], oob[O["bounces"]])
+    direct = oob[O["bounces"]] == 1
+    rel = S.block_relative_difference(gfin[:, direct], ofin[:, direct])
+    assert direct.mean() > 0.9 and rel.max() <= 1e-4
+
+
 def test_general_potential_restrictions(ai, torch):
     """Other exponents run in the plain double kernel only, m up to 16, and not
     in a batch."""
