@@ -184,6 +184,23 @@ int ai_integrate_batch_async(const ai_batch_item *items, int32_t count, int32_t 
 /* As ai_integrate_batch_async on the null stream, waiting for the result. */
 int ai_integrate_batch(const ai_batch_item *items, int32_t count, int32_t kernel);
 
+/* Replay one trajectory with its path: the integration ai_integrate performs
+ * for it (same attempts, bitwise the same final state and observables), with
+ * (t, y) recorded at t0 and after every accepted step (Sec. 4.1 follows single
+ * trajectories, e.g. the longest-lived one of an ensemble).  Blocks until done.
+ *
+ * y0: device, the trajectory's 12 components (consecutive doubles).
+ * capacity >= 0 points; t_out: device, capacity doubles; y_out: device, 12
+ *   planes of capacity doubles (component c of point k at y_out[c*capacity+k]).
+ *   Points beyond capacity are counted but not stored.
+ * final_state: device, 12 doubles; obs: device, AI_NOBS doubles.
+ * *points (host) receives the trajectory's number of points, accepted steps + 1.
+ * The potential may have any exponents ai_integrate accepts in its plain
+ * kernel.  Returns AI_OK, AI_WRTOL or a negative ai_rc. */
+int ai_trace(const ai_params *p, const double *y0, double t0, double tmax, double rtol,
+             double atol, int64_t capacity, double *t_out, double *y_out, double *final_state,
+             double *obs, int64_t *points);
+
 /* ---- Serving: a stream of integration requests ------------------------------
  *
  * The paper's ensemble call (Sec. 3.3) offered as a service: requests of

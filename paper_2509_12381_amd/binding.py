@@ -26,7 +26,7 @@ OK, WRTOL, EINVAL, EHIP, ENOMEM, EUNSUPPORTED, EAGAIN = 0, 1, -1, -2, -3, -4, -5
 
 # exported symbols of the C ABI, in declaration order
 SYMBOLS = ("ai_integrate", "ai_integrate_async", "ai_integrate_batch",
-           "ai_integrate_batch_async", "ai_server_create", "ai_server_submit", "ai_server_wait",
+           "ai_integrate_batch_async", "ai_trace", "ai_server_create", "ai_server_submit", "ai_server_wait",
            "ai_server_destroy", "ai_get_kernel_info", "ai_last_error", "ai_nobs", "ai_version")
 
 
@@ -113,6 +113,9 @@ def load(path: str = LIB_PATH):
         lib.ai_integrate_batch_async.argtypes = [C.POINTER(AiBatchItem), C.c_int32, C.c_int32,
                                                  C.c_void_p]
         lib.ai_integrate_batch_async.restype = C.c_int
+        lib.ai_trace.argtypes = [_P, _D, C.c_double, C.c_double, C.c_double, C.c_double,
+                                 C.c_int64, _D, _D, _D, _D, C.POINTER(C.c_int64)]
+        lib.ai_trace.restype = C.c_int
         lib.ai_server_create.argtypes = [C.POINTER(AiServerConfig), C.POINTER(C.c_void_p)]
         lib.ai_server_create.restype = C.c_int
         lib.ai_server_submit.argtypes = [C.c_void_p, C.POINTER(AiBatchItem), C.c_int32,
@@ -240,6 +243,29 @@ def ai_integrate_batch_async(items, schedule=None, stream=None):
     arr = batch_items(items)
     return _check(load().ai_integrate_batch_async(arr, len(items), SCHEDULES[schedule],
                                                   C.c_void_p(s.cuda_stream)))
+
+
+def ai_trace(system, y0, t0, tmax, rtol, atol, capacity: int):
+    """Replay one trajectory (y0: 12 device doubles) and record its path:
+    returns (t (capacity,), y (12, capacity), final_state (12,), obs (AI_NOBS,),
+    points) with tensors on y0's device; points is the trajectory's number of
+    points (accepted steps + 1), of which the first `capacity` are stored."""
+    import torch
+    y = y0.reshape(-1)
+    if y.numel() != NSTATE or y.dtype != torch.float64 or not y.is_cuda or not y.is_contiguous():
+        raise ValueError("y0 must be 12 contiguous float64 values on the GPU")
+    dev = y.device
+    t_out = torch.empty((max(capacity, 1),), dtype=torch.float64, device=dev)
+    y_out = torch.empty((NSTATE, max(capacity, 1)), dtype=torch.float64, device=dev)
+    fin = torch.empty((NSTATE,), dtype=torch.float64, device=dev)
+    obs = torch.empty((NOBS,), dtype=torch.float64, device=dev)
+    pts = C.c_int64()
+    p = system if isinstance(system, AiParams) else params(system)
+    _check(load().ai_trace(C.byref(p), C.c_void_p(y.data_ptr()), float(t0), float(tmax),
+                           float(rtol), float(atol), int(capacity), C.c_void_p(t_out.data_ptr()),
+                           C.c_void_p(y_out.data_ptr()), C.c_void_p(fin.data_ptr()),
+                           C.c_void_p(obs.data_ptr()), C.byref(pts)))
+    return t_out[:capacity], y_out[:, :capacity], fin, obs, pts.value
 
 
 def ai_server_create(max_batch: int = 0, schedule="longest-first", workers: int = 0) -> C.c_void_p:

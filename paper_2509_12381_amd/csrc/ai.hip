@@ -1058,6 +1058,58 @@ __global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P) { plain_body<
 // The same with single-precision stages (AI_FP32_STAGES).
 __global__ __launch_bounds__(BLOCK) void ai_plain32_kernel(Launch P) { plain_body<float>(P); }
 
+// One trajectory (the lane 0 of one wave) with the ensemble kernels' attempt,
+// recording (t, y) at t0 and after every accepted step: point k at t_out[k]
+// and y_out[c * cap + k], for the first cap points.  Initial state y0[c],
+// final state yf[c] and observables obs[c] are 12 and AI_NOBS consecutive
+// doubles (P.ld = 1).
+template <class F>
+__device__ __forceinline__ void trace_body(const Launch& P, long long cap, double* t_out,
+                                           double* y_out) {
+  if (threadIdx.x != 0) return;
+  const Ctl K = lane_ctl(P);
+  const F Fc = lane_force_of(P, (const F*)nullptr);
+  Lane L;
+  double y[12];
+  load_column(P, 0, y);
+  start(Fc, start_const(P), y, L);
+  long long k = 0;
+  auto record = [&]() {
+    if (k < cap) {
+      t_out[k] = L.t;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        y_out[c * cap + k] = L.x[c];            // x_ion
+        y_out[(3 + c) * cap + k] = L.v[c];      // v_ion
+        y_out[(6 + c) * cap + k] = L.x[3 + c];  // x_atom
+        y_out[(9 + c) * cap + k] = L.v[3 + c];  // v_atom
+      }
+    }
+    ++k;
+  };
+  record();
+  int seen = 0;
+  while (L.status == 0) {
+    if (L.fresh) begin_step(K, L);
+    attempt(Fc, K, L);
+    if (L.nsteps != seen) {
+      seen = L.nsteps;
+      record();
+    }
+  }
+  finish(P.yf, P.obs, 1, L, 0, y[9], y[10], y[11]);
+}
+
+__global__ __launch_bounds__(BLOCK) void ai_trace_kernel(Launch P, long long cap, double* t_out,
+                                                         double* y_out) {
+  trace_body<Force>(P, cap, t_out, y_out);
+}
+
+__global__ __launch_bounds__(BLOCK) void ai_trace_nm_kernel(Launch P, long long cap,
+                                                            double* t_out, double* y_out) {
+  trace_body<ForceNM>(P, cap, t_out, y_out);
+}
+
 // The same for potentials with exponents other than n = 4, m = 8.
 __global__ __launch_bounds__(BLOCK) void ai_plain_nm_kernel(Launch P) {
   plain_body<double, ForceNM>(P);
@@ -1606,6 +1658,58 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
     return hip_fail(e, "hipFreeAsync(queue)");
   }
   return conclude();
+}
+
+int ai_trace(const ai_params* p, const double* y0, double t0, double tmax, double rtol,
+             double atol, int64_t capacity, double* t_out, double* y_out, double* final_state,
+             double* obs, int64_t* points) {
+  g_error.clear();
+  if (!points) return fail(AI_EINVAL, "points is NULL");
+  *points = 0;
+  if (capacity < 0) return fail(AI_EINVAL, "capacity = %lld < 0", (long long)capacity);
+  if (capacity > 0 && (!t_out || !y_out)) return fail(AI_EINVAL, "NULL point buffer");
+  if (capacity > (int64_t)(INT64_MAX / 8 / 16)) return fail(AI_EINVAL, "capacity too large");
+  int rc = validate(p, y0, 1, 1, t0, tmax, rtol, atol, final_state, obs, AI_KERNEL_PLAIN);
+  if (rc != AI_OK) return rc;
+  if (capacity > 0) {
+    // the point buffers are disjoint from each other and from the others
+    const char* lo[5] = {(const char*)y0, (const char*)final_state, (const char*)obs,
+                         (const char*)t_out, (const char*)y_out};
+    const int64_t ext[5] = {12 * 8, 12 * 8, AI_NOBS * 8, capacity * 8, 12 * capacity * 8};
+    for (int i = 3; i < 5; ++i)
+      for (int j = 0; j < i; ++j)
+        if (lo[i] < lo[j] + ext[j] && lo[j] < lo[i] + ext[i])
+          return fail(AI_EINVAL, "point buffers overlap");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (!on_current_device(t_out, dev) || !on_current_device(y_out, dev))
+      return fail(AI_EINVAL, "t_out and y_out must be device memory of the current device");
+  }
+  int warn = AI_OK;
+  if (rtol < 100.0 * 2.220446049250313e-16) {
+    rtol = 100.0 * 2.220446049250313e-16;
+    warn = AI_WRTOL;
+  }
+  Launch P = launch_constants(p, 1, 1, t0, tmax, rtol, atol);
+  P.y0 = y0;
+  P.yf = final_state;
+  P.obs = obs;
+  if (p->n != 4 || p->m != 8)
+    hipLaunchKernelGGL(ai_trace_nm_kernel, dim3(1), dim3(BLOCK), 0, nullptr, P,
+                       (long long)capacity, t_out, y_out);
+  else
+    hipLaunchKernelGGL(ai_trace_kernel, dim3(1), dim3(BLOCK), 0, nullptr, P,
+                       (long long)capacity, t_out, y_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "launch(trace)");
+  rc = launch_finalize(P, final_state, obs, nullptr);
+  if (rc != AI_OK) return rc;
+  double nsteps = 0.0;
+  e = hipMemcpy(&nsteps, obs + AI_OBS_NSTEPS, sizeof nsteps, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(nsteps)");
+  *points = (int64_t)nsteps + 1;
+  return warn;
 }
 
 int ai_integrate(const ai_params* p, const double* y0, int64_t n, int64_t ld, double t0,

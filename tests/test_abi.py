@@ -27,7 +27,8 @@ def lib():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     assert names == sorted(["ai_integrate", "ai_integrate_async", "ai_integrate_batch",
-                            "ai_integrate_batch_async", "ai_server_create", "ai_server_submit",
+                            "ai_integrate_batch_async", "ai_trace", "ai_server_create",
+                            "ai_server_submit",
                             "ai_server_wait", "ai_server_destroy", "ai_get_kernel_info",
                             "ai_last_error", "ai_nobs", "ai_version"])
 
@@ -79,6 +80,23 @@ def test_struct_layout_against_the_c_compiler(tmp_path):
         cls = structs[cname]
         got = ctypes.sizeof(cls) if what == "sizeof" else getattr(cls, what).offset
         assert got == int(value), (cname, what, got, value)
+
+
+def test_trace_argument_errors_without_gpu(lib):
+    """ai_trace refuses a NULL point count, a negative capacity and missing
+    point buffers before any device call."""
+    from paper_2509_12381_amd import binding, workload as W
+    L = binding.load()
+    p = binding.params(W.small_ensemble().system)
+    pts = ctypes.c_int64(7)
+    assert L.ai_trace(ctypes.byref(p), None, 0.0, 1.0, 1e-8, 1e-10, 0, None, None, None, None,
+                      None) == binding.EINVAL
+    assert L.ai_trace(ctypes.byref(p), None, 0.0, 1.0, 1e-8, 1e-10, -1, None, None, None, None,
+                      ctypes.byref(pts)) == binding.EINVAL
+    assert pts.value == 0
+    assert L.ai_trace(ctypes.byref(p), None, 0.0, 1.0, 1e-8, 1e-10, 5, None, None, None, None,
+                      ctypes.byref(pts)) == binding.EINVAL
+    assert b"point buffer" in L.ai_last_error()
 
 
 def test_server_argument_errors_without_gpu(lib):

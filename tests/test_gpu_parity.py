@@ -699,3 +699,67 @@ def test_batch_full_grid_runs(ai, torch):
         assert np.all((st >= 1) & (st <= 5)), wl.name
         if W.BATCH_Q[k % len(W.BATCH_Q)] >= 0.5:
             assert np.mean(st == W.ST_ESCAPED) > 0.99, wl.name
+
+
+def test_trace_replays_ensemble_trajectories(ai, torch):
+    """ai_trace on trajectories picked from an ensemble run (the longest-lived,
+    the most bounces, a typical flyby) gives bitwise the ensemble's final
+    state and observables, with one point per accepted step plus t0."""
+    wl = W.small_ensemble()
+    y0 = wl.initial_states()
+    gfin, gob, _ = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
+    picks = {int(np.argmax(gob[O["tend"]])), int(np.argmax(gob[O["bounces"]])), 5}
+    for i in picks:
+        yi = torch.from_numpy(np.ascontiguousarray(y0[:, i])).cuda()
+        cap = int(gob[O["nsteps"], i]) + 1
+        t, y, fin, obs, pts = ai.ai_trace(wl.system, yi, wl.t0, wl.tmax, wl.rtol, wl.atol, cap + 3)
+        t, y, fin, obs = (a.cpu().numpy() for a in (t, y, fin, obs))
+        np.testing.assert_array_equal(fin, gfin[:, i])
+        np.testing.assert_array_equal(obs, gob[:, i])
+        assert pts == cap
+        assert t[0] == wl.t0 and np.array_equal(y[:, 0], y0[:, i])
+        assert np.all(np.diff(t[:pts]) > 0)
+        assert t[pts - 1] == gob[O["tend"], i]
+        np.testing.assert_array_equal(y[:, pts - 1], gfin[:, i])
+
+
+def test_trace_capacity_and_other_potentials(ai, torch):
+    """A capacity below the point count stores the leading points and still
+    integrates to the end; a (6, 12) potential replays its ensemble run."""
+    import dataclasses
+    wl = W.small_ensemble()
+    y0 = wl.initial_states()[:, :8]
+    yi = torch.from_numpy(np.ascontiguousarray(y0[:, 3])).cuda()
+    full = ai.ai_trace(wl.system, yi, wl.t0, wl.tmax, wl.rtol, wl.atol, 100000)
+    part = ai.ai_trace(wl.system, yi, wl.t0, wl.tmax, wl.rtol, wl.atol, 10)
+    assert part[4] == full[4] > 10
+    np.testing.assert_array_equal(part[0].cpu().numpy(), full[0].cpu().numpy()[:10])
+    np.testing.assert_array_equal(part[1].cpu().numpy(), full[1].cpu().numpy()[:, :10])
+    np.testing.assert_array_equal(part[2].cpu().numpy(), full[2].cpu().numpy())
+    none = ai.ai_trace(wl.system, yi, wl.t0, wl.tmax, wl.rtol, wl.atol, 0)
+    assert none[4] == full[4]
+    cn, cm = _potential(6, 12)
+    system = dataclasses.replace(wl.system, n=6, m=12, Cn=cn, Cm=cm)
+    gfin, gob, _ = run_gpu(ai, torch, system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
+    tr = ai.ai_trace(system, yi, wl.t0, wl.tmax, wl.rtol, wl.atol, 100000)
+    np.testing.assert_array_equal(tr[2].cpu().numpy(), gfin[:, 3])
+    np.testing.assert_array_equal(tr[3].cpu().numpy(), gob[:, 3])
+
+
+def test_trace_path_conserves_energy_trap_off(ai, torch, aio):
+    """With the trap off a head-on collision conserves the Hamiltonian (the
+    oracle's independent energy function) along the whole recorded path,
+    through the bounce at the bottom of the well."""
+    import dataclasses
+    wl = W.small_ensemble()
+    system = dataclasses.replace(wl.system, a=(0.0, 0.0, 0.0), q=(0.0, 0.0, 0.0), omega_rf=0.0)
+    y0 = W.head_on_state(system, 2e3, 1e-3, 0.7, 0.3)
+    yi = torch.from_numpy(y0).cuda()
+    t, y, fin, obs, pts = ai.ai_trace(system, yi, 0.0, wl.tmax, 1e-10, 1e-12, 200000)
+    t, y = t.cpu().numpy()[:pts], y.cpu().numpy()[:, :pts]
+    assert obs.cpu().numpy()[O["bounces"]] == 1
+    e = np.array([aio.energy(system, t[k], y[:, k]) for k in range(pts)])
+    depth = system.Cn ** 2 / (4 * system.Cm)
+    assert np.max(np.abs(e - e[0])) < 1e-6 * depth
+    r = np.linalg.norm(y[0:3] - y[6:9], axis=0)
+    assert r.min() < 15.0                                  # it did reach the well
