@@ -141,7 +141,11 @@ int ai_integrate(const ai_params *p, const double *y0, int64_t n, int64_t ld, do
  * stream) and returning at once.  Buffers must stay allocated until the work
  * on the stream has completed; the library keeps no pointer after that.
  * The persistent kernel takes an 8-byte queue counter from the stream-ordered
- * allocator for the duration of the call. */
+ * allocator for the duration of the call.  The plain kernel without
+ * AI_SCHEDULE_LONGEST_FIRST enqueues two kernels and nothing else (no
+ * allocation, no memset), so that call may be captured in a HIP graph and
+ * replayed; the schedule and the persistent kernel allocate stream-ordered
+ * memory and the schedule's sort clears buffers, so those are not for capture. */
 int ai_integrate_async(const ai_params *p, const double *y0, int64_t n, int64_t ld, double t0,
                        double tmax, double rtol, double atol, double *final_state, double *obs,
                        int32_t kernel, void *stream);

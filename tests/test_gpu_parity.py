@@ -763,3 +763,32 @@ def test_trace_path_conserves_energy_trap_off(ai, torch, aio):
     assert np.max(np.abs(e - e[0])) < 1e-6 * depth
     r = np.linalg.norm(y[0:3] - y[6:9], axis=0)
     assert r.min() < 15.0                                  # it did reach the well
+
+
+def test_unscheduled_plain_call_replays_from_a_graph(ai, torch):
+    """The plain kernel without the schedule enqueues two kernels and nothing
+    else (no allocation, no memset), so a caller may capture the call in a HIP
+    graph: every replay, with eager work between them, gives the eager result."""
+    wl = W.small_ensemble()
+    y0 = torch.from_numpy(wl.initial_states()).cuda()
+    fin = torch.empty_like(y0)
+    obs = torch.empty((13, wl.n), dtype=torch.float64, device="cuda")
+    ai.ai_integrate(wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, fin, obs, "plain")
+    torch.cuda.synchronize()
+    ref_f, ref_o = fin.cpu().numpy(), obs.cpu().numpy()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ai.ai_integrate_async(wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, fin, obs,
+                                  "plain", stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        fin.fill_(-1.0)
+        obs.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(fin.cpu().numpy(), ref_f)
+        np.testing.assert_array_equal(obs.cpu().numpy(), ref_o)
