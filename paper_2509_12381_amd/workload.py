@@ -295,6 +295,56 @@ def thermal_ensemble(system: System, n: int, seed: int, T_ion: float, T_atom: fl
     return y0
 
 
+def potential_cn_de(n: int, m: int, Cn: float, De: float) -> float:
+    """Cm of V(r) = -Cn/r^n + Cm/r^m from Cn and the well depth De (the
+    paper's "CnDe" parameterization, Sec. 4): at the minimum r_e, V'(r_e) = 0
+    gives r_e^(m-n) = m Cm / (n Cn) and V(r_e) = -Cn r_e^-n (1 - n/m) = -De."""
+    r_e = (Cn * (1.0 - n / m) / De) ** (1.0 / n)
+    return n * Cn * r_e ** (m - n) / m
+
+
+def potential_de_re(n: int, m: int, De: float, Re: float) -> tuple[float, float]:
+    """(Cn, Cm) from the well depth De and its position Re (the paper's
+    "DeRe" parameterization, Sec. 4)."""
+    cn = De * Re**n / (1.0 - n / m)
+    return cn, n * cn * Re ** (m - n) / m
+
+
+def nangles_auto(count: int) -> tuple[int, int]:
+    """(n_theta, n_phi) near sqrt(count) with n_theta * n_phi >= count (the
+    product may exceed count a little, as in the paper's automatic choice)."""
+    nt = max(1, int(math.ceil(math.sqrt(count))))
+    return nt, max(1, int(math.ceil(count / nt)))
+
+
+def angle_grid(n_theta: int, n_phi: int, mode: str = "uniform", theta_min: float = 0.0,
+               theta_max: float = math.pi / 2, phi_min: float = 0.0, phi_max: float = math.pi / 2,
+               seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """Launch directions (theta, phi), n_theta * n_phi of them (the paper's
+    "uniform" and "random" positions, Sec. 4).  theta = arccos(1 - 2u) with u
+    between (1 - cos theta_min)/2 and (1 - cos theta_max)/2, so equal steps of u
+    are equal solid angles.  uniform: n_theta evenly spaced u times n_phi evenly
+    spaced phi, every pair (theta-major); random: u and phi uniform from a PCG64
+    stream of `seed`.  The default range is the first octant."""
+    u_lo, u_hi = (1.0 - math.cos(theta_min)) / 2.0, (1.0 - math.cos(theta_max)) / 2.0
+    if mode == "uniform":
+        u = np.linspace(u_lo, u_hi, n_theta)
+        ph = np.linspace(phi_min, phi_max, n_phi)
+        uu, pp = np.meshgrid(u, ph, indexing="ij")
+        return np.arccos(1.0 - 2.0 * uu.ravel()), pp.ravel()
+    if mode == "random":
+        r = np.random.Generator(np.random.PCG64(seed)).random((n_theta * n_phi, 2))
+        u = u_lo + (u_hi - u_lo) * r[:, 0]
+        return np.arccos(1.0 - 2.0 * u), phi_min + (phi_max - phi_min) * r[:, 1]
+    raise ValueError(f"unknown mode {mode!r}")
+
+
+def head_on_ensemble(system: System, r0: float, T_atom: float, theta: np.ndarray,
+                     phi: np.ndarray) -> np.ndarray:
+    """(12, N) head-on initial states, one per direction (theta[i], phi[i])."""
+    return np.stack([head_on_state(system, r0, T_atom, t, p) for t, p in zip(theta, phi)], axis=1)
+
+
 def head_on_state(system: System, r0: float, T_atom: float, theta: float, phi: float) -> np.ndarray:
     """Ion at rest at the origin, atom at r0 (sin t cos p, sin t sin p, cos t) moving
     towards it with speed sqrt(3 kT / m_atom) (paper Sec. 2.1, initial conditions)."""

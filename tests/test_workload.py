@@ -89,3 +89,49 @@ def test_serving_stream():
     assert abs(fp32 - 0.25) < 4 * math.sqrt(0.25 * 0.75 / len(st))
     assert all(0 <= r.offset and r.offset + r.n <= W.SERVING_POOL for r in st)
     assert all(r.n <= 1000 for r in W.serving_stream(50, max_size=1000))
+
+
+@pytest.mark.parametrize("n,m", [(4, 8), (6, 12), (3, 7), (4, 6)])
+def test_potential_parameterizations(n, m):
+    """DeRe and CnDe give a potential whose minimum is -De at Re (V'(Re) = 0,
+    V''(Re) > 0), and they agree with each other; for n=4, m=8
+    with the configuration's well (10 a0, 4.1e-3 E_h) they give C4 = 82,
+    C8 = 4.1e5."""
+    De, Re = 4.1e-3, 10.0
+    cn, cm = W.potential_de_re(n, m, De, Re)
+    V = lambda r: -cn / r**n + cm / r**m
+    assert V(Re) == pytest.approx(-De, rel=1e-12)
+    dV = n * cn / Re ** (n + 1) - m * cm / Re ** (m + 1)
+    assert abs(dV) <= 1e-12 * n * cn / Re ** (n + 1)
+    assert V(Re * 1.01) > V(Re) and V(Re * 0.99) > V(Re)
+    assert W.potential_cn_de(n, m, cn, De) == pytest.approx(cm, rel=1e-12)
+    if (n, m) == (4, 8):
+        assert cn == pytest.approx(82.0, rel=1e-12) and cm == pytest.approx(4.1e5, rel=1e-12)
+
+
+def test_angle_grids():
+    """uniform: every pair of n_theta evenly spaced cos(theta) and n_phi evenly
+    spaced phi, so each cell has the same solid angle; random: 1 - cos(theta) and
+    phi uniform over the range; nangles_auto covers the count."""
+    th, ph = W.angle_grid(50, 40)
+    assert th.shape == ph.shape == (2000,)
+    assert th.min() == 0.0 and th.max() == pytest.approx(math.pi / 2)
+    c = np.unique(np.round(np.cos(th), 12))
+    assert len(c) == 50 and np.allclose(np.diff(c), np.diff(c)[0])
+    assert len(np.unique(ph)) == 40 and ph.max() == pytest.approx(math.pi / 2)
+    th, ph = W.angle_grid(100, 100, "random", theta_min=0.3, theta_max=2.0, phi_min=1.0,
+                          phi_max=4.0, seed=3)
+    u = (1 - np.cos(th)) / 2
+    lo, hi = (1 - math.cos(0.3)) / 2, (1 - math.cos(2.0)) / 2
+    assert stats.kstest((u - lo) / (hi - lo), "uniform").pvalue > 1e-3
+    assert stats.kstest((ph - 1.0) / 3.0, "uniform").pvalue > 1e-3
+    for count in (1, 2, 99, 2500, 10004569):
+        nt, nph = W.nangles_auto(count)
+        assert nt * nph >= count and nt * nph - count < nt
+    wl = W.small_ensemble()
+    y = W.head_on_ensemble(wl.system, 5000.0, 1e-6, *W.angle_grid(3, 4))
+    assert y.shape == (12, 12)
+    np.testing.assert_allclose(np.linalg.norm(y[6:9], axis=0), 5000.0)
+    # aimed at the ion: velocity antiparallel to position
+    np.testing.assert_allclose(np.sum(y[6:9] * y[9:12], axis=0),
+                               -np.linalg.norm(y[6:9], axis=0) * np.linalg.norm(y[9:12], axis=0))
