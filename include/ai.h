@@ -190,20 +190,27 @@ int ai_integrate_batch(const ai_batch_item *items, int32_t count, int32_t kernel
 
 /* Replay one trajectory with its path: the integration ai_integrate performs
  * for it (same attempts, bitwise the same final state and observables), with
- * (t, y) recorded at t0 and after every accepted step (Sec. 4.1 follows single
- * trajectories, e.g. the longest-lived one of an ensemble).  Blocks until done.
+ * (t, y) recorded at t0 and at `refine` points per accepted step (Sec. 4.1
+ * follows single trajectories, e.g. the longest-lived one of an ensemble).
+ * Blocks until done.
  *
  * y0: device, the trajectory's 12 components (consecutive doubles).
+ * refine: 1 .. 1024 points per accepted step, at fractions j/refine of the step,
+ *   the last at its end.  Points inside a step come from the quintic Hermite
+ *   interpolant of the positions through position, velocity and acceleration at
+ *   both ends of the step (locally sixth order; ode45's own continuous extension
+ *   is fourth order), velocities from its derivative.
  * capacity >= 0 points; t_out: device, capacity doubles; y_out: device, 12
  *   planes of capacity doubles (component c of point k at y_out[c*capacity+k]).
  *   Points beyond capacity are counted but not stored.
  * final_state: device, 12 doubles; obs: device, AI_NOBS doubles.
- * *points (host) receives the trajectory's number of points, accepted steps + 1.
+ * *points (host) receives the trajectory's number of points,
+ *   1 + refine * accepted steps.
  * The potential may have any exponents ai_integrate accepts in its plain
  * kernel.  Returns AI_OK, AI_WRTOL or a negative ai_rc. */
 int ai_trace(const ai_params *p, const double *y0, double t0, double tmax, double rtol,
-             double atol, int64_t capacity, double *t_out, double *y_out, double *final_state,
-             double *obs, int64_t *points);
+             double atol, int32_t refine, int64_t capacity, double *t_out, double *y_out,
+             double *final_state, double *obs, int64_t *points);
 
 /* ---- Serving: a stream of integration requests ------------------------------
  *

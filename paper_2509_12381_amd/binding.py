@@ -114,7 +114,7 @@ def load(path: str = LIB_PATH):
                                                  C.c_void_p]
         lib.ai_integrate_batch_async.restype = C.c_int
         lib.ai_trace.argtypes = [_P, _D, C.c_double, C.c_double, C.c_double, C.c_double,
-                                 C.c_int64, _D, _D, _D, _D, C.POINTER(C.c_int64)]
+                                 C.c_int32, C.c_int64, _D, _D, _D, _D, C.POINTER(C.c_int64)]
         lib.ai_trace.restype = C.c_int
         lib.ai_server_create.argtypes = [C.POINTER(AiServerConfig), C.POINTER(C.c_void_p)]
         lib.ai_server_create.restype = C.c_int
@@ -245,11 +245,12 @@ def ai_integrate_batch_async(items, schedule=None, stream=None):
                                                   C.c_void_p(s.cuda_stream)))
 
 
-def ai_trace(system, y0, t0, tmax, rtol, atol, capacity: int):
-    """Replay one trajectory (y0: 12 device doubles) and record its path:
-    returns (t (capacity,), y (12, capacity), final_state (12,), obs (AI_NOBS,),
-    points) with tensors on y0's device; points is the trajectory's number of
-    points (accepted steps + 1), of which the first `capacity` are stored."""
+def ai_trace(system, y0, t0, tmax, rtol, atol, capacity: int, refine: int = 1):
+    """Replay one trajectory (y0: 12 device doubles) and record its path at
+    `refine` points per accepted step: returns (t (capacity,), y (12, capacity),
+    final_state (12,), obs (AI_NOBS,), points) with tensors on y0's device;
+    points is the trajectory's number of points (1 + refine * accepted steps),
+    of which the first `capacity` are stored."""
     import torch
     y = y0.reshape(-1)
     if y.numel() != NSTATE or y.dtype != torch.float64 or not y.is_cuda or not y.is_contiguous():
@@ -262,7 +263,8 @@ def ai_trace(system, y0, t0, tmax, rtol, atol, capacity: int):
     pts = C.c_int64()
     p = system if isinstance(system, AiParams) else params(system)
     _check(load().ai_trace(C.byref(p), C.c_void_p(y.data_ptr()), float(t0), float(tmax),
-                           float(rtol), float(atol), int(capacity), C.c_void_p(t_out.data_ptr()),
+                           float(rtol), float(atol), int(refine), int(capacity),
+                           C.c_void_p(t_out.data_ptr()),
                            C.c_void_p(y_out.data_ptr()), C.c_void_p(fin.data_ptr()),
                            C.c_void_p(obs.data_ptr()), C.byref(pts)))
     return t_out[:capacity], y_out[:, :capacity], fin, obs, pts.value

@@ -1059,13 +1059,16 @@ __global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P) { plain_body<
 __global__ __launch_bounds__(BLOCK) void ai_plain32_kernel(Launch P) { plain_body<float>(P); }
 
 // One trajectory (the lane 0 of one wave) with the ensemble kernels' attempt,
-// recording (t, y) at t0 and after every accepted step: point k at t_out[k]
-// and y_out[c * cap + k], for the first cap points.  Initial state y0[c],
-// final state yf[c] and observables obs[c] are 12 and AI_NOBS consecutive
-// doubles (P.ld = 1).
+// recording (t, y) at t0 and at `refine` points per accepted step, the last at
+// the step's end: point k at t_out[k] and y_out[c * cap + k], for the first
+// cap points.  Points inside a step come from the quintic Hermite interpolant
+// of the positions through (x, v, a) at both ends of the step (a = the
+// first-same-as-last accelerations), velocities from its derivative.  Initial
+// state y0[c], final state yf[c] and observables obs[c] are 12 and AI_NOBS
+// consecutive doubles (P.ld = 1).
 template <class F>
-__device__ __forceinline__ void trace_body(const Launch& P, long long cap, double* t_out,
-                                           double* y_out) {
+__device__ __forceinline__ void trace_body(const Launch& P, int refine, long long cap,
+                                           double* t_out, double* y_out) {
   if (threadIdx.x != 0) return;
   const Ctl K = lane_ctl(P);
   const F Fc = lane_force_of(P, (const F*)nullptr);
@@ -1074,40 +1077,75 @@ __device__ __forceinline__ void trace_body(const Launch& P, long long cap, doubl
   load_column(P, 0, y);
   start(Fc, start_const(P), y, L);
   long long k = 0;
-  auto record = [&]() {
+  auto store = [&](double t, const double* x, const double* v) {
     if (k < cap) {
-      t_out[k] = L.t;
+      t_out[k] = t;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        y_out[c * cap + k] = L.x[c];            // x_ion
-        y_out[(3 + c) * cap + k] = L.v[c];      // v_ion
-        y_out[(6 + c) * cap + k] = L.x[3 + c];  // x_atom
-        y_out[(9 + c) * cap + k] = L.v[3 + c];  // v_atom
+        y_out[c * cap + k] = x[c];            // x_ion
+        y_out[(3 + c) * cap + k] = v[c];      // v_ion
+        y_out[(6 + c) * cap + k] = x[3 + c];  // x_atom
+        y_out[(9 + c) * cap + k] = v[3 + c];  // v_atom
       }
     }
     ++k;
   };
-  record();
+  store(L.t, L.x, L.v);
+  double t0 = L.t, x0[6], v0[6], a0[6];
+  auto keep = [&]() {
+    t0 = L.t;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      x0[c] = L.x[c];
+      v0[c] = L.v[c];
+      a0[c] = L.F1[c];
+    }
+  };
+  keep();
   int seen = 0;
   while (L.status == 0) {
     if (L.fresh) begin_step(K, L);
     attempt(Fc, K, L);
     if (L.nsteps != seen) {
       seen = L.nsteps;
-      record();
+      const double h = L.t - t0;
+      for (int j = 1; j < refine; ++j) {
+        const double u = (double)j / refine, u2 = u * u, u3 = u2 * u, u4 = u3 * u, u5 = u4 * u;
+        const double h0 = 1.0 - 10.0 * u3 + 15.0 * u4 - 6.0 * u5, h3 = 1.0 - h0;
+        const double h1 = u - 6.0 * u3 + 8.0 * u4 - 3.0 * u5;
+        const double h2 = 0.5 * (u2 - 3.0 * u3 + 3.0 * u4 - u5);
+        const double h4 = -4.0 * u3 + 7.0 * u4 - 3.0 * u5;
+        const double h5 = 0.5 * (u3 - 2.0 * u4 + u5);
+        const double d0 = -30.0 * u2 + 60.0 * u3 - 30.0 * u4;  // derivatives in u
+        const double d1 = 1.0 - 18.0 * u2 + 32.0 * u3 - 15.0 * u4;
+        const double d2 = u - 4.5 * u2 + 6.0 * u3 - 2.5 * u4;
+        const double d4 = -12.0 * u2 + 28.0 * u3 - 15.0 * u4;
+        const double d5 = 1.5 * u2 - 4.0 * u3 + 2.5 * u4;
+        double xi[6], vi[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const double dx = L.x[c] - x0[c];
+          xi[c] = x0[c] + h3 * dx + h * (h1 * v0[c] + h4 * L.v[c]) +
+                  h * h * (h2 * a0[c] + h5 * L.F1[c]);
+          vi[c] = (-d0) * dx / h + d1 * v0[c] + d4 * L.v[c] + h * (d2 * a0[c] + d5 * L.F1[c]);
+        }
+        store(t0 + u * h, xi, vi);
+      }
+      store(L.t, L.x, L.v);
+      keep();
     }
   }
   finish(P.yf, P.obs, 1, L, 0, y[9], y[10], y[11]);
 }
 
-__global__ __launch_bounds__(BLOCK) void ai_trace_kernel(Launch P, long long cap, double* t_out,
-                                                         double* y_out) {
-  trace_body<Force>(P, cap, t_out, y_out);
+__global__ __launch_bounds__(BLOCK) void ai_trace_kernel(Launch P, int refine, long long cap,
+                                                         double* t_out, double* y_out) {
+  trace_body<Force>(P, refine, cap, t_out, y_out);
 }
 
-__global__ __launch_bounds__(BLOCK) void ai_trace_nm_kernel(Launch P, long long cap,
+__global__ __launch_bounds__(BLOCK) void ai_trace_nm_kernel(Launch P, int refine, long long cap,
                                                             double* t_out, double* y_out) {
-  trace_body<ForceNM>(P, cap, t_out, y_out);
+  trace_body<ForceNM>(P, refine, cap, t_out, y_out);
 }
 
 // The same for potentials with exponents other than n = 4, m = 8.
@@ -1661,11 +1699,12 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
 }
 
 int ai_trace(const ai_params* p, const double* y0, double t0, double tmax, double rtol,
-             double atol, int64_t capacity, double* t_out, double* y_out, double* final_state,
-             double* obs, int64_t* points) {
+             double atol, int32_t refine, int64_t capacity, double* t_out, double* y_out,
+             double* final_state, double* obs, int64_t* points) {
   g_error.clear();
   if (!points) return fail(AI_EINVAL, "points is NULL");
   *points = 0;
+  if (refine < 1 || refine > 1024) return fail(AI_EINVAL, "refine = %d not in 1 .. 1024", refine);
   if (capacity < 0) return fail(AI_EINVAL, "capacity = %lld < 0", (long long)capacity);
   if (capacity > 0 && (!t_out || !y_out)) return fail(AI_EINVAL, "NULL point buffer");
   if (capacity > (int64_t)(INT64_MAX / 8 / 16)) return fail(AI_EINVAL, "capacity too large");
@@ -1696,10 +1735,10 @@ int ai_trace(const ai_params* p, const double* y0, double t0, double tmax, doubl
   P.yf = final_state;
   P.obs = obs;
   if (p->n != 4 || p->m != 8)
-    hipLaunchKernelGGL(ai_trace_nm_kernel, dim3(1), dim3(BLOCK), 0, nullptr, P,
+    hipLaunchKernelGGL(ai_trace_nm_kernel, dim3(1), dim3(BLOCK), 0, nullptr, P, (int)refine,
                        (long long)capacity, t_out, y_out);
   else
-    hipLaunchKernelGGL(ai_trace_kernel, dim3(1), dim3(BLOCK), 0, nullptr, P,
+    hipLaunchKernelGGL(ai_trace_kernel, dim3(1), dim3(BLOCK), 0, nullptr, P, (int)refine,
                        (long long)capacity, t_out, y_out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "launch(trace)");
@@ -1708,7 +1747,7 @@ int ai_trace(const ai_params* p, const double* y0, double t0, double tmax, doubl
   double nsteps = 0.0;
   e = hipMemcpy(&nsteps, obs + AI_OBS_NSTEPS, sizeof nsteps, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(nsteps)");
-  *points = (int64_t)nsteps + 1;
+  *points = (int64_t)nsteps * refine + 1;
   return warn;
 }
 

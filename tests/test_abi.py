@@ -83,19 +83,21 @@ def test_struct_layout_against_the_c_compiler(tmp_path):
 
 
 def test_trace_argument_errors_without_gpu(lib):
-    """ai_trace refuses a NULL point count, a negative capacity and missing
-    point buffers before any device call."""
+    """ai_trace refuses a NULL point count, a negative capacity, refine < 1 and
+    missing point buffers before any device call."""
     from paper_2509_12381_amd import binding, workload as W
     L = binding.load()
     p = binding.params(W.small_ensemble().system)
     pts = ctypes.c_int64(7)
-    assert L.ai_trace(ctypes.byref(p), None, 0.0, 1.0, 1e-8, 1e-10, 0, None, None, None, None,
-                      None) == binding.EINVAL
-    assert L.ai_trace(ctypes.byref(p), None, 0.0, 1.0, 1e-8, 1e-10, -1, None, None, None, None,
-                      ctypes.byref(pts)) == binding.EINVAL
+    assert L.ai_trace(ctypes.byref(p), None, 0.0, 1.0, 1e-8, 1e-10, 1, 0, None, None, None,
+                      None, None) == binding.EINVAL
+    assert L.ai_trace(ctypes.byref(p), None, 0.0, 1.0, 1e-8, 1e-10, 1, -1, None, None, None,
+                      None, ctypes.byref(pts)) == binding.EINVAL
     assert pts.value == 0
-    assert L.ai_trace(ctypes.byref(p), None, 0.0, 1.0, 1e-8, 1e-10, 5, None, None, None, None,
-                      ctypes.byref(pts)) == binding.EINVAL
+    assert L.ai_trace(ctypes.byref(p), None, 0.0, 1.0, 1e-8, 1e-10, 0, 5, None, None, None,
+                      None, ctypes.byref(pts)) == binding.EINVAL
+    assert L.ai_trace(ctypes.byref(p), None, 0.0, 1.0, 1e-8, 1e-10, 1, 5, None, None, None,
+                      None, ctypes.byref(pts)) == binding.EINVAL
     assert b"point buffer" in L.ai_last_error()
 
 

@@ -792,3 +792,36 @@ def test_unscheduled_plain_call_replays_from_a_graph(ai, torch):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(fin.cpu().numpy(), ref_f)
         np.testing.assert_array_equal(obs.cpu().numpy(), ref_o)
+
+
+def test_trace_refine_follows_closed_form(ai, torch):
+    """refine = 4 (ode45's default number of output points per step): with the
+    atom-ion interaction off and a static harmonic trap, the ion oscillates as
+    x0 cos wt + (v0/w) sin wt per axis and the atom flies straight; every
+    recorded point, interpolated or not, follows that within 1e-8 of the motion's
+    scale, and every fourth point is bitwise the refine = 1 trace."""
+    import dataclasses
+    wl = W.small_ensemble()
+    s = wl.system
+    a = (0.02, 0.03, 0.05)
+    system = dataclasses.replace(s, Cn=0.0, Cm=0.0, a=a, q=(0.0, 0.0, 0.0), r_exit=0.0)
+    y0 = wl.initial_states()[:, 17].copy()
+    yi = torch.from_numpy(y0).cuda()
+    tmax = W.rf_periods(system, 40.0)
+    t1, y1, f1, o1, p1 = ai.ai_trace(system, yi, 0.0, tmax, 1e-10, 1e-20, 10**6)
+    t4, y4, f4, o4, p4 = ai.ai_trace(system, yi, 0.0, tmax, 1e-10, 1e-20, 10**6, refine=4)
+    t1, y1, t4, y4 = (x.cpu().numpy() for x in (t1, y1, t4, y4))
+    assert p4 == 4 * (p1 - 1) + 1
+    np.testing.assert_array_equal(t4[:p4:4], t1[:p1])
+    np.testing.assert_array_equal(y4[:, :p4:4], y1[:, :p1])
+    np.testing.assert_array_equal(f4.cpu().numpy(), f1.cpu().numpy())
+    t = t4[:p4]
+    w = np.sqrt(np.array(a)) * abs(system.omega_rf) / 2.0
+    xi = y0[0:3, None] * np.cos(w[:, None] * t) + (y0[3:6] / w)[:, None] * np.sin(w[:, None] * t)
+    vi = -y0[0:3, None] * w[:, None] * np.sin(w[:, None] * t) + y0[3:6, None] * np.cos(w[:, None] * t)
+    xa = y0[6:9, None] + y0[9:12, None] * t
+    amp = np.sqrt(y0[0:3] ** 2 + (y0[3:6] / w) ** 2)
+    assert np.max(np.abs(y4[0:3, :p4] - xi) / amp[:, None]) < 1e-8
+    assert np.max(np.abs(y4[3:6, :p4] - vi) / (amp * w)[:, None]) < 1e-8
+    assert np.max(np.abs(y4[6:9, :p4] - xa)) / np.abs(xa).max() < 1e-10
+    assert np.all(np.diff(t) > 0)
