@@ -344,6 +344,16 @@ def main() -> int:
                 other.append({"kernel": "persistent", "schedule": "longest-first",
                               "refill_min": k_, "ms_per_step": o_total / 3})
 
+    tuned = None
+    if not args.no_compare:
+        t_fin = torch.empty_like(y0)
+        t_obs = torch.empty_like(obs)
+        best, best_ms = binding.ai_tune(wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol,
+                                        t_fin, t_obs)
+        tuned = {"best_kernel_code": best, "best_ms": best_ms,
+                 "what": "ai_tune: each configuration run once on this ensemble"}
+        del t_fin, t_obs
+
     batched = None
     if not args.no_batch and args.n is None:
         batched = batched_grid(binding, W, flops, torch)
@@ -388,6 +398,7 @@ def main() -> int:
                      "flop_per_launch": flop, "launch_ms": launch_ms},
         "kernel_info": info,
         "other_variants": other,
+        "autotune": tuned,
         "batched_grid": batched,
         "serving": served,
         "cpu_baseline": cpu,

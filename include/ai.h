@@ -150,6 +150,21 @@ int ai_integrate_async(const ai_params *p, const double *y0, int64_t n, int64_t 
                        double tmax, double rtol, double atol, double *final_state, double *obs,
                        int32_t kernel, void *stream);
 
+/* Choose the fastest kernel configuration for an ensemble by running it: the
+ * ensemble is integrated once with each of AI_KERNEL_PLAIN,
+ * AI_KERNEL_PLAIN | AI_SCHEDULE_LONGEST_FIRST and AI_KERNEL_PERSISTENT |
+ * AI_SCHEDULE_LONGEST_FIRST | AI_REFILL_MIN(k) for k = 1, 16, 64 (plain only
+ * for exponents other than n=4, m=8), timed with HIP events on the null
+ * stream.  Every configuration gives bitwise the same results, so the outputs
+ * hold the ensemble's results afterwards, as after ai_integrate.  Arguments as
+ * for ai_integrate, except that final_state must not be y0 (the ensemble runs
+ * several times).  *best_kernel (host) receives the fastest configuration, to
+ * pass as `kernel` to later calls on similar ensembles, *best_ms (host) its
+ * time.  Blocks until done; returns AI_OK, AI_WRTOL or a negative ai_rc. */
+int ai_tune(const ai_params *p, const double *y0, int64_t n, int64_t ld, double t0,
+            double tmax, double rtol, double atol, double *final_state, double *obs,
+            int32_t *best_kernel, float *best_ms);
+
 /* One ensemble of a batched call: its system, buffers, span and tolerances,
  * each with the meaning and constraints it has in ai_integrate. */
 typedef struct ai_batch_item {

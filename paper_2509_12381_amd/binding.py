@@ -26,7 +26,7 @@ OK, WRTOL, EINVAL, EHIP, ENOMEM, EUNSUPPORTED, EAGAIN = 0, 1, -1, -2, -3, -4, -5
 
 # exported symbols of the C ABI, in declaration order
 SYMBOLS = ("ai_integrate", "ai_integrate_async", "ai_integrate_batch",
-           "ai_integrate_batch_async", "ai_trace", "ai_server_create", "ai_server_submit", "ai_server_wait",
+           "ai_integrate_batch_async", "ai_tune", "ai_trace", "ai_server_create", "ai_server_submit", "ai_server_wait",
            "ai_server_destroy", "ai_get_kernel_info", "ai_last_error", "ai_nobs", "ai_version")
 
 
@@ -113,6 +113,8 @@ def load(path: str = LIB_PATH):
         lib.ai_integrate_batch_async.argtypes = [C.POINTER(AiBatchItem), C.c_int32, C.c_int32,
                                                  C.c_void_p]
         lib.ai_integrate_batch_async.restype = C.c_int
+        lib.ai_tune.argtypes = args[:-1] + [C.POINTER(C.c_int32), C.POINTER(C.c_float)]
+        lib.ai_tune.restype = C.c_int
         lib.ai_trace.argtypes = [_P, _D, C.c_double, C.c_double, C.c_double, C.c_double,
                                  C.c_int32, C.c_int64, _D, _D, _D, _D, C.POINTER(C.c_int64)]
         lib.ai_trace.restype = C.c_int
@@ -243,6 +245,15 @@ def ai_integrate_batch_async(items, schedule=None, stream=None):
     arr = batch_items(items)
     return _check(load().ai_integrate_batch_async(arr, len(items), SCHEDULES[schedule],
                                                   C.c_void_p(s.cuda_stream)))
+
+
+def ai_tune(system, y0, t0, tmax, rtol, atol, final_state, obs, n=None):
+    """ai_tune: time the kernel configurations on this ensemble (the outputs
+    hold its results afterwards); returns (best kernel code, its ms)."""
+    best, ms = C.c_int32(), C.c_float()
+    a = _args(system, y0, n, t0, tmax, rtol, atol, final_state, obs, 0)[:-1]
+    _check(load().ai_tune(*a, C.byref(best), C.byref(ms)))
+    return best.value, ms.value
 
 
 def ai_trace(system, y0, t0, tmax, rtol, atol, capacity: int, refine: int = 1):

@@ -1751,6 +1751,55 @@ int ai_trace(const ai_params* p, const double* y0, double t0, double tmax, doubl
   return warn;
 }
 
+int ai_tune(const ai_params* p, const double* y0, int64_t n, int64_t ld, double t0,
+            double tmax, double rtol, double atol, double* final_state, double* obs,
+            int32_t* best_kernel, float* best_ms) {
+  g_error.clear();
+  if (!best_kernel || !best_ms) return fail(AI_EINVAL, "best_kernel or best_ms is NULL");
+  *best_kernel = AI_KERNEL_PLAIN;
+  *best_ms = 0.0f;
+  if (final_state == y0 && n > 0)
+    return fail(AI_EINVAL, "tuning runs the ensemble several times: final_state must not be y0");
+  const bool general = p && (p->n != 4 || p->m != 8);
+  const int32_t candidates[] = {
+      AI_KERNEL_PLAIN,
+      AI_KERNEL_PLAIN | AI_SCHEDULE_LONGEST_FIRST,
+      AI_KERNEL_PERSISTENT | AI_SCHEDULE_LONGEST_FIRST | AI_REFILL_MIN(1),
+      AI_KERNEL_PERSISTENT | AI_SCHEDULE_LONGEST_FIRST | AI_REFILL_MIN(16),
+      AI_KERNEL_PERSISTENT | AI_SCHEDULE_LONGEST_FIRST | AI_REFILL_MIN(64)};
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e;
+  if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return hip_fail(e, "hipEventCreate");
+  }
+  int rc = AI_OK, warn = AI_OK;
+  float best = -1.0f;
+  for (int32_t k : candidates) {
+    if (general && (k & 0xf) != AI_KERNEL_PLAIN) continue;  // other exponents: plain only
+    (void)hipEventRecord(a, nullptr);
+    rc = ai_integrate_async(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs, k, nullptr);
+    if (rc < 0) break;
+    warn = rc;
+    (void)hipEventRecord(b, nullptr);
+    if ((e = hipEventSynchronize(b)) != hipSuccess) {
+      rc = hip_fail(e, "hipEventSynchronize");
+      break;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (best < 0.0f || ms < best) {
+      best = ms;
+      *best_kernel = k;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc < 0) return rc;
+  *best_ms = best < 0.0f ? 0.0f : best;
+  return warn;
+}
+
 int ai_integrate(const ai_params* p, const double* y0, int64_t n, int64_t ld, double t0,
                  double tmax, double rtol, double atol, double* final_state, double* obs,
                  int32_t kernel) {

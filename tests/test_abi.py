@@ -27,7 +27,8 @@ def lib():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     assert names == sorted(["ai_integrate", "ai_integrate_async", "ai_integrate_batch",
-                            "ai_integrate_batch_async", "ai_trace", "ai_server_create",
+                            "ai_integrate_batch_async", "ai_tune", "ai_trace",
+                            "ai_server_create",
                             "ai_server_submit",
                             "ai_server_wait", "ai_server_destroy", "ai_get_kernel_info",
                             "ai_last_error", "ai_nobs", "ai_version"])

@@ -825,3 +825,31 @@ def test_trace_refine_follows_closed_form(ai, torch):
     assert np.max(np.abs(y4[3:6, :p4] - vi) / (amp * w)[:, None]) < 1e-8
     assert np.max(np.abs(y4[6:9, :p4] - xa)) / np.abs(xa).max() < 1e-10
     assert np.all(np.diff(t) > 0)
+
+
+def test_tune_picks_a_configuration_and_leaves_the_results(ai, torch):
+    """ai_tune times the configurations on the ensemble itself; afterwards the
+    outputs are bitwise the results of ai_integrate, the returned code is one of
+    the candidates (plain-only for other exponents), and in-place outputs are
+    refused."""
+    import dataclasses
+    wl = W.full_ensemble()
+    y0 = wl.initial_states(16384)
+    ref_f, ref_o, _ = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
+    d = torch.from_numpy(y0).cuda()
+    fin = torch.full_like(d, -7.0)
+    obs = torch.full((13, d.shape[1]), -7.0, dtype=torch.float64, device="cuda")
+    best, ms = ai.ai_tune(wl.system, d, wl.t0, wl.tmax, wl.rtol, wl.atol, fin, obs)
+    torch.cuda.synchronize()
+    assert best in (0, 16, 16 | 1 | (1 << 8), 16 | 1 | (16 << 8), 16 | 1 | (64 << 8))
+    assert ms > 0
+    np.testing.assert_array_equal(fin.cpu().numpy(), ref_f)
+    np.testing.assert_array_equal(obs.cpu().numpy(), ref_o)
+    cn, cm = _potential(6, 12)
+    system = dataclasses.replace(wl.system, n=6, m=12, Cn=cn, Cm=cm)
+    best, _ = ai.ai_tune(system, d[:, :1024].contiguous(), wl.t0, wl.tmax, wl.rtol, wl.atol,
+                         fin[:, :1024].contiguous(), obs[:, :1024].contiguous())
+    assert best & 0xf == 0
+    with pytest.raises(ai.AiError) as e:
+        ai.ai_tune(wl.system, d, wl.t0, wl.tmax, wl.rtol, wl.atol, d, obs)
+    assert e.value.rc == ai.EINVAL
