@@ -518,15 +518,17 @@ def _check_distributions(tag, wl, gob, ofull):
 
 def test_full_ensemble_sampled_and_distributions(ai, torch, aio, oracle_full):
     """2^20 trajectories in the launch configuration the benchmark times
-    (persistent kernel): per-trajectory parity on a seeded sample, and the
-    ensemble's complex probability and angle/lifetime distributions against
-    the oracle's full ensemble."""
+    (plain kernel, longest-first schedule): per-trajectory parity on a seeded
+    sample, the ensemble's complex probability and angle/lifetime distributions
+    against the oracle's full ensemble, and bitwise equality with the
+    persistent kernel."""
     wl, y0, _, ofull = oracle_full
     gfin, gob, grc = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol,
-                             "persistent", schedule="longest-first")
+                             "plain", schedule="longest-first")
     assert grc == 0
     assert np.all(gob[O["status"]] >= 1) and np.all(gob[O["status"]] <= 5)
-    pfin, pob, _ = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "plain")
+    pfin, pob, _ = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol,
+                           "persistent", schedule="longest-first")
     np.testing.assert_array_equal(gfin, pfin)
     np.testing.assert_array_equal(gob, pob)
     rng = np.random.default_rng(123)
@@ -681,10 +683,12 @@ def test_batch_oracle_parity(ai, torch, aio):
         assert rel.max() <= 1e-6 and same >= 0.99
 
 
-def test_batch_full_grid_runs(ai, torch):
+def test_batch_full_grid_runs(ai, torch, aio):
     """All 64 ensembles of the batched configuration (3.2 M trajectories) in
-    one launch: every trajectory ends with a status, and the Mathieu-unstable
-    ensembles (q >= 0.5) end by escape."""
+    the launch the benchmark times (one longest-first batched launch): every
+    trajectory ends with a status, the Mathieu-unstable ensembles (q >= 0.5) end
+    by escape, and 8 seeded samples of every ensemble match the oracle (1e-6 on
+    the non-chaotic ones, statuses on 99%)."""
     grid = W.batch_grid()
     dev = []
     for wl in grid:
@@ -699,6 +703,21 @@ def test_batch_full_grid_runs(ai, torch):
         assert np.all((st >= 1) & (st <= 5)), wl.name
         if W.BATCH_Q[k % len(W.BATCH_Q)] >= 0.5:
             assert np.mean(st == W.ST_ESCAPED) > 0.99, wl.name
+    rng = np.random.default_rng(64)
+    rels, calms, same_status = [], [], []
+    for wl, d, f, o in dev:
+        idx = np.sort(rng.choice(wl.n, min(8, wl.n), replace=False))
+        y = d.cpu().numpy()[:, idx]
+        gfin, gob = f.cpu().numpy()[:, idx], o.cpu().numpy()[:, idx]
+        ofin, oob, _ = run_oracle(aio, wl.system, y, wl.t0, wl.tmax, wl.rtol, wl.atol)
+        calm, _ = non_chaotic(aio, wl.system, y, wl.t0, wl.tmax, wl.rtol, wl.atol, ofin, oob)
+        aligned = aligned_oracle_state(aio, wl.system, ofin, oob, gob)
+        rels.append(S.block_relative_difference(gfin, aligned)[calm])
+        calms.append(calm)
+        same_status.append(gob[O["status"]] == oob[O["status"]])
+    assert np.concatenate(calms).mean() > 0.9
+    assert np.concatenate(rels).max() <= 1e-6
+    assert np.concatenate(same_status).mean() >= 0.99
 
 
 def test_trace_replays_ensemble_trajectories(ai, torch):
