@@ -96,7 +96,13 @@ enum ai_kernel {
    * formed in double before narrowing.  Results differ from the double
    * kernels by the single-precision rounding of the stage arithmetic (each
    * observable's difference is stated with the tests). */
-  AI_FP32_STAGES = 32
+  AI_FP32_STAGES = 32,
+  /* flag, any kernel and ai_integrate_batch[_async]: record HIP events on the
+   * call's stream right before and after its integration kernel (schedule,
+   * sort and observable kernels excluded); ai_kernel_time() returns that
+   * duration once the stream has reached it.  The events belong to the calling
+   * thread, which keeps its last 64 such calls. */
+  AI_TIME_KERNEL = 64
 };
 
 /* Persistent kernel only, OR-ed into the kernel argument: a wave draws new
@@ -286,6 +292,14 @@ int ai_server_wait(ai_server *srv, uint64_t ticket, double timeout_s, ai_request
  * Requests not yet waited for are forgotten (their outputs are complete).  No
  * other call on the server may be in progress or follow. */
 int ai_server_destroy(ai_server *srv);
+
+/* The duration in milliseconds of the integration kernel of one of the calling
+ * thread's calls made with AI_TIME_KERNEL: back = 0 for the last such call, 1
+ * for the one before, ... up to 63 (the last 64 are kept), so calls can run
+ * back to back and be read afterwards.  Returns AI_OK, AI_EAGAIN if the
+ * stream has not reached that kernel's end yet, AI_EINVAL if there is no such
+ * call (or ms is NULL), AI_EHIP. */
+int ai_kernel_time(int32_t back, float *ms);
 
 /* Launch facts of one kernel on the current device. */
 typedef struct ai_kernel_info {

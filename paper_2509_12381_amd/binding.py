@@ -22,12 +22,14 @@ SCHEDULE_LONGEST_FIRST = 16
 SCHEDULES = {None: 0, "index": 0, "longest-first": SCHEDULE_LONGEST_FIRST}
 FP32_STAGES = 32                      # AI_FP32_STAGES
 PRECISIONS = {"fp64": 0, "fp32-stages": FP32_STAGES}
+TIME_KERNEL = 64                      # AI_TIME_KERNEL
 OK, WRTOL, EINVAL, EHIP, ENOMEM, EUNSUPPORTED, EAGAIN = 0, 1, -1, -2, -3, -4, -5
 
 # exported symbols of the C ABI, in declaration order
 SYMBOLS = ("ai_integrate", "ai_integrate_async", "ai_integrate_batch",
            "ai_integrate_batch_async", "ai_tune", "ai_trace", "ai_server_create", "ai_server_submit", "ai_server_wait",
-           "ai_server_destroy", "ai_get_kernel_info", "ai_last_error", "ai_nobs", "ai_version")
+           "ai_server_destroy", "ai_kernel_time", "ai_get_kernel_info", "ai_last_error",
+           "ai_nobs", "ai_version")
 
 
 class AiParams(C.Structure):
@@ -128,6 +130,8 @@ def load(path: str = LIB_PATH):
         lib.ai_server_wait.restype = C.c_int
         lib.ai_server_destroy.argtypes = [C.c_void_p]
         lib.ai_server_destroy.restype = C.c_int
+        lib.ai_kernel_time.argtypes = [C.c_int32, C.POINTER(C.c_float)]
+        lib.ai_kernel_time.restype = C.c_int
         lib.ai_get_kernel_info.argtypes = [C.c_int32, C.POINTER(AiKernelInfo)]
         lib.ai_get_kernel_info.restype = C.c_int
         lib.ai_last_error.restype = C.c_char_p
@@ -238,13 +242,27 @@ def ai_integrate_batch(items, schedule=None):
     return _check(load().ai_integrate_batch(arr, len(items), SCHEDULES[schedule]))
 
 
-def ai_integrate_batch_async(items, schedule=None, stream=None):
-    """ai_integrate_batch_async on `stream` (default: torch's current stream)."""
+def ai_integrate_batch_async(items, schedule=None, stream=None, time_kernel=False):
+    """ai_integrate_batch_async on `stream` (default: torch's current stream);
+    time_kernel adds AI_TIME_KERNEL."""
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
     arr = batch_items(items)
-    return _check(load().ai_integrate_batch_async(arr, len(items), SCHEDULES[schedule],
+    k = SCHEDULES[schedule] | (TIME_KERNEL if time_kernel else 0)
+    return _check(load().ai_integrate_batch_async(arr, len(items), k,
                                                   C.c_void_p(s.cuda_stream)))
+
+
+def ai_kernel_time(back: int = 0):
+    """Milliseconds of the integration kernel of this thread's call made with
+    AI_TIME_KERNEL `back` calls ago (0: the last; the last 64 are kept), or None
+    if its stream has not reached the kernel's end."""
+    ms = C.c_float()
+    rc = load().ai_kernel_time(int(back), C.byref(ms))
+    if rc == EAGAIN:
+        return None
+    _check(rc)
+    return ms.value
 
 
 def ai_tune(system, y0, t0, tmax, rtol, atol, final_state, obs, n=None):

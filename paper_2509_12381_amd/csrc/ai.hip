@@ -1427,7 +1427,8 @@ int validate(const ai_params* p, const double* y0, int64_t n, int64_t ld, double
   if (ld < n) return fail(AI_EINVAL, "ld = %lld < n = %lld", (long long)ld, (long long)n);
   const int32_t base_kernel = kernel & 0xf;
   if ((base_kernel != AI_KERNEL_PLAIN && base_kernel != AI_KERNEL_PERSISTENT) ||
-      (kernel & ~(0xf | AI_SCHEDULE_LONGEST_FIRST | AI_FP32_STAGES | (0x7f << 8))) != 0 ||
+      (kernel & ~(0xf | AI_SCHEDULE_LONGEST_FIRST | AI_FP32_STAGES | AI_TIME_KERNEL |
+                  (0x7f << 8))) != 0 ||
       ((kernel >> 8) & 0x7f) > 64)
     return fail(AI_EINVAL, "unknown kernel argument 0x%x", (unsigned)kernel);
   if ((kernel & AI_FP32_STAGES) && base_kernel != AI_KERNEL_PLAIN)
@@ -1525,6 +1526,53 @@ Launch launch_constants(const ai_params* p, int64_t n, int64_t ld, double t0, do
   P.key = nullptr;
   P.queue = nullptr;
   return P;
+}
+
+// AI_TIME_KERNEL: per thread, a ring of start/stop event pairs recorded around
+// the integration kernels of its last AI_TIMER_RING calls with the flag.
+constexpr int AI_TIMER_RING = 64;
+struct KernelTimer {
+  int device = -1;
+  hipEvent_t start[AI_TIMER_RING] = {}, stop[AI_TIMER_RING] = {};
+  int next = 0;        // slot of the next call
+  long long count = 0; // calls recorded
+};
+thread_local KernelTimer g_timer;
+
+hipError_t timer_events(KernelTimer& T) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (T.device != dev) {
+    for (int i = 0; i < AI_TIMER_RING; ++i) {
+      if (T.start[i]) (void)hipEventDestroy(T.start[i]);
+      if (T.stop[i]) (void)hipEventDestroy(T.stop[i]);
+      T.start[i] = T.stop[i] = nullptr;
+    }
+    T.next = 0;
+    T.count = 0;
+    T.device = -1;
+    for (int i = 0; i < AI_TIMER_RING; ++i) {
+      if ((e = hipEventCreate(&T.start[i])) != hipSuccess) return e;
+      if ((e = hipEventCreate(&T.stop[i])) != hipSuccess) return e;
+    }
+    T.device = dev;
+  }
+  return hipSuccess;
+}
+
+// Record the start (or stop) event of the integration kernel on s if asked.
+int time_mark(int32_t kernel, bool start, hipStream_t s) {
+  if (!(kernel & AI_TIME_KERNEL)) return AI_OK;
+  hipError_t e = timer_events(g_timer);
+  if (e == hipSuccess)
+    e = hipEventRecord(start ? g_timer.start[g_timer.next] : g_timer.stop[g_timer.next], s);
+  if (e != hipSuccess) return hip_fail(e, "kernel timing event");
+  if (!start) {
+    g_timer.next = (g_timer.next + 1) % AI_TIMER_RING;
+    g_timer.count += 1;
+  }
+  return AI_OK;
 }
 
 ai_order_model order_model(const ai_params* p, double t0, double tmax, double rtol, bool sampled) {
@@ -1653,6 +1701,10 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
       release();
       return fail(AI_EINVAL, "n too large for one launch");
     }
+    if ((rc = time_mark(kernel, true, s)) != AI_OK) {
+      release();
+      return rc;
+    }
     if (kernel & AI_FP32_STAGES)
       hipLaunchKernelGGL(ai_plain32_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
     else if (p->n != 4 || p->m != 8)
@@ -1662,6 +1714,10 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
     if ((e = hipGetLastError()) != hipSuccess) {
       release();
       return hip_fail(e, "launch(plain)");
+    }
+    if ((rc = time_mark(kernel, false, s)) != AI_OK) {
+      release();
+      return rc;
     }
     return conclude();
   }
@@ -1685,11 +1741,21 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
     return hip_fail(e, "launch(queue reset)");
   }
   P.queue = queue;
+  if ((rc = time_mark(kernel, true, s)) != AI_OK) {
+    (void)hipFreeAsync(queue, s);
+    release();
+    return rc;
+  }
   hipLaunchKernelGGL(ai_persistent_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
   if ((e = hipGetLastError()) != hipSuccess) {
     (void)hipFreeAsync(queue, s);
     release();
     return hip_fail(e, "launch(persistent)");
+  }
+  if ((rc = time_mark(kernel, false, s)) != AI_OK) {
+    (void)hipFreeAsync(queue, s);
+    release();
+    return rc;
   }
   if ((e = hipFreeAsync(queue, s)) != hipSuccess) {
     release();
@@ -1749,6 +1815,19 @@ int ai_trace(const ai_params* p, const double* y0, double t0, double tmax, doubl
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(nsteps)");
   *points = (int64_t)nsteps * refine + 1;
   return warn;
+}
+
+int ai_kernel_time(int32_t back, float* ms) {
+  g_error.clear();
+  if (!ms) return fail(AI_EINVAL, "ms is NULL");
+  *ms = 0.0f;
+  if (back < 0 || back >= AI_TIMER_RING || back >= g_timer.count)
+    return fail(AI_EINVAL, "no timed call %d back on this thread (%lld recorded, at most %d kept)",
+                back, g_timer.count, AI_TIMER_RING);
+  const int slot = ((g_timer.next - 1 - back) % AI_TIMER_RING + AI_TIMER_RING) % AI_TIMER_RING;
+  const hipError_t e = hipEventElapsedTime(ms, g_timer.start[slot], g_timer.stop[slot]);
+  if (e == hipErrorNotReady) return AI_EAGAIN;
+  return e == hipSuccess ? AI_OK : hip_fail(e, "hipEventElapsedTime");
 }
 
 int ai_tune(const ai_params* p, const double* y0, int64_t n, int64_t ld, double t0,
@@ -1816,7 +1895,7 @@ int ai_integrate_batch_async(const ai_batch_item* items, int32_t count, int32_t 
   g_error.clear();
   if (count < 0) return fail(AI_EINVAL, "count = %d < 0", count);
   if (count > 0 && !items) return fail(AI_EINVAL, "items is NULL");
-  if ((kernel & ~AI_SCHEDULE_LONGEST_FIRST) != AI_KERNEL_PLAIN)
+  if ((kernel & ~(AI_SCHEDULE_LONGEST_FIRST | AI_TIME_KERNEL)) != AI_KERNEL_PLAIN)
     return fail(AI_EUNSUPPORTED, "a batch runs the plain double kernel (kernel 0x%x)",
                 (unsigned)kernel);
   int warn = AI_OK;
@@ -1910,11 +1989,20 @@ int ai_integrate_batch_async(const ai_batch_item* items, int32_t count, int32_t 
     B.order = order;
     B.key = key;
   }
+  int trc = time_mark(kernel, true, s);
+  if (trc != AI_OK) {
+    release();
+    return trc;
+  }
   hipLaunchKernelGGL(ai_plain_batch_kernel, dim3((unsigned)((total + BLOCK - 1) / BLOCK)),
                      dim3(BLOCK), 0, s, B);
   if ((e = hipGetLastError()) != hipSuccess) {
     release();
     return hip_fail(e, "launch(batch)");
+  }
+  if ((trc = time_mark(kernel, false, s)) != AI_OK) {
+    release();
+    return trc;
   }
   hipLaunchKernelGGL(ai_finalize_batch_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
                      0, s, B);

@@ -30,7 +30,8 @@ def test_header_declares_the_entry_points():
                             "ai_integrate_batch_async", "ai_tune", "ai_trace",
                             "ai_server_create",
                             "ai_server_submit",
-                            "ai_server_wait", "ai_server_destroy", "ai_get_kernel_info",
+                            "ai_server_wait", "ai_server_destroy", "ai_kernel_time",
+                            "ai_get_kernel_info",
                             "ai_last_error", "ai_nobs", "ai_version"])
 
 
@@ -100,6 +101,28 @@ def test_trace_argument_errors_without_gpu(lib):
     assert L.ai_trace(ctypes.byref(p), None, 0.0, 1.0, 1e-8, 1e-10, 1, 5, None, None, None,
                       None, ctypes.byref(pts)) == binding.EINVAL
     assert b"point buffer" in L.ai_last_error()
+
+
+def test_kernel_time_without_a_timed_call(lib):
+    """The timing record is per thread: a thread that made no call with
+    AI_TIME_KERNEL gets AI_EINVAL (checked on a fresh thread, whatever other
+    tests in this process have done)."""
+    import threading
+    from paper_2509_12381_amd import binding
+    L = binding.load()
+    out = {}
+
+    def probe():
+        ms = ctypes.c_float(1.0)
+        out["null"] = L.ai_kernel_time(0, None)
+        out["rc"] = L.ai_kernel_time(0, ctypes.byref(ms))
+        out["ms"] = ms.value
+
+    t = threading.Thread(target=probe)
+    t.start()
+    t.join()
+    assert out["null"] == binding.EINVAL
+    assert out["rc"] == binding.EINVAL and out["ms"] == 0.0
 
 
 def test_server_argument_errors_without_gpu(lib):

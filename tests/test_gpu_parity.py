@@ -872,3 +872,39 @@ def test_tune_picks_a_configuration_and_leaves_the_results(ai, torch):
     with pytest.raises(ai.AiError) as e:
         ai.ai_tune(wl.system, d, wl.t0, wl.tmax, wl.rtol, wl.atol, d, obs)
     assert e.value.rc == ai.EINVAL
+
+
+def test_kernel_timing_flag(ai, torch):
+    """AI_TIME_KERNEL changes no result and times the integration kernel alone:
+    positive, below the whole call's time (single call and batch)."""
+    wl = W.full_ensemble()
+    y0 = wl.initial_states(65536)
+    ref_f, ref_o, _ = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol,
+                              schedule="longest-first")
+    d = torch.from_numpy(y0).cuda()
+    f = torch.empty_like(d)
+    o = torch.empty((13, d.shape[1]), dtype=torch.float64, device="cuda")
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    ai.ai_integrate_async(wl.system, d, wl.t0, wl.tmax, wl.rtol, wl.atol, f, o,
+                          ai.KERNELS["plain"] | ai.TIME_KERNEL, schedule="longest-first")
+    b.record()
+    torch.cuda.synchronize()
+    k = ai.ai_kernel_time()
+    assert 0.0 < k <= a.elapsed_time(b)
+    np.testing.assert_array_equal(f.cpu().numpy(), ref_f)
+    np.testing.assert_array_equal(o.cpu().numpy(), ref_o)
+    items = [(wl.system, d, f, o, wl.t0, wl.tmax, wl.rtol, wl.atol)]
+    ai.ai_integrate_batch_async(items, schedule="longest-first", time_kernel=True)
+    torch.cuda.synchronize()
+    assert 0.0 < ai.ai_kernel_time() <= 1.5 * a.elapsed_time(b)
+    np.testing.assert_array_equal(f.cpu().numpy(), ref_f)
+    # back-to-back calls read afterwards, newest first
+    for _ in range(3):
+        ai.ai_integrate_async(wl.system, d, wl.t0, wl.tmax, wl.rtol, wl.atol, f, o,
+                              ai.KERNELS["plain"] | ai.TIME_KERNEL, schedule="longest-first")
+    torch.cuda.synchronize()
+    times = [ai.ai_kernel_time(back) for back in range(5)]
+    assert all(t > 0.0 for t in times)
+    with pytest.raises(ai.AiError):
+        ai.ai_kernel_time(64)
