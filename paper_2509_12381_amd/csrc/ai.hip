@@ -1854,24 +1854,26 @@ int ai_tune(const ai_params* p, const double* y0, int64_t n, int64_t ld, double 
   }
   int rc = AI_OK, warn = AI_OK;
   float best = -1.0f;
-  for (int32_t k : candidates) {
-    if (general && (k & 0xf) != AI_KERNEL_PLAIN) continue;  // other exponents: plain only
-    (void)hipEventRecord(a, nullptr);
-    rc = ai_integrate_async(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs, k, nullptr);
-    if (rc < 0) break;
-    warn = rc;
-    (void)hipEventRecord(b, nullptr);
-    if ((e = hipEventSynchronize(b)) != hipSuccess) {
-      rc = hip_fail(e, "hipEventSynchronize");
-      break;
+  // two rounds over the candidates, each timed on its own; the best time wins
+  for (int round = 0; round < 2 && rc >= 0; ++round)
+    for (int32_t k : candidates) {
+      if (general && (k & 0xf) != AI_KERNEL_PLAIN) continue;  // other exponents: plain only
+      (void)hipEventRecord(a, nullptr);
+      rc = ai_integrate_async(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs, k, nullptr);
+      if (rc < 0) break;
+      warn = rc;
+      (void)hipEventRecord(b, nullptr);
+      if ((e = hipEventSynchronize(b)) != hipSuccess) {
+        rc = hip_fail(e, "hipEventSynchronize");
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      if (best < 0.0f || ms < best) {
+        best = ms;
+        *best_kernel = k;
+      }
     }
-    float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, a, b);
-    if (best < 0.0f || ms < best) {
-      best = ms;
-      *best_kernel = k;
-    }
-  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (rc < 0) return rc;
