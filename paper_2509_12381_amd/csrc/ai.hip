@@ -75,6 +75,12 @@ constexpr double P1 = 611.0 / 230400.0, P3 = -514.0 / 83475.0, P4 = 391.0 / 3840
 constexpr int WAVE = 64;
 constexpr int BLOCK = 64;  // one wave per workgroup: a finished wave frees its slot at once
 
+// Leading positions of a scheduled plain launch integrated by four lanes each
+// (16 waves).  Past position 256 of the 2^20-trajectory thermal ensemble's
+// order no trajectory needs more than 80% of the longest one's attempts, and
+// 1024 lanes are a negligible share of the launch.
+constexpr long long WIDE_TRAJECTORIES = 256;
+
 // Launch constants: the system constants folded into the forms the force and
 // the controller use, computed once per call on the host, and the call's
 // buffers.  The integration kernels take it as their only argument; the force
@@ -92,6 +98,9 @@ struct Launch {
   double hinit_den;          // 0.8 rtol^(1/5)
   long long n, ld;
   long long first_dynamic;   // persistent kernel: first index handed out by the queue
+  long long wide;            // scheduled plain kernel: leading positions integrated by four
+                             // lanes each (see integrate_wide)
+  int wide_waves;            // the waves at the start of the grid that hold them
   int max_steps;
   int exit_on;               // r_exit > 0
   int refill_min;            // persistent kernel: idle lanes a wave gathers before drawing work
@@ -525,8 +534,8 @@ __device__ __forceinline__ void start(const F& Fc, const StartConst& S, const do
 
 // Step set-up of ode45: floor and cap the step, stretch it onto tf when within
 // 10% of the remaining span.
-template <class R>
-__device__ __forceinline__ void begin_step(const Ctl& K, LaneT<R>& L) {
+template <class LN>
+__device__ __forceinline__ void begin_step(const Ctl& K, LN& L) {
   const double hmin = 16.0 * spacing(L.t);
   L.absh = vmin(K.hmax, vmax(hmin, L.absh));
   L.done = false;
@@ -574,16 +583,56 @@ __device__ __forceinline__ void stage_phases(const Ctl& K, double cph, double sp
   }
 }
 
-// The rest of an attempt, the same in both stage precisions: the error test
-// and ode45's step-size control; on acceptance the state advances (xn, vn,
-// F7 at tnew, the phase rotated to tnew) and the observables and exits are
-// updated from the separation d = (dx, dy, dz) and r2n = |d|^2 at tnew.
-template <class R, class R7>
-__device__ __forceinline__ void conclude(const Ctl& K, LaneT<R>& L, double t, double h,
-                                         double tnew, double err, const double* xn,
-                                         const double* vn, const R7* F7, double cs6,
-                                         double sn6, double dx, double dy, double dz,
-                                         double r2n) {
+// Of two error components (signed value, positive scale), the one with the
+// larger ratio |value| / scale, compared by cross-multiplication; the first on
+// a tie.
+__device__ __forceinline__ void pick(double& na, double& da, double nb, double db) {
+  if (fabs(nb) * da > fabs(na) * db) {
+    na = nb;
+    da = db;
+  }
+}
+
+// The error norm err = h max_c |e_c| / max(|y_c|, |ynew_c|, AbsTol/RelTol)
+// takes the largest ratio by cross-multiplication in a fixed order: for the
+// positions, and then for the velocities, the ion's and the atom's component
+// of each axis, then the axes as ((x, y), z); last the position's and the
+// velocity's maximum.  Every path uses this order (the four-lane path reduces
+// each axis on its own lane), so all select the same component.  The position
+// half is reduced before the last force evaluation, which keeps few of its
+// values live across it.  half_norm() reduces one half: e the error
+// components, y and yn the solution before and after; returns whether an e is
+// NaN.
+template <class RE>
+__device__ __forceinline__ bool half_norm(const Ctl& K, const RE* e, const double* y,
+                                          const double* yn, double& n, double& d) {
+  double an[3], ad[3];
+  bool nan_seen = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double n0 = (double)e[k], d0 = max_abs(max_abs(y[k], yn[k]), K.thr);
+    const double n1 = (double)e[3 + k], d1 = max_abs(max_abs(y[3 + k], yn[3 + k]), K.thr);
+    nan_seen = nan_seen || (n0 != n0) || (n1 != n1);
+    pick(n0, d0, n1, d1);
+    an[k] = n0;
+    ad[k] = d0;
+  }
+  pick(an[0], ad[0], an[1], ad[1]);
+  pick(an[0], ad[0], an[2], ad[2]);
+  n = an[0];
+  d = ad[0];
+  return nan_seen;
+}
+
+// The rest of an attempt, the same in every path: the error test and ode45's
+// step-size control; on acceptance advance() moves the lane's state to tnew
+// (the phase is rotated here), and the observables and exits are updated from
+// w() = d . (v_ion - v_atom) and r2n = |d|^2 at tnew; ion_distance() gives
+// |x_ion| at tnew for the first bounce.
+template <class LN, class Advance, class W, class IonDistance>
+__device__ __forceinline__ void conclude(const Ctl& K, LN& L, double t, double h, double tnew,
+                                         double err, double cs6, double sn6, double r2n,
+                                         Advance advance, W w_of, IonDistance ion_distance) {
   if (!isfinite(err)) {
     L.status = AI_ST_NONFINITE;
     return;
@@ -608,25 +657,20 @@ __device__ __forceinline__ void conclude(const Ctl& K, LaneT<R>& L, double t, do
   L.t = tnew;
   L.cph = cs6;
   L.sph = sn6;
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    L.x[c] = xn[c];
-    L.v[c] = vn[c];
-    L.F1[c] = (R)F7[c];
-  }
+  advance();
   // growth 1/(1.25 (err/rtol)^(1/5)), at most 5x
   if (L.nofailed) L.absh = (w5 < 6.25) ? h * (0.8 * w5) : 5.0 * h;
   L.fresh = true;
 
   // observables: closest approach = sign change of r r' from - to +
-  const double w = fma(dz, vn[2] - vn[5], fma(dy, vn[1] - vn[4], dx * (vn[0] - vn[3])));
+  const double w = w_of();
   if (L.w_prev < 0.0 && w >= 0.0) {
     L.approached = true;
     if (r2n < K.r_bounce2) {
       L.bounces += 1;
       if (L.bounces == 1) {
         L.t_first = tnew;
-        L.position = sqrt(fma(xn[2], xn[2], fma(xn[1], xn[1], xn[0] * xn[0])));
+        L.position = ion_distance();
       }
       L.t_last = tnew;
     }
@@ -640,6 +684,28 @@ __device__ __forceinline__ void conclude(const Ctl& K, LaneT<R>& L, double t, do
     L.status = AI_ST_TMAX;
   else if (L.nsteps >= K.max_steps)
     L.status = AI_ST_MAXSTEPS;
+}
+
+// conclude() for a one-lane attempt: the new state xn, vn, F7 and the
+// separation d = (dx, dy, dz) at tnew.
+template <class R, class R7>
+__device__ __forceinline__ void conclude_lane(const Ctl& K, LaneT<R>& L, double t, double h,
+                                              double tnew, double err, const double* xn,
+                                              const double* vn, const R7* F7, double cs6,
+                                              double sn6, double dx, double dy, double dz,
+                                              double r2n) {
+  conclude(
+      K, L, t, h, tnew, err, cs6, sn6, r2n,
+      [&] {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          L.x[c] = xn[c];
+          L.v[c] = vn[c];
+          L.F1[c] = (R)F7[c];
+        }
+      },
+      [&] { return fma(dz, vn[2] - vn[5], fma(dy, vn[1] - vn[4], dx * (vn[0] - vn[3]))); },
+      [&] { return sqrt(fma(xn[2], xn[2], fma(xn[1], xn[1], xn[0] * xn[0]))); });
 }
 
 // One Dormand-Prince attempt of size h = absh from (t, x, v), the error test
@@ -705,35 +771,18 @@ __device__ __forceinline__ void attempt(const F& P, const Ctl& K, Lane& L) {
   }
   // stage 7 at tnew; tnew == t + h unless the step was stretched onto tf
   const double cos7 = L.done ? cos_rf(K.omega * tnew) : cs6;
+  // error norm (order in half_norm()): the position half, stage 7, the
+  // velocity half, then one reciprocal
+  double pn, pd, vn7, vd7;
+  const bool nan_x = half_norm(K, ex, x, xn, pn, pd);
   const double r2n = accel(P, cos7, xn, F7, dx, dy, dz);
-
-  // err = |h| max_c |eps_c| / max(|y_c|, |ynew_c|, AbsTol/RelTol): the
-  // largest ratio is found by cross-multiplication in a balanced tree (four
-  // levels instead of a chain of eleven comparisons), then one reciprocal
-  double num[12], den[12];  // error components (signed) and their scales
-  bool nan_seen = false;
+  double ev7[6];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    const int k = c % 6;
-    const double e = c < 6 ? ex[k] : fma(E7, F7[k], ev[k]);
-    const double y_ = c < 6 ? x[k] : v[k];
-    const double yn_ = c < 6 ? xn[k] : vn[k];
-    num[c] = e;
-    den[c] = max_abs(max_abs(y_, yn_), K.thr);
-    nan_seen = nan_seen || (e != e);
-  }
-#pragma unroll
-  for (int w = 1; w < 12; w *= 2) {
-#pragma unroll
-    for (int c = 0; c + w < 12; c += 2 * w) {
-      if (fabs(num[c + w]) * den[c] > fabs(num[c]) * den[c + w]) {
-        num[c] = num[c + w];
-        den[c] = den[c + w];
-      }
-    }
-  }
-  const double err = nan_seen ? __builtin_nan("") : h * fabs(num[0]) * recip(den[0]);
-  conclude(K, L, t, h, tnew, err, xn, vn, F7, cs6, sn6, dx, dy, dz, r2n);
+  for (int c = 0; c < 6; ++c) ev7[c] = fma(E7, F7[c], ev[c]);
+  const bool nan_v = half_norm(K, ev7, v, vn, vn7, vd7);
+  pick(pn, pd, vn7, vd7);
+  const double err = (nan_x || nan_v) ? __builtin_nan("") : h * fabs(pn) * recip(pd);
+  conclude_lane(K, L, t, h, tnew, err, xn, vn, F7, cs6, sn6, dx, dy, dz, r2n);
 }
 
 // Dormand-Prince coefficients in single precision for the variant below.
@@ -832,7 +881,10 @@ __device__ __forceinline__ void attempt32(const Force32& P, const Ctl& K, Lane& 
       ev[c] = fmaf(E6f, F6[c], fmaf(E5f, F5[c], fmaf(E4f, F4[c], fmaf(E3f, F3[c], E1f * F1[c]))));
     }
   }
-  // stage 7 at tnew from the new double state
+  // error norm in double, as in attempt(): the position half, stage 7 at tnew
+  // from the new double state, the velocity half
+  double pn, pd, vn7, vd7;
+  const bool nan_x = half_norm(K, ex, x, xn, pn, pd);
   const double cos7 = L.done ? cos_rf(K.omega * tnew) : cs6;
   const double dx = xn[0] - xn[3], dy = xn[1] - xn[4], dz = xn[2] - xn[5];
   {
@@ -841,32 +893,13 @@ __device__ __forceinline__ void attempt32(const Force32& P, const Ctl& K, Lane& 
     accel32(P, (float)cos7, dn, xin, F7);
   }
   const double r2n = fma(dz, dz, fma(dy, dy, dx * dx));
-
-  // error norm in double, as in attempt()
-  double num[12], den[12];
-  bool nan_seen = false;
+  float ev7[6];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    const int k = c % 6;
-    const double e = c < 6 ? (double)ex[k] : (double)fmaf(E7f, F7[k], ev[k]);
-    const double y_ = c < 6 ? x[k] : v[k];
-    const double yn_ = c < 6 ? xn[k] : vn[k];
-    num[c] = e;
-    den[c] = max_abs(max_abs(y_, yn_), K.thr);
-    nan_seen = nan_seen || (e != e);
-  }
-#pragma unroll
-  for (int w = 1; w < 12; w *= 2) {
-#pragma unroll
-    for (int c = 0; c + w < 12; c += 2 * w) {
-      if (fabs(num[c + w]) * den[c] > fabs(num[c]) * den[c + w]) {
-        num[c] = num[c + w];
-        den[c] = den[c + w];
-      }
-    }
-  }
-  const double err = nan_seen ? __builtin_nan("") : h * fabs(num[0]) * recip(den[0]);
-  conclude(K, L, t, h, tnew, err, xn, vn, F7, cs6, sn6, dx, dy, dz, r2n);
+  for (int c = 0; c < 6; ++c) ev7[c] = fmaf(E7f, F7[c], ev[c]);
+  const bool nan_v = half_norm(K, ev7, v, vn, vn7, vd7);
+  pick(pn, pd, vn7, vd7);
+  const double err = (nan_x || nan_v) ? __builtin_nan("") : h * fabs(pn) * recip(pd);
+  conclude_lane(K, L, t, h, tnew, err, xn, vn, F7, cs6, sn6, dx, dy, dz, r2n);
 }
 
 // End of trajectory idx: store the final state and the raw accumulators.
@@ -1036,19 +1069,285 @@ __device__ __forceinline__ void integrate_one(const Launch& P, long long idx) {
   finish(P.yf, P.obs, P.ld, L, idx, va0[0], va0[P.ld], va0[2 * P.ld]);
 }
 
+// ---- Four lanes per trajectory ----
+//
+// A scheduled launch ends with its longest trajectories (thousands of
+// attempts where the bulk needs hundreds), and one lane runs an attempt no
+// faster than its wave issues the ~700 instructions of the loop.  The leading
+// positions of the longest-first order therefore run four lanes each: lane a
+// of a quad holds axis a (lane 3 repeats axis 2) of the ion's and the atom's
+// position, velocity and acceleration, and does that axis's share of the stage
+// sums, the forces and the error components, about a third of the
+// arithmetic.  The separation components, the velocity differences and the
+// per-axis error maxima pass between the quad's lanes by DPP; everything that
+// depends on all three axes (|d|^2, the force magnitude, the step-size
+// control, the observables) is computed by each lane from the same operands
+// in the same order as the one-lane path, so every lane of the quad takes the
+// same decisions and the results are bitwise those of one lane.
+
+// v of lane SRC of this lane's quad (quad_perm [SRC, SRC, SRC, SRC]).  Every
+// lane of a quad is active whenever one is: they integrate one trajectory and
+// take the same decisions.
+template <int SRC>
+__device__ __forceinline__ int from_quad_lane(int v) {
+  return __builtin_amdgcn_mov_dpp(v, SRC * 0x55, 0xf, 0xf, true);
+}
+template <int SRC>
+__device__ __forceinline__ double from_quad_lane(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = from_quad_lane<SRC>((int)b), hi = from_quad_lane<SRC>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double axis_value(int ax, double a0, double a1, double a2) {
+  return ax == 0 ? a0 : (ax == 1 ? a1 : a2);
+}
+
+// One lane's share of a trajectory: axis ax of the ion's and the atom's
+// position, velocity and acceleration; the rest as in Lane.
+struct WideLane {
+  double xi, xa, vi, va, Fi, Fa;
+  double t, absh;
+  double cph, sph;
+  double w_prev, t_first, t_last, position, rmin2;
+  long long nfailed;
+  int nsteps, bounces, status;
+  int done, nofailed, fresh, approached;
+};
+
+// accel() for axis ax of the stage position (Xi, Xa): the trap coefficients of
+// that axis are ka, kq.  Returns r^2, the separation (dx, dy, dz) and the
+// axis's accelerations.
+template <class F>
+__device__ __forceinline__ double accel_wide(const F& P, double ka, double kq, double cosrf,
+                                             double Xi, double Xa, double& Fi, double& Fa,
+                                             double& dx, double& dy, double& dz) {
+  const double d = Xi - Xa;
+  dx = from_quad_lane<0>(d);
+  dy = from_quad_lane<1>(d);
+  dz = from_quad_lane<2>(d);
+  const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  const double s = recip(r2);
+  const double g = force_g(P, s);
+  const double gi = g * P.inv_mi, ga = g * P.inv_ma;
+  Fi = -fma(gi, d, fma(kq, cosrf, ka) * Xi);
+  Fa = ga * d;
+  return r2;
+}
+
+// attempt() on one axis per lane.
+template <class F>
+__device__ __forceinline__ void attempt_wide(const F& P, double ka, double kq, const Ctl& K,
+                                             WideLane& L) {
+  const double t = L.t, h = L.absh, hh = h * h;
+  const double tnew = L.done ? K.tf : t + h;
+  const double xi = L.xi, xa = L.xa, vi = L.vi, va = L.va, F1i = L.Fi, F1a = L.Fa;
+  double F2i, F2a, F3i, F3a, F4i, F4a, F5i, F5a, F6i, F6a, F7i, F7a;
+  double dx, dy, dz;
+
+  double cs2, cs3, cs4, cs5, cs6, sn6;
+  stage_phases(K, L.cph, L.sph, t, h, cs2, cs3, cs4, cs5, cs6, sn6);
+  {
+    const double a = C2 * h;
+    accel_wide(P, ka, kq, cs2, fma(a, vi, xi), fma(a, va, xa), F2i, F2a, dx, dy, dz);
+  }
+  {
+    const double a = C3 * h, q1 = Q31 * hh;
+    accel_wide(P, ka, kq, cs3, fma(q1, F1i, fma(a, vi, xi)), fma(q1, F1a, fma(a, va, xa)), F3i,
+               F3a, dx, dy, dz);
+  }
+  {
+    const double a = C4 * h, q1 = Q41 * hh, q2 = Q42 * hh;
+    accel_wide(P, ka, kq, cs4, fma(q2, F2i, fma(q1, F1i, fma(a, vi, xi))),
+               fma(q2, F2a, fma(q1, F1a, fma(a, va, xa))), F4i, F4a, dx, dy, dz);
+  }
+  {
+    const double a = C5 * h, q1 = Q51 * hh, q2 = Q52 * hh, q3 = Q53 * hh;
+    accel_wide(P, ka, kq, cs5, fma(q3, F3i, fma(q2, F2i, fma(q1, F1i, fma(a, vi, xi)))),
+               fma(q3, F3a, fma(q2, F2a, fma(q1, F1a, fma(a, va, xa)))), F5i, F5a, dx, dy, dz);
+  }
+  {
+    const double q1 = Q61 * hh, q2 = Q62 * hh, q3 = Q63 * hh, q4 = Q64 * hh;
+    accel_wide(P, ka, kq, cs6,
+               fma(q4, F4i, fma(q3, F3i, fma(q2, F2i, fma(q1, F1i, fma(h, vi, xi))))),
+               fma(q4, F4a, fma(q3, F3a, fma(q2, F2a, fma(q1, F1a, fma(h, va, xa))))), F6i, F6a,
+               dx, dy, dz);
+  }
+  double xni, xna, vni, vna, exi, exa, evi, eva;
+  {
+    const double q1 = Q71 * hh, q3 = Q73 * hh, q4 = Q74 * hh, q5 = Q75 * hh;
+    const double b1 = B1 * h, b3 = B3 * h, b4 = B4 * h, b5 = B5 * h, b6 = B6 * h;
+    const double p1 = P1 * h, p3 = P3 * h, p4 = P4 * h, p5 = P5 * h, p6 = P6 * h;
+    xni = fma(q5, F5i, fma(q4, F4i, fma(q3, F3i, fma(q1, F1i, fma(h, vi, xi)))));
+    xna = fma(q5, F5a, fma(q4, F4a, fma(q3, F3a, fma(q1, F1a, fma(h, va, xa)))));
+    vni = fma(b6, F6i, fma(b5, F5i, fma(b4, F4i, fma(b3, F3i, fma(b1, F1i, vi)))));
+    vna = fma(b6, F6a, fma(b5, F5a, fma(b4, F4a, fma(b3, F3a, fma(b1, F1a, va)))));
+    exi = fma(p6, F6i, fma(p5, F5i, fma(p4, F4i, fma(p3, F3i, p1 * F1i))));
+    exa = fma(p6, F6a, fma(p5, F5a, fma(p4, F4a, fma(p3, F3a, p1 * F1a))));
+    evi = fma(E6, F6i, fma(E5, F5i, fma(E4, F4i, fma(E3, F3i, E1 * F1i))));
+    eva = fma(E6, F6a, fma(E5, F5a, fma(E4, F4a, fma(E3, F3a, E1 * F1a))));
+  }
+  // error norm in the order of half_norm(): this axis's ion and atom
+  // components on this lane, the axes across the quad
+  double pn = exi, pd = max_abs(max_abs(xi, xni), K.thr);
+  int nan_here;
+  {
+    const double n1 = exa, d1 = max_abs(max_abs(xa, xna), K.thr);
+    nan_here = (pn != pn) | (n1 != n1);
+    pick(pn, pd, n1, d1);
+  }
+  const double pny = from_quad_lane<1>(pn), pdy = from_quad_lane<1>(pd);
+  const double pnz = from_quad_lane<2>(pn), pdz = from_quad_lane<2>(pd);
+  pn = from_quad_lane<0>(pn);
+  pd = from_quad_lane<0>(pd);
+  pick(pn, pd, pny, pdy);
+  pick(pn, pd, pnz, pdz);
+
+  const double cos7 = L.done ? cos_rf(K.omega * tnew) : cs6;
+  const double r2n = accel_wide(P, ka, kq, cos7, xni, xna, F7i, F7a, dx, dy, dz);
+
+  double vn7 = fma(E7, F7i, evi), vd7 = max_abs(max_abs(vi, vni), K.thr);
+  {
+    const double n3 = fma(E7, F7a, eva), d3 = max_abs(max_abs(va, vna), K.thr);
+    nan_here |= (vn7 != vn7) | (n3 != n3);
+    pick(vn7, vd7, n3, d3);
+  }
+  const double vny = from_quad_lane<1>(vn7), vdy = from_quad_lane<1>(vd7);
+  const double vnz = from_quad_lane<2>(vn7), vdz = from_quad_lane<2>(vd7);
+  vn7 = from_quad_lane<0>(vn7);
+  vd7 = from_quad_lane<0>(vd7);
+  pick(vn7, vd7, vny, vdy);
+  pick(vn7, vd7, vnz, vdz);
+  pick(pn, pd, vn7, vd7);
+  const int nan_seen =
+      from_quad_lane<0>(nan_here) | from_quad_lane<1>(nan_here) | from_quad_lane<2>(nan_here);
+  const double err = nan_seen ? __builtin_nan("") : h * fabs(pn) * recip(pd);
+
+  conclude(
+      K, L, t, h, tnew, err, cs6, sn6, r2n,
+      [&] {
+        L.xi = xni;
+        L.xa = xna;
+        L.vi = vni;
+        L.va = vna;
+        L.Fi = F7i;
+        L.Fa = F7a;
+      },
+      [&] {
+        const double dv = vni - vna;
+        const double dvx = from_quad_lane<0>(dv), dvy = from_quad_lane<1>(dv),
+                     dvz = from_quad_lane<2>(dv);
+        return fma(dz, dvz, fma(dy, dvy, dx * dvx));
+      },
+      [&] {
+        const double x0 = from_quad_lane<0>(xni), x1 = from_quad_lane<1>(xni),
+                     x2 = from_quad_lane<2>(xni);
+        return sqrt(fma(x2, x2, fma(x1, x1, x0 * x0)));
+      });
+}
+
+// Trajectory idx by the four lanes of a quad; this lane holds axis ax and, if
+// it is the quad's lane q < 3, stores that axis's final state (q = 0 also the
+// observables).  The start is the one-lane start on every lane.
+template <class F>
+__device__ __forceinline__ void integrate_wide(const Launch& P, long long idx, int q) {
+  const int ax = q < 3 ? q : 2;
+  const Ctl K = lane_ctl(P);
+  const F Fc = lane_force_of(P, (const F*)nullptr);
+  double y[12];
+  load_column(P, idx, y);
+  WideLane W;
+  {
+    Lane L;
+    start(Fc, start_const(P), y, L);
+    W.xi = axis_value(ax, L.x[0], L.x[1], L.x[2]);
+    W.xa = axis_value(ax, L.x[3], L.x[4], L.x[5]);
+    W.vi = axis_value(ax, L.v[0], L.v[1], L.v[2]);
+    W.va = axis_value(ax, L.v[3], L.v[4], L.v[5]);
+    W.Fi = axis_value(ax, L.F1[0], L.F1[1], L.F1[2]);
+    W.Fa = axis_value(ax, L.F1[3], L.F1[4], L.F1[5]);
+    W.t = L.t;
+    W.absh = L.absh;
+    W.cph = L.cph;
+    W.sph = L.sph;
+    W.w_prev = L.w_prev;
+    W.t_first = L.t_first;
+    W.t_last = L.t_last;
+    W.position = L.position;
+    W.rmin2 = L.rmin2;
+    W.nfailed = L.nfailed;
+    W.nsteps = L.nsteps;
+    W.bounces = L.bounces;
+    W.status = L.status;
+    W.done = L.done;
+    W.nofailed = L.nofailed;
+    W.fresh = L.fresh;
+    W.approached = L.approached;
+  }
+  const double ka = in_vgpr(axis_value(ax, Fc.ka[0], Fc.ka[1], Fc.ka[2]));
+  const double kq = in_vgpr(axis_value(ax, Fc.kq[0], Fc.kq[1], Fc.kq[2]));
+  while (W.status == 0) {
+    if (W.fresh) begin_step(K, W);
+    attempt_wide(Fc, ka, kq, K, W);
+  }
+  // the initial atom velocity y[9..11] was read before final_state (possibly
+  // y0) is written
+  const long long ld = P.ld;
+  if (q < 3) {
+    P.yf[ax * ld + idx] = W.xi;
+    P.yf[(3 + ax) * ld + idx] = W.vi;
+    P.yf[(6 + ax) * ld + idx] = W.xa;
+    P.yf[(9 + ax) * ld + idx] = W.va;
+  }
+  if (q == 0) {
+    double o[AI_NOBS];
+    o[AI_OBS_TEND] = W.t;
+    o[AI_OBS_STATUS] = (double)W.status;
+    o[AI_OBS_NSTEPS] = (double)W.nsteps;
+    o[AI_OBS_NFAILED] = (double)W.nfailed;
+    o[AI_OBS_BOUNCES] = (double)W.bounces;
+    o[AI_OBS_LIFETIME] = W.t_first;
+    o[AI_OBS_ANGLE] = W.t_last;
+    o[AI_OBS_TRANSFER] = y[9];
+    o[AI_OBS_POSITION] = W.position;
+    o[AI_OBS_DIST] = y[10];
+    o[AI_OBS_KE] = y[11];
+    o[AI_OBS_RMIN] = W.rmin2;
+    o[AI_OBS_HNEXT] = W.absh;
+#pragma unroll
+    for (int c = 0; c < AI_NOBS; ++c) P.obs[c * ld + idx] = o[c];
+  }
+}
+
 // With the schedule's keys a wave takes the priority of its first (longest)
-// trajectory.
-__device__ __forceinline__ void wave_priority_from_keys(const unsigned* key) {
+// trajectory, the one at schedule position first.
+__device__ __forceinline__ void wave_priority_from_keys(const unsigned* key, long long first) {
   if (key) {
-    const float top = (float)key[0], mine = (float)key[(long long)blockIdx.x * BLOCK];
+    const float top = (float)key[0], mine = (float)key[first];
     set_wave_priority(wave_uniform(top > 0.0f ? mine / top : 0.0f));
   }
 }
 
+// The plain kernels' grid: P.wide_waves waves of WAVE/4 trajectories each
+// (schedule positions 0 .. P.wide - 1, four lanes per trajectory), then one
+// trajectory per lane for positions P.wide .. n - 1.  Position g holds
+// trajectory order[g] (g itself without a schedule).
 template <class R, class F = Force>
 __device__ __forceinline__ void plain_body(const Launch& P) {
-  const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  wave_priority_from_keys(P.key);
+  const long long w = blockIdx.x;
+  if constexpr (sizeof(R) == sizeof(double)) {
+    if (w < P.wide_waves) {
+      const long long first = w * (WAVE / 4);
+      wave_priority_from_keys(P.key, first);
+      const long long g = first + (threadIdx.x >> 2);
+      if (g >= P.wide) return;
+      integrate_wide<F>(P, (long long)P.order[g], (int)(threadIdx.x & 3));
+      return;
+    }
+  }
+  const long long first = P.wide + (w - P.wide_waves) * BLOCK;
+  wave_priority_from_keys(P.key, first);
+  const long long g = first + threadIdx.x;
   if (g >= P.n) return;
   integrate_one<R, F>(P, P.order ? (long long)P.order[g] : g);
 }
@@ -1158,7 +1457,7 @@ __global__ __launch_bounds__(BLOCK) void ai_plain_nm_kernel(Launch P) {
 // ensemble's constants, buffers and tolerances.
 __global__ __launch_bounds__(BLOCK) void ai_plain_batch_kernel(BatchLaunch B) {
   const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  wave_priority_from_keys(B.key);
+  wave_priority_from_keys(B.key, (long long)blockIdx.x * BLOCK);
   if (g >= B.total) return;
   const long long j = B.order ? (long long)B.order[g] : g;
   const BatchEntry& E = B.entries[batch_entry(B.entries, B.count, j)];
@@ -1507,6 +1806,8 @@ Launch launch_constants(const ai_params* p, int64_t n, int64_t ld, double t0, do
   P.n = n;
   P.ld = ld;
   P.first_dynamic = 0;
+  P.wide = 0;
+  P.wide_waves = 0;
   P.exit_on = p->r_exit > 0.0;
   // single-precision stages: waves integrate in double within 100 R_e of the
   // ion, R_e = (m Cm / (n Cn))^(1/(m-n)) the minimum of V (10 a0 for Li +
@@ -1696,7 +1997,12 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
   };
 
   if ((kernel & 0xf) == AI_KERNEL_PLAIN) {
-    const long long blocks = (n + BLOCK - 1) / BLOCK;
+    // with the schedule, the longest predicted trajectories run four lanes each
+    if (order && !(kernel & AI_FP32_STAGES)) {
+      P.wide = n < WIDE_TRAJECTORIES ? n : WIDE_TRAJECTORIES;
+      P.wide_waves = (int)((P.wide + WAVE / 4 - 1) / (WAVE / 4));
+    }
+    const long long blocks = P.wide_waves + (n - P.wide + BLOCK - 1) / BLOCK;
     if (blocks > 0x7fffffffLL) {
       release();
       return fail(AI_EINVAL, "n too large for one launch");
@@ -1846,36 +2152,45 @@ int ai_tune(const ai_params* p, const double* y0, int64_t n, int64_t ld, double 
       AI_KERNEL_PERSISTENT | AI_SCHEDULE_LONGEST_FIRST | AI_REFILL_MIN(1),
       AI_KERNEL_PERSISTENT | AI_SCHEDULE_LONGEST_FIRST | AI_REFILL_MIN(16),
       AI_KERNEL_PERSISTENT | AI_SCHEDULE_LONGEST_FIRST | AI_REFILL_MIN(64)};
-  hipEvent_t a = nullptr, b = nullptr;
-  hipError_t e;
-  if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) {
-    if (a) (void)hipEventDestroy(a);
-    return hip_fail(e, "hipEventCreate");
-  }
-  int rc = AI_OK, warn = AI_OK;
+  constexpr int NC = sizeof(candidates) / sizeof(candidates[0]);
+  // one pair of events per candidate; a round enqueues every candidate
+  // back-to-back on the null stream, so each is timed with the GPU busy as in
+  // a sequence of calls (not from idle), and is read after the round
+  hipEvent_t ev[2 * NC] = {};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 2 * NC && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  int rc = e == hipSuccess ? AI_OK : hip_fail(e, "hipEventCreate");
+  int warn = AI_OK;
   float best = -1.0f;
-  // two rounds over the candidates, each timed on its own; the best time wins
-  for (int round = 0; round < 2 && rc >= 0; ++round)
-    for (int32_t k : candidates) {
+  for (int round = 0; round < 2 && rc >= 0; ++round) {
+    bool ran[NC] = {};
+    for (int i = 0; i < NC; ++i) {
+      const int32_t k = candidates[i];
       if (general && (k & 0xf) != AI_KERNEL_PLAIN) continue;  // other exponents: plain only
-      (void)hipEventRecord(a, nullptr);
+      (void)hipEventRecord(ev[2 * i], nullptr);
       rc = ai_integrate_async(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs, k, nullptr);
       if (rc < 0) break;
       warn = rc;
-      (void)hipEventRecord(b, nullptr);
-      if ((e = hipEventSynchronize(b)) != hipSuccess) {
-        rc = hip_fail(e, "hipEventSynchronize");
-        break;
-      }
+      (void)hipEventRecord(ev[2 * i + 1], nullptr);
+      ran[i] = true;
+    }
+    if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) {
+      if (rc >= 0) rc = hip_fail(e, "hipStreamSynchronize");
+      break;
+    }
+    if (rc < 0) break;
+    for (int i = 0; i < NC; ++i) {
+      if (!ran[i]) continue;
       float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, a, b);
+      (void)hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
       if (best < 0.0f || ms < best) {
         best = ms;
-        *best_kernel = k;
+        *best_kernel = candidates[i];
       }
     }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
+  }
+  for (int i = 0; i < 2 * NC; ++i)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
   if (rc < 0) return rc;
   *best_ms = best < 0.0f ? 0.0f : best;
   return warn;

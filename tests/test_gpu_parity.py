@@ -303,6 +303,72 @@ def test_kernels_and_schedules_agree_bitwise(ai, torch, kernel, schedule, refill
     assert np.all(b[0][:, 1000:] == -7.0) and np.all(b[1][:, 1000:] == -7.0)
 
 
+def _four_lane_inputs(wl, oracle_full, n):
+    """The first n of: a non-finite start, an atom on the ion, the initial
+    states of the 2^20-trajectory ensemble's complexes (two or more bounces in
+    the oracle) and of its longest other trajectories by the oracle's step
+    count, 40 in all (the schedule puts them first), then thermal
+    trajectories."""
+    _, yfull, _, ofull = oracle_full
+    cplx = np.nonzero(ofull[O["bounces"]] >= 2)[0][:40]
+    longest = np.argsort(-ofull[O["nsteps"]], kind="stable")
+    longest = longest[~np.isin(longest, cplx)][:40 - cplx.size]
+    assert cplx.size >= 1
+    y0 = wl.initial_states(300).copy()
+    y0[4, 0] = np.nan
+    y0[6:9, 1] = y0[0:3, 1]
+    y0[:, 2:42] = yfull[:, np.concatenate([cplx, longest])]
+    return y0[:, :n]
+
+
+@pytest.mark.parametrize("n", [1, 5, 16, 17, 255, 256, 257, 300])
+def test_four_lane_path_agrees_bitwise(ai, torch, oracle_full, n):
+    """The scheduled plain kernel integrates its leading 256 positions with four
+    lanes per trajectory (one axis each).  At sizes that fill the quads and the
+    waves raggedly, its results equal the unscheduled one-lane integration bit
+    for bit, also for bounces, complexes, a non-finite start and the step cap."""
+    import dataclasses
+    wl = W.small_ensemble()
+    y0 = _four_lane_inputs(wl, oracle_full, n)
+    ld = n + 3
+    for cap in (None, 300):
+        system = wl.system if cap is None else dataclasses.replace(wl.system, max_steps=cap)
+        a = run_gpu(ai, torch, system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "plain", ld=ld)
+        b = run_gpu(ai, torch, system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "plain", ld=ld,
+                    schedule="longest-first")
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+        assert np.all(b[0][:, n:] == -7.0) and np.all(b[1][:, n:] == -7.0)
+        assert a[1][O["status"], 0] == W.ST_NONFINITE
+        if cap is None and n >= 42:
+            assert np.sum(a[1][O["bounces"], :n] >= 2) >= 1     # complexes among them
+            assert np.sum(a[1][O["nsteps"], :n] >= 3000) >= 20  # and long trajectories
+        if cap is not None and n >= 42:
+            assert np.sum(a[1][O["status"], :n] == W.ST_MAXSTEPS) >= 20
+
+
+def test_four_lane_path_other_exponents_and_in_place(ai, torch, oracle_full):
+    """The same for a (6, 12) potential (the general-exponent kernel), and with
+    the final state written over the initial states."""
+    import dataclasses
+    wl = W.small_ensemble()
+    s612 = dataclasses.replace(wl.system, n=6, m=12, Cn=8200.0 * 2.0, Cm=4.1e9)
+    y0 = _four_lane_inputs(wl, oracle_full, 300)
+    a = run_gpu(ai, torch, s612, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "plain")
+    b = run_gpu(ai, torch, s612, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "plain",
+                schedule="longest-first")
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    d = torch.from_numpy(y0.copy()).cuda()
+    obs = torch.full((13, 300), -7.0, dtype=torch.float64, device="cuda")
+    ai.ai_integrate(wl.system, d, wl.t0, wl.tmax, wl.rtol, wl.atol, d, obs, "plain",
+                    schedule="longest-first")
+    torch.cuda.synchronize()
+    ref = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "plain")
+    np.testing.assert_array_equal(d.cpu().numpy(), ref[0])
+    np.testing.assert_array_equal(obs.cpu().numpy(), ref[1])
+
+
 @pytest.fixture(scope="module")
 def queue_ensemble(ai, torch):
     """Initial states for sizes past the persistent grid's lane count, where
