@@ -583,6 +583,16 @@ __device__ __forceinline__ void stage_phases(const Ctl& K, double cph, double sp
   }
 }
 
+// dst = src by one move into dst's own register (executed by the lanes of the
+// current branch only), so that a value carried around the loop keeps its
+// register on both sides of a divergent branch.
+__device__ __forceinline__ void move_into(double& dst, double src) {
+  asm volatile("v_mov_b64 %0, %1" : "+v"(dst) : "v"(src));
+}
+__device__ __forceinline__ void move_into(float& dst, float src) {
+  asm volatile("v_mov_b32 %0, %1" : "+v"(dst) : "v"(src));
+}
+
 // Of two error components (signed value, positive scale), the one with the
 // larger ratio |value| / scale, compared by cross-multiplication; the first on
 // a tie.
@@ -645,7 +655,7 @@ __device__ __forceinline__ void conclude(const Ctl& K, LN& L, double t, double h
       L.status = AI_ST_HMIN;
       return;
     }
-    L.absh = L.nofailed ? fmax(hmin, h * fmax(0.1, 0.8 * w5)) : fmax(hmin, 0.5 * h);
+    move_into(L.absh, L.nofailed ? fmax(hmin, h * fmax(0.1, 0.8 * w5)) : fmax(hmin, 0.5 * h));
     L.nofailed = false;
     L.done = false;
     L.fresh = false;
@@ -654,12 +664,12 @@ __device__ __forceinline__ void conclude(const Ctl& K, LN& L, double t, double h
 
   // accepted
   L.nsteps += 1;
-  L.t = tnew;
-  L.cph = cs6;
-  L.sph = sn6;
+  move_into(L.t, tnew);
+  move_into(L.cph, cs6);
+  move_into(L.sph, sn6);
   advance();
   // growth 1/(1.25 (err/rtol)^(1/5)), at most 5x
-  if (L.nofailed) L.absh = (w5 < 6.25) ? h * (0.8 * w5) : 5.0 * h;
+  if (L.nofailed) move_into(L.absh, (w5 < 6.25) ? h * (0.8 * w5) : 5.0 * h);
   L.fresh = true;
 
   // observables: closest approach = sign change of r r' from - to +
@@ -699,9 +709,9 @@ __device__ __forceinline__ void conclude_lane(const Ctl& K, LaneT<R>& L, double 
       [&] {
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-          L.x[c] = xn[c];
-          L.v[c] = vn[c];
-          L.F1[c] = (R)F7[c];
+          move_into(L.x[c], xn[c]);
+          move_into(L.v[c], vn[c]);
+          move_into(L.F1[c], (R)F7[c]);
         }
       },
       [&] { return fma(dz, vn[2] - vn[5], fma(dy, vn[1] - vn[4], dx * (vn[0] - vn[3]))); },
@@ -1226,12 +1236,12 @@ __device__ __forceinline__ void attempt_wide(const F& P, double ka, double kq, c
   conclude(
       K, L, t, h, tnew, err, cs6, sn6, r2n,
       [&] {
-        L.xi = xni;
-        L.xa = xna;
-        L.vi = vni;
-        L.va = vna;
-        L.Fi = F7i;
-        L.Fa = F7a;
+        move_into(L.xi, xni);
+        move_into(L.xa, xna);
+        move_into(L.vi, vni);
+        move_into(L.va, vna);
+        move_into(L.Fi, F7i);
+        move_into(L.Fa, F7a);
       },
       [&] {
         const double dv = vni - vna;
