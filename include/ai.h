@@ -211,6 +211,38 @@ int ai_integrate_batch_async(const ai_batch_item *items, int32_t count, int32_t 
 /* As ai_integrate_batch_async on the null stream, waiting for the result. */
 int ai_integrate_batch(const ai_batch_item *items, int32_t count, int32_t kernel);
 
+/* A batch prepared once and launched many times, for callers that capture
+ * the launch in a HIP graph or repeat it on the same buffers (Sec. 4.2 sweeps
+ * collision energy and trap parameters over the same ensembles).
+ *
+ * ai_batch_plan_create validates `items` as ai_integrate_batch does (kernel
+ * AI_KERNEL_PLAIN, optionally | AI_SCHEDULE_LONGEST_FIRST), copies the
+ * launch table to device memory it allocates and, with the schedule, orders
+ * the trajectories by the cost predicted from the initial states present now.
+ * Blocks until done.  The plan keeps the items' device pointers (y0,
+ * final_state, obs), their sizes, spans, tolerances and systems; the caller
+ * keeps those buffers allocated while the plan is used.  Returns AI_OK or
+ * AI_WRTOL and *out, or a negative ai_rc and *out = NULL.
+ *
+ * ai_batch_plan_launch enqueues the batch's integration and observables
+ * kernels on `stream` (hipStream_t; NULL = null stream) and nothing else: no
+ * allocation, no copy, no memset, so it may be captured in a HIP graph and
+ * replayed.  Each launch integrates the initial states that y0 holds when it
+ * runs; the results are bitwise those of ai_integrate_batch on them (the
+ * order computed at creation affects only the time, never the results).
+ * Launches of one plan on different streams must not overlap (they write the
+ * same outputs).  Returns the creation's AI_OK / AI_WRTOL or a negative
+ * ai_rc.
+ *
+ * ai_batch_plan_destroy frees the plan's device memory; the caller makes sure
+ * that no launch of the plan is still running or will be replayed. */
+typedef struct ai_batch_plan ai_batch_plan;
+
+int ai_batch_plan_create(const ai_batch_item *items, int32_t count, int32_t kernel,
+                         ai_batch_plan **out);
+int ai_batch_plan_launch(const ai_batch_plan *plan, void *stream);
+int ai_batch_plan_destroy(ai_batch_plan *plan);
+
 /* Replay one trajectory with its path: the integration ai_integrate performs
  * for it (same attempts, bitwise the same final state and observables), with
  * (t, y) recorded at t0 and at `refine` points per accepted step (Sec. 4.1

@@ -27,9 +27,10 @@ OK, WRTOL, EINVAL, EHIP, ENOMEM, EUNSUPPORTED, EAGAIN = 0, 1, -1, -2, -3, -4, -5
 
 # exported symbols of the C ABI, in declaration order
 SYMBOLS = ("ai_integrate", "ai_integrate_async", "ai_integrate_batch",
-           "ai_integrate_batch_async", "ai_tune", "ai_trace", "ai_server_create", "ai_server_submit", "ai_server_wait",
-           "ai_server_destroy", "ai_kernel_time", "ai_get_kernel_info", "ai_last_error",
-           "ai_nobs", "ai_version")
+           "ai_integrate_batch_async", "ai_batch_plan_create", "ai_batch_plan_launch",
+           "ai_batch_plan_destroy", "ai_tune", "ai_trace", "ai_server_create",
+           "ai_server_submit", "ai_server_wait", "ai_server_destroy", "ai_kernel_time",
+           "ai_get_kernel_info", "ai_last_error", "ai_nobs", "ai_version")
 
 
 class AiParams(C.Structure):
@@ -115,6 +116,13 @@ def load(path: str = LIB_PATH):
         lib.ai_integrate_batch_async.argtypes = [C.POINTER(AiBatchItem), C.c_int32, C.c_int32,
                                                  C.c_void_p]
         lib.ai_integrate_batch_async.restype = C.c_int
+        lib.ai_batch_plan_create.argtypes = [C.POINTER(AiBatchItem), C.c_int32, C.c_int32,
+                                             C.POINTER(C.c_void_p)]
+        lib.ai_batch_plan_create.restype = C.c_int
+        lib.ai_batch_plan_launch.argtypes = [C.c_void_p, C.c_void_p]
+        lib.ai_batch_plan_launch.restype = C.c_int
+        lib.ai_batch_plan_destroy.argtypes = [C.c_void_p]
+        lib.ai_batch_plan_destroy.restype = C.c_int
         lib.ai_tune.argtypes = args[:-1] + [C.POINTER(C.c_int32), C.POINTER(C.c_float)]
         lib.ai_tune.restype = C.c_int
         lib.ai_trace.argtypes = [_P, _D, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -328,6 +336,48 @@ def ai_server_wait(server, ticket: int, timeout=None):
 
 def ai_server_destroy(server) -> int:
     return _check(load().ai_server_destroy(server))
+
+
+def ai_batch_plan_create(items, schedule="longest-first"):
+    """ai_batch_plan_create over batch_items(items); returns (plan handle, rc)."""
+    h = C.c_void_p()
+    rc = _check(load().ai_batch_plan_create(batch_items(items), len(items), SCHEDULES[schedule],
+                                            C.byref(h)))
+    return h, rc
+
+
+def ai_batch_plan_launch(plan, stream=None):
+    """Enqueue a plan's kernels on `stream` (default: torch's current stream)."""
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _check(load().ai_batch_plan_launch(plan, C.c_void_p(s.cuda_stream)))
+
+
+def ai_batch_plan_destroy(plan):
+    return _check(load().ai_batch_plan_destroy(plan))
+
+
+class BatchPlan:
+    """ai_batch_plan: a batch (batch_items tuples) prepared once; launch()
+    enqueues only its two kernels (capturable in a HIP graph).  The tensors of
+    the items must stay alive while the plan is used."""
+
+    def __init__(self, items, schedule="longest-first"):
+        self._h, self.rc = ai_batch_plan_create(items, schedule)
+
+    def launch(self, stream=None):
+        return ai_batch_plan_launch(self._h, stream)
+
+    def close(self):
+        if self._h:
+            h, self._h = self._h, None
+            ai_batch_plan_destroy(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Server:

@@ -1914,6 +1914,67 @@ int ai_check_request(const ai_batch_item* item, int32_t kernel) {
   return item->rtol < 100.0 * 2.220446049250313e-16 ? AI_WRTOL : AI_OK;
 }
 
+namespace {
+
+// The host side of a batched call: validated items, the launch table's
+// entries and the schedule's per-item models.
+struct BatchPrep {
+  std::vector<BatchEntry> entries;
+  std::vector<ai_order_item> keys;
+  long long total = 0;
+  double cost_max = 0.0;
+};
+
+// Validate a batch and fill prep; `extra` are the kernel flags allowed besides
+// the schedule.  Returns AI_OK, AI_WRTOL or a negative ai_rc (g_error set).
+int prepare_batch(const ai_batch_item* items, int32_t count, int32_t kernel, int32_t extra,
+                  BatchPrep& prep) {
+  if (count < 0) return fail(AI_EINVAL, "count = %d < 0", count);
+  if (count > 0 && !items) return fail(AI_EINVAL, "items is NULL");
+  if ((kernel & ~(AI_SCHEDULE_LONGEST_FIRST | extra)) != AI_KERNEL_PLAIN)
+    return fail(AI_EUNSUPPORTED, "a batch runs the plain double kernel (kernel 0x%x)",
+                (unsigned)kernel);
+  int warn = AI_OK;
+  for (int32_t b = 0; b < count; ++b) {
+    const ai_batch_item& it = items[b];
+    int rc = validate(&it.params, it.y0, it.n, it.ld, it.t0, it.tmax, it.rtol, it.atol,
+                      it.final_state, it.obs, AI_KERNEL_PLAIN);
+    if (rc != AI_OK) {
+      const std::string why = g_error;
+      return fail(rc, "item %d: %s", b, why.c_str());
+    }
+    if (it.params.n != 4 || it.params.m != 8)
+      return fail(AI_EUNSUPPORTED, "item %d: a batch integrates n=4, m=8 potentials", b);
+    if (it.n == 0) continue;
+    double rtol = it.rtol;
+    if (rtol < 100.0 * 2.220446049250313e-16) {
+      rtol = 100.0 * 2.220446049250313e-16;
+      warn = AI_WRTOL;
+    }
+    BatchEntry E;
+    E.P = launch_constants(&it.params, it.n, it.ld, it.t0, it.tmax, rtol, it.atol);
+    E.P.y0 = it.y0;
+    E.P.yf = it.final_state;
+    E.P.obs = it.obs;
+    E.offset = prep.total;
+    prep.entries.push_back(E);
+    ai_order_item K;
+    K.y0 = it.y0;
+    K.ld = it.ld;
+    K.offset = prep.total;
+    K.n = it.n;
+    K.model = order_model(&it.params, it.t0, it.tmax, rtol, true);
+    prep.cost_max = std::fmax(prep.cost_max, (double)K.model.horizon * K.model.rate);
+    prep.keys.push_back(K);
+    prep.total += it.n;
+  }
+  if ((prep.total + BLOCK - 1) / BLOCK > 0x7fffffffLL)
+    return fail(AI_EINVAL, "%lld trajectories are too many for one launch", prep.total);
+  return warn;
+}
+
+}  // namespace
+
 extern "C" {
 
 int ai_version(void) { return 1; }
@@ -2220,52 +2281,14 @@ int ai_integrate(const ai_params* p, const double* y0, int64_t n, int64_t ld, do
 int ai_integrate_batch_async(const ai_batch_item* items, int32_t count, int32_t kernel,
                              void* stream) {
   g_error.clear();
-  if (count < 0) return fail(AI_EINVAL, "count = %d < 0", count);
-  if (count > 0 && !items) return fail(AI_EINVAL, "items is NULL");
-  if ((kernel & ~(AI_SCHEDULE_LONGEST_FIRST | AI_TIME_KERNEL)) != AI_KERNEL_PLAIN)
-    return fail(AI_EUNSUPPORTED, "a batch runs the plain double kernel (kernel 0x%x)",
-                (unsigned)kernel);
-  int warn = AI_OK;
-  std::vector<BatchEntry> entries;
-  std::vector<ai_order_item> keys;
-  long long total = 0;
-  double cost_max = 0.0;
-  for (int32_t b = 0; b < count; ++b) {
-    const ai_batch_item& it = items[b];
-    int rc = validate(&it.params, it.y0, it.n, it.ld, it.t0, it.tmax, it.rtol, it.atol,
-                      it.final_state, it.obs, AI_KERNEL_PLAIN);
-    if (rc != AI_OK) {
-      const std::string why = g_error;
-      return fail(rc, "item %d: %s", b, why.c_str());
-    }
-    if (it.params.n != 4 || it.params.m != 8)
-      return fail(AI_EUNSUPPORTED, "item %d: a batch integrates n=4, m=8 potentials", b);
-    if (it.n == 0) continue;
-    double rtol = it.rtol;
-    if (rtol < 100.0 * 2.220446049250313e-16) {
-      rtol = 100.0 * 2.220446049250313e-16;
-      warn = AI_WRTOL;
-    }
-    BatchEntry E;
-    E.P = launch_constants(&it.params, it.n, it.ld, it.t0, it.tmax, rtol, it.atol);
-    E.P.y0 = it.y0;
-    E.P.yf = it.final_state;
-    E.P.obs = it.obs;
-    E.offset = total;
-    entries.push_back(E);
-    ai_order_item K;
-    K.y0 = it.y0;
-    K.ld = it.ld;
-    K.offset = total;
-    K.n = it.n;
-    K.model = order_model(&it.params, it.t0, it.tmax, rtol, true);
-    cost_max = std::fmax(cost_max, (double)K.model.horizon * K.model.rate);
-    keys.push_back(K);
-    total += it.n;
-  }
+  BatchPrep prep;
+  int warn = prepare_batch(items, count, kernel, AI_TIME_KERNEL, prep);
+  if (warn < 0) return warn;
+  std::vector<BatchEntry>& entries = prep.entries;
+  std::vector<ai_order_item>& keys = prep.keys;
+  const long long total = prep.total;
+  const double cost_max = prep.cost_max;
   if (total == 0) return warn;
-  if ((total + BLOCK - 1) / BLOCK > 0x7fffffffLL)
-    return fail(AI_EINVAL, "%lld trajectories are too many for one launch", total);
 
   hipStream_t s = (hipStream_t)stream;
   int dev = 0;
@@ -2347,6 +2370,114 @@ int ai_integrate_batch(const ai_batch_item* items, int32_t count, int32_t kernel
   hipError_t e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   return rc;
+}
+
+// A batch prepared once: its launch table and (with the schedule) its order in
+// device memory, so that each launch enqueues the integration and the
+// observables kernels and nothing else.
+struct ai_batch_plan {
+  int device = 0;
+  char* table = nullptr;  // BatchEntry[count] (hipMalloc)
+  void* order_ws = nullptr;  // the schedule's stream-ordered workspace
+  BatchLaunch launch{};
+  int warn = AI_OK;
+};
+
+static void plan_release(ai_batch_plan* pl) {
+  if (pl->order_ws) {
+    (void)hipFreeAsync(pl->order_ws, nullptr);
+    (void)hipStreamSynchronize(nullptr);
+  }
+  if (pl->table) (void)hipFree(pl->table);
+  delete pl;
+}
+
+int ai_batch_plan_create(const ai_batch_item* items, int32_t count, int32_t kernel,
+                         ai_batch_plan** out) {
+  g_error.clear();
+  if (!out) return fail(AI_EINVAL, "out is NULL");
+  *out = nullptr;
+  BatchPrep prep;
+  const int warn = prepare_batch(items, count, kernel, 0, prep);
+  if (warn < 0) return warn;
+  ai_batch_plan* pl = new (std::nothrow) ai_batch_plan;
+  if (!pl) return fail(AI_ENOMEM, "plan");
+  pl->warn = warn;
+  hipError_t e = hipGetDevice(&pl->device);
+  if (e != hipSuccess) {
+    plan_release(pl);
+    return hip_fail(e, "hipGetDevice");
+  }
+  const int E = (int)prep.entries.size();
+  BatchLaunch& B = pl->launch;
+  B.count = E;
+  B.total = prep.total;
+  B.order = nullptr;
+  B.key = nullptr;
+  B.entries = nullptr;
+  if (prep.total > 0) {
+    const size_t ebytes = (sizeof(BatchEntry) * E + 255) & ~size_t(255);
+    const size_t kbytes = sizeof(ai_order_item) * E;
+    std::vector<char> host(ebytes + kbytes);
+    std::memcpy(host.data(), prep.entries.data(), sizeof(BatchEntry) * E);
+    std::memcpy(host.data() + ebytes, prep.keys.data(), kbytes);
+    if ((e = hipMalloc((void**)&pl->table, host.size())) != hipSuccess) {
+      (void)hipGetLastError();
+      plan_release(pl);
+      return fail(AI_ENOMEM, "hipMalloc(plan table): %s", hipGetErrorString(e));
+    }
+    if ((e = hipMemcpy(pl->table, host.data(), host.size(), hipMemcpyHostToDevice)) !=
+        hipSuccess) {
+      plan_release(pl);
+      return hip_fail(e, "hipMemcpy(plan table)");
+    }
+    B.entries = (const BatchEntry*)pl->table;
+    if ((kernel & AI_SCHEDULE_LONGEST_FIRST) && prep.total <= 0xffffffffLL) {
+      unsigned* order = nullptr;
+      unsigned* key = nullptr;
+      e = ai_longest_first_order_batch((const ai_order_item*)(pl->table + ebytes), E,
+                                       prep.total, prep.cost_max, &order, &key, &pl->order_ws,
+                                       nullptr);
+      if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        plan_release(pl);
+        return e == hipErrorOutOfMemory
+                   ? fail(AI_ENOMEM, "schedule workspace: %s", hipGetErrorString(e))
+                   : hip_fail(e, "schedule(plan)");
+      }
+      B.order = order;
+      B.key = key;
+    }
+  }
+  *out = pl;
+  return warn;
+}
+
+int ai_batch_plan_launch(const ai_batch_plan* pl, void* stream) {
+  g_error.clear();
+  if (!pl) return fail(AI_EINVAL, "plan is NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl->device)
+    return fail(AI_EINVAL, "launch a plan on the device it was created on");
+  const BatchLaunch& B = pl->launch;
+  if (B.total == 0) return pl->warn;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(ai_plain_batch_kernel, dim3((unsigned)((B.total + BLOCK - 1) / BLOCK)),
+                     dim3(BLOCK), 0, s, B);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "launch(plan)");
+  hipLaunchKernelGGL(ai_finalize_batch_kernel, dim3((unsigned)((B.total + 255) / 256)), dim3(256),
+                     0, s, B);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "launch(plan finalize)");
+  return pl->warn;
+}
+
+int ai_batch_plan_destroy(ai_batch_plan* pl) {
+  g_error.clear();
+  if (!pl) return fail(AI_EINVAL, "plan is NULL");
+  plan_release(pl);
+  return AI_OK;
 }
 
 }  // extern "C"

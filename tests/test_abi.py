@@ -27,7 +27,9 @@ def lib():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     assert names == sorted(["ai_integrate", "ai_integrate_async", "ai_integrate_batch",
-                            "ai_integrate_batch_async", "ai_tune", "ai_trace",
+                            "ai_integrate_batch_async", "ai_batch_plan_create",
+                            "ai_batch_plan_launch", "ai_batch_plan_destroy", "ai_tune",
+                            "ai_trace",
                             "ai_server_create",
                             "ai_server_submit",
                             "ai_server_wait", "ai_server_destroy", "ai_kernel_time",
@@ -147,6 +149,36 @@ def test_server_argument_errors_without_gpu(lib):
     if not _gpu_visible():
         rc = L.ai_server_create(None, ctypes.byref(h))
         assert rc == binding.EHIP and h.value is None
+
+
+def test_batch_plan_argument_errors_without_gpu(lib):
+    """ai_batch_plan_*: a NULL out pointer, a negative count, a kernel other
+    than the plain double one (timing included), an invalid item and NULL
+    plans are refused before any device call; an empty plan without a GPU
+    reports the HIP error."""
+    from paper_2509_12381_amd import binding, workload as W
+    L = binding.load()
+    p = binding.params(W.liyb_system())
+    h = ctypes.c_void_p()
+    items = (binding.AiBatchItem * 2)()
+    for it in items:
+        it.params = p
+        it.n, it.ld, it.t0, it.tmax, it.rtol, it.atol = 0, 0, 0.0, 1.0, 1e-8, 1e-10
+    assert L.ai_batch_plan_create(items, 2, 0, None) == binding.EINVAL
+    assert L.ai_batch_plan_create(None, -1, 0, ctypes.byref(h)) == binding.EINVAL
+    assert L.ai_batch_plan_create(items, 2, binding.TIME_KERNEL,
+                                  ctypes.byref(h)) == binding.EUNSUPPORTED
+    assert L.ai_batch_plan_create(items, 2, 1, ctypes.byref(h)) == binding.EUNSUPPORTED
+    items[1].tmax = -1.0
+    assert L.ai_batch_plan_create(items, 2, 0, ctypes.byref(h)) == binding.EINVAL
+    assert binding.ai_last_error().startswith("item 1:")
+    assert h.value is None
+    assert L.ai_batch_plan_launch(None, None) == binding.EINVAL
+    assert L.ai_batch_plan_destroy(None) == binding.EINVAL
+    if not _gpu_visible():
+        items[1].tmax = 1.0
+        assert L.ai_batch_plan_create(items, 2, 0, ctypes.byref(h)) == binding.EHIP
+        assert h.value is None
 
 
 def _gpu_visible():

@@ -721,6 +721,72 @@ def test_batch_matches_single_calls(ai, torch, schedule):
         assert np.all(obs.cpu().numpy()[:, n:] == -7.0)
 
 
+def _batch_tuples(items, dev):
+    return [(it["wl"].system, d, fin, obs, it["t0"], it["tmax"], it["rtol"], it["atol"], n)
+            for it, (d, fin, obs, n) in zip(items, dev)]
+
+
+@pytest.mark.parametrize("schedule", [None, "longest-first"])
+def test_batch_plan_matches_batched_call(ai, torch, schedule):
+    """A prepared batch launched twice gives, each time, bitwise the results of
+    ai_integrate_batch on the same items, and writes nothing past each n."""
+    items = _batch_case()
+    dev = [_device_item(torch, it) for it in items]
+    ref = [_device_item(torch, it) for it in items]
+    ai.ai_integrate_batch(_batch_tuples(items, ref), schedule=schedule)
+    torch.cuda.synchronize()
+    with ai.BatchPlan(_batch_tuples(items, dev), schedule=schedule) as plan:
+        assert plan.rc == 0
+        for rep in range(2):
+            for _, fin, obs, _ in dev:
+                fin.fill_(-7.0)
+                obs.fill_(-7.0)
+            assert plan.launch() == 0
+            torch.cuda.synchronize()
+            for (_, f, o, n), (_, rf, ro, _) in zip(dev, ref):
+                np.testing.assert_array_equal(f.cpu().numpy(), rf.cpu().numpy())
+                np.testing.assert_array_equal(o.cpu().numpy(), ro.cpu().numpy())
+                assert np.all(o.cpu().numpy()[:, n:] == -7.0)
+
+
+def test_batch_plan_replays_from_a_graph(ai, torch):
+    """A plan's launch enqueues two kernels and nothing else, so it can be
+    captured in a HIP graph: every replay, with eager work between them, gives
+    the batched call's result, also after new initial states are written into
+    the items' buffers (the order computed at creation affects only the time)."""
+    items = _batch_case()
+    dev = [_device_item(torch, it) for it in items]
+    plan = ai.BatchPlan(_batch_tuples(items, dev), schedule="longest-first")
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.launch(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    rng = np.random.default_rng(5)
+    for rep in range(4):
+        if rep == 2:   # new initial states for two items, in place
+            for k in (1, 5):
+                d, _, _, n = dev[k]
+                fresh = items[k]["wl"].initial_states(n + 7)[:, 7:]
+                d[:, :n] = torch.from_numpy(fresh).cuda()
+        ref = [(d.clone(), torch.full_like(f, -7.0), torch.full_like(o, -7.0), n)
+               for d, f, o, n in dev]
+        ai.ai_integrate_batch(_batch_tuples(items, ref), schedule="longest-first")
+        for _, fin, obs, _ in dev:
+            fin.fill_(float(rng.integers(-9, -1)))
+            obs.fill_(-7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (_, f, o, n), (_, rf, ro, _) in zip(dev, ref):
+            np.testing.assert_array_equal(f.cpu().numpy()[:, :n], rf.cpu().numpy()[:, :n])
+            np.testing.assert_array_equal(o.cpu().numpy(), ro.cpu().numpy())
+    del g
+    plan.close()
+
+
 def test_batch_oracle_parity(ai, torch, aio):
     """Samples of three contrasting ensembles of the batched grid (10 uK at
     q = 0.05, 0.5 mK at q = 0.4, 10 mK at the Mathieu-unstable q = 0.7) through
