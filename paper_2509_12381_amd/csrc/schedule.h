@@ -21,7 +21,8 @@ constexpr unsigned AI_ORDER_CODES = 1u << AI_ORDER_CODE_BITS;
 // of a trajectory's duration:
 //  - analytic: the time at which the atom, on a straight line at its initial
 //    velocity, is r_exit away from the ion on its secular orbit (Newton steps
-//    from the straight-line exit from the sphere about the trap centre);
+//    from the straight-line exit from the sphere about the trap centre), plus
+//    the span a close pass costs (below);
 //  - sampled: the exit rule itself, evaluated on AI_ORDER_SAMPLES samples per
 //    RF period of a model in which only the trap acts: the atom flies in a
 //    straight line and the ion follows the trap's linear equation of motion
@@ -34,8 +35,21 @@ constexpr unsigned AI_ORDER_CODES = 1u << AI_ORDER_CODE_BITS;
 // which both predict alike; the analytic one is cheaper.  Across ensembles
 // of different systems the packing of lanes dominates and needs the sampled
 // one.
+// A close pass costs the integrator extra attempts at short range that its
+// duration does not show: over the 2^20-trajectory thermal Li + Yb+ ensemble,
+// trajectories whose atom passes within 500 a0 of the ion's secular orbit
+// took up to ~250 attempts (8 RF periods' worth) more than their duration
+// predicts, fading to none beyond 2000 a0.  The analytic prediction adds that
+// span for a close pass, tapered linearly between the two radii (a generous
+// estimate: starting such a trajectory early costs little, starting it late
+// can end the launch late).
+constexpr double AI_ORDER_CLOSE_R_IN = 500.0;    // a0
+constexpr double AI_ORDER_CLOSE_R_OUT = 2000.0;  // a0
+constexpr double AI_ORDER_CLOSE_PERIODS = 8.0;   // RF periods
+
 struct ai_order_model {
   float horizon;   // tmax - t0
+  float close_span;  // analytic: AI_ORDER_CLOSE_PERIODS RF periods (0 for a static trap)
   float r_exit2;   // sampled: r_exit^2 (1 + 2^-12)
   float dt;        // sampled: sample spacing, one RF period / AI_ORDER_SAMPLES
   int periods;     // sampled: periods searched, min(ceil(horizon / period), AI_ORDER_MAX_PERIODS)

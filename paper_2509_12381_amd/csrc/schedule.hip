@@ -81,7 +81,40 @@ __device__ float analytic_duration(const double* __restrict__ y0, long long ld, 
       if (tn > 0.5 * ts && tn < 2.0 * ts) t = tn;
     }
   }
-  const float tf = (float)t;  // inf for an atom at rest; NaN sorts anywhere
+  // closest approach to the ion's secular orbit before the exit: Newton steps
+  // on d/dt |d|^2 = 0 from the closest approach of the initial relative
+  // motion, kept within [0, t]
+  float close = 0.0f;
+  if (M.close_span > 0.0f && t > 0.0) {
+    double d0v = 0.0, uu = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double u = va[k] - vi[k];
+      d0v += (xa[k] - xi[k]) * u;
+      uu += u * u;
+    }
+    double tc = uu > 0.0 ? fmin(fmax(-d0v / uu, 0.0), t) : 0.0;
+    double r2c = 0.0;
+    for (int it = 0; it < 4; ++it) {
+      double x[3], v[3];
+      ion_secular(M, xi, vi, tc, x, v);
+      double f1 = 0.0, f2 = 0.0;
+      r2c = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double w = M.secular_omega[k];
+        const double dk = xa[k] + va[k] * tc - x[k], uk = va[k] - v[k];
+        r2c += dk * dk;
+        f1 += dk * uk;
+        f2 += uk * uk - dk * (-w * w * x[k]);
+      }
+      if (f2 > 0.0) tc = fmin(fmax(tc - f1 / f2, 0.0), t);
+    }
+    const double rc = sqrt(r2c);
+    const double frac = (AI_ORDER_CLOSE_R_OUT - rc) / (AI_ORDER_CLOSE_R_OUT - AI_ORDER_CLOSE_R_IN);
+    close = M.close_span * (float)fmin(fmax(frac, 0.0), 1.0);
+  }
+  const float tf = (float)t + close;  // inf for an atom at rest; NaN sorts anywhere
   return tf < horizon ? (tf > 0.0f ? tf : 0.0f) : horizon;
 }
 
@@ -346,6 +379,7 @@ ai_order_model ai_make_order_model(const double a[3], const double q[3], double 
   // one RF period (any interval for a static trap, whose equation is autonomous)
   const double period = w > 0.0 ? 6.283185307179586 / w : horizon / AI_ORDER_MAX_PERIODS;
   m.horizon = (float)horizon;
+  m.close_span = w > 0.0 ? (float)(AI_ORDER_CLOSE_PERIODS * period) : 0.0f;
   m.r_exit2 = (float)(r_exit * r_exit * (1.0 + 0x1p-12));
   m.dt = (float)(period / AI_ORDER_SAMPLES);
   m.periods = (int)std::fmin(std::ceil(horizon / period), (double)AI_ORDER_MAX_PERIODS);
