@@ -360,7 +360,7 @@ def main() -> int:
         best, best_ms = binding.ai_tune(wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol,
                                         t_fin, t_obs)
         tuned = {"best_kernel_code": best, "best_ms": best_ms,
-                 "what": "ai_tune: each configuration run twice on this ensemble"}
+                 "what": "ai_tune: each configuration timed twice on this ensemble, each after an untimed run of itself"}
         del t_fin, t_obs
 
     batched = None

@@ -161,9 +161,9 @@ int ai_integrate_async(const ai_params *p, const double *y0, int64_t n, int64_t 
  * AI_KERNEL_PLAIN | AI_SCHEDULE_LONGEST_FIRST and AI_KERNEL_PERSISTENT |
  * AI_SCHEDULE_LONGEST_FIRST | AI_REFILL_MIN(k) for k = 1, 16, 64 (plain only
  * for exponents other than n=4, m=8) in two rounds; a round enqueues the
- * candidates back-to-back on the null stream, each between HIP events, so
- * each is timed on a busy GPU as in a sequence of calls.  The best single time
- * wins.  Every configuration gives bitwise the same results, so the outputs
+ * candidates back-to-back on the null stream, each as an untimed run followed
+ * by a run between HIP events, so each is timed as in a sequence of its own
+ * calls.  The best single time wins.  Every configuration gives bitwise the same results, so the outputs
  * hold the ensemble's results afterwards, as after ai_integrate.  Arguments as
  * for ai_integrate, except that final_state must not be y0 (the ensemble runs
  * several times).  *best_kernel (host) receives the fastest configuration, to

@@ -2225,8 +2225,11 @@ int ai_tune(const ai_params* p, const double* y0, int64_t n, int64_t ld, double 
       AI_KERNEL_PERSISTENT | AI_SCHEDULE_LONGEST_FIRST | AI_REFILL_MIN(64)};
   constexpr int NC = sizeof(candidates) / sizeof(candidates[0]);
   // one pair of events per candidate; a round enqueues every candidate
-  // back-to-back on the null stream, so each is timed with the GPU busy as in
-  // a sequence of calls (not from idle), and is read after the round
+  // back-to-back on the null stream, each timed run right after an untimed run
+  // of the same configuration, so each is timed as in a sequence of its own
+  // calls (not from idle, and not after another configuration's different
+  // load, e.g. the long, sparse tail of the unscheduled plain launch), and is
+  // read after the round
   hipEvent_t ev[2 * NC] = {};
   hipError_t e = hipSuccess;
   for (int i = 0; i < 2 * NC && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
@@ -2238,6 +2241,8 @@ int ai_tune(const ai_params* p, const double* y0, int64_t n, int64_t ld, double 
     for (int i = 0; i < NC; ++i) {
       const int32_t k = candidates[i];
       if (general && (k & 0xf) != AI_KERNEL_PLAIN) continue;  // other exponents: plain only
+      rc = ai_integrate_async(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs, k, nullptr);
+      if (rc < 0) break;
       (void)hipEventRecord(ev[2 * i], nullptr);
       rc = ai_integrate_async(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs, k, nullptr);
       if (rc < 0) break;

@@ -42,14 +42,14 @@ constexpr unsigned AI_ORDER_CODES = 1u << AI_ORDER_CODE_BITS;
 // predicts, fading to none beyond 2000 a0.  The analytic prediction adds that
 // span for a close pass, tapered linearly between the two radii (a generous
 // estimate: starting such a trajectory early costs little, starting it late
-// can end the launch late).
+// can end the launch late).  The sampled prediction adds it too.
 constexpr double AI_ORDER_CLOSE_R_IN = 500.0;    // a0
 constexpr double AI_ORDER_CLOSE_R_OUT = 2000.0;  // a0
 constexpr double AI_ORDER_CLOSE_PERIODS = 8.0;   // RF periods
 
 struct ai_order_model {
   float horizon;   // tmax - t0
-  float close_span;  // analytic: AI_ORDER_CLOSE_PERIODS RF periods (0 for a static trap)
+  float close_span;  // AI_ORDER_CLOSE_PERIODS RF periods (0 for a static trap)
   float r_exit2;   // sampled: r_exit^2 (1 + 2^-12)
   float dt;        // sampled: sample spacing, one RF period / AI_ORDER_SAMPLES
   int periods;     // sampled: periods searched, min(ceil(horizon / period), AI_ORDER_MAX_PERIODS)

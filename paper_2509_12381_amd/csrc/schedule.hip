@@ -34,6 +34,43 @@ __device__ __forceinline__ void ion_secular(const ai_order_model& M, const doubl
   }
 }
 
+// The span a close pass adds to a trajectory that exits at t (see
+// AI_ORDER_CLOSE_* in schedule.h): the closest approach of the atom's
+// straight line to the ion's secular orbit before t, by Newton steps on
+// d/dt |d|^2 = 0 from the closest approach of the initial relative motion,
+// kept within [0, t].
+__device__ float close_pass_span(const double* xi, const double* vi, const double* xa,
+                                 const double* va, const ai_order_model& M, double t) {
+  if (!(M.close_span > 0.0f) || !(t > 0.0)) return 0.0f;
+  double d0v = 0.0, uu = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double u = va[k] - vi[k];
+    d0v += (xa[k] - xi[k]) * u;
+    uu += u * u;
+  }
+  double tc = uu > 0.0 ? fmin(fmax(-d0v / uu, 0.0), t) : 0.0;
+  double r2c = 0.0;
+  for (int it = 0; it < 4; ++it) {
+    double x[3], v[3];
+    ion_secular(M, xi, vi, tc, x, v);
+    double f1 = 0.0, f2 = 0.0;
+    r2c = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double w = M.secular_omega[k];
+      const double dk = xa[k] + va[k] * tc - x[k], uk = va[k] - v[k];
+      r2c += dk * dk;
+      f1 += dk * uk;
+      f2 += uk * uk + dk * w * w * x[k];
+    }
+    if (f2 > 0.0) tc = fmin(fmax(tc - f1 / f2, 0.0), t);
+  }
+  const double frac =
+      (AI_ORDER_CLOSE_R_OUT - sqrt(r2c)) / (AI_ORDER_CLOSE_R_OUT - AI_ORDER_CLOSE_R_IN);
+  return M.close_span * (float)fmin(fmax(frac, 0.0), 1.0);
+}
+
 // Analytic duration (see schedule.h): the straight-line exit of the atom from
 // the sphere of radius r_exit about the trap centre, refined by Newton steps
 // against the ion's secular orbit.
@@ -81,39 +118,7 @@ __device__ float analytic_duration(const double* __restrict__ y0, long long ld, 
       if (tn > 0.5 * ts && tn < 2.0 * ts) t = tn;
     }
   }
-  // closest approach to the ion's secular orbit before the exit: Newton steps
-  // on d/dt |d|^2 = 0 from the closest approach of the initial relative
-  // motion, kept within [0, t]
-  float close = 0.0f;
-  if (M.close_span > 0.0f && t > 0.0) {
-    double d0v = 0.0, uu = 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double u = va[k] - vi[k];
-      d0v += (xa[k] - xi[k]) * u;
-      uu += u * u;
-    }
-    double tc = uu > 0.0 ? fmin(fmax(-d0v / uu, 0.0), t) : 0.0;
-    double r2c = 0.0;
-    for (int it = 0; it < 4; ++it) {
-      double x[3], v[3];
-      ion_secular(M, xi, vi, tc, x, v);
-      double f1 = 0.0, f2 = 0.0;
-      r2c = 0.0;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double w = M.secular_omega[k];
-        const double dk = xa[k] + va[k] * tc - x[k], uk = va[k] - v[k];
-        r2c += dk * dk;
-        f1 += dk * uk;
-        f2 += uk * uk - dk * (-w * w * x[k]);
-      }
-      if (f2 > 0.0) tc = fmin(fmax(tc - f1 / f2, 0.0), t);
-    }
-    const double rc = sqrt(r2c);
-    const double frac = (AI_ORDER_CLOSE_R_OUT - rc) / (AI_ORDER_CLOSE_R_OUT - AI_ORDER_CLOSE_R_IN);
-    close = M.close_span * (float)fmin(fmax(frac, 0.0), 1.0);
-  }
+  const float close = close_pass_span(xi, vi, xa, va, M, t);
   const float tf = (float)t + close;  // inf for an atom at rest; NaN sorts anywhere
   return tf < horizon ? (tf > 0.0f ? tf : 0.0f) : horizon;
 }
@@ -198,6 +203,7 @@ __device__ float sampled_duration(const double* __restrict__ y0, long long ld, l
     const float line = disc > 0.0 && vv > 0.0 ? (float)((sqrt(disc) - xv) / vv) : horizon;
     t_exit = fmaxf(span, line);
   }
+  t_exit += close_pass_span(xi, vi, xa, va, M, (double)t_exit);
   return t_exit < horizon ? t_exit : horizon;  // NaN sorts anywhere
 }
 
