@@ -38,37 +38,52 @@ __device__ __forceinline__ void ion_secular(const ai_order_model& M, const doubl
 // AI_ORDER_CLOSE_* in schedule.h): the closest approach of the atom's
 // straight line to the ion's secular orbit before t, by Newton steps on
 // d/dt |d|^2 = 0 from the closest approach of the initial relative motion,
-// kept within [0, t].
-__device__ float close_pass_span(const double* xi, const double* vi, const double* xa,
-                                 const double* va, const ai_order_model& M, double t) {
-  if (!(M.close_span > 0.0f) || !(t > 0.0)) return 0.0f;
-  double d0v = 0.0, uu = 0.0;
+// kept within [0, t].  Single precision: the radii that matter are hundreds to
+// thousands of a0, positions at most ~1e6 a0.
+__device__ float close_pass_span(const double* xi_d, const double* vi_d, const double* xa_d,
+                                 const double* va_d, const ai_order_model& M, double t_d) {
+  if (!(M.close_span > 0.0f) || !(t_d > 0.0)) return 0.0f;
+  const float t = (float)t_d;
+  float xi[3], vi[3], xa[3], va[3], w[3];
+  float d0v = 0.0f, uu = 0.0f;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const double u = va[k] - vi[k];
+    xi[k] = (float)xi_d[k];
+    vi[k] = (float)vi_d[k];
+    xa[k] = (float)xa_d[k];
+    va[k] = (float)va_d[k];
+    w[k] = (float)M.secular_omega[k];
+    const float u = va[k] - vi[k];
     d0v += (xa[k] - xi[k]) * u;
     uu += u * u;
   }
-  double tc = uu > 0.0 ? fmin(fmax(-d0v / uu, 0.0), t) : 0.0;
-  double r2c = 0.0;
+  float tc = uu > 0.0f ? fminf(fmaxf(-d0v / uu, 0.0f), t) : 0.0f;
+  float r2c = 0.0f;
   for (int it = 0; it < 4; ++it) {
-    double x[3], v[3];
-    ion_secular(M, xi, vi, tc, x, v);
-    double f1 = 0.0, f2 = 0.0;
-    r2c = 0.0;
+    float f1 = 0.0f, f2 = 0.0f;
+    r2c = 0.0f;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double w = M.secular_omega[k];
-      const double dk = xa[k] + va[k] * tc - x[k], uk = va[k] - v[k];
+      float x, v;
+      if (w[k] > 0.0f) {
+        float sn, cs;
+        sincosf(w[k] * tc, &sn, &cs);
+        x = xi[k] * cs + vi[k] / w[k] * sn;
+        v = vi[k] * cs - xi[k] * w[k] * sn;
+      } else {
+        x = xi[k] + vi[k] * tc;
+        v = vi[k];
+      }
+      const float dk = xa[k] + va[k] * tc - x, uk = va[k] - v;
       r2c += dk * dk;
       f1 += dk * uk;
-      f2 += uk * uk + dk * w * w * x[k];
+      f2 += uk * uk + dk * w[k] * w[k] * x;
     }
-    if (f2 > 0.0) tc = fmin(fmax(tc - f1 / f2, 0.0), t);
+    if (f2 > 0.0f) tc = fminf(fmaxf(tc - f1 / f2, 0.0f), t);
   }
-  const double frac =
-      (AI_ORDER_CLOSE_R_OUT - sqrt(r2c)) / (AI_ORDER_CLOSE_R_OUT - AI_ORDER_CLOSE_R_IN);
-  return M.close_span * (float)fmin(fmax(frac, 0.0), 1.0);
+  const float frac = (float)((AI_ORDER_CLOSE_R_OUT - (double)sqrtf(r2c)) /
+                             (AI_ORDER_CLOSE_R_OUT - AI_ORDER_CLOSE_R_IN));
+  return M.close_span * fminf(fmaxf(frac, 0.0f), 1.0f);
 }
 
 // Analytic duration (see schedule.h): the straight-line exit of the atom from
