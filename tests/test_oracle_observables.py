@@ -126,3 +126,112 @@ def test_ensemble_argument_checks(aio):
         assert aio.integrate(dataclasses.replace(s, **change), y0, **ok)[2] == aio.EINVAL
     assert aio.integrate(s, y0, **dict(ok, rtol=1e-17))[2] == aio.WRTOL
     assert aio.integrate(s, np.zeros((12, 0)), **ok)[2] == aio.OK
+
+
+# ---- closed forms for the lifetime and the position at the first bounce ----
+#
+# With the trap off and the total momentum zero, the pair's relative
+# coordinate d = x_ion - x_atom moves in V(r) with the reduced mass
+# mu = m_ion m_atom / M, M = m_ion + m_atom, while the centre of mass X stays
+# put; so x_ion = X + (m_atom / M) d.  Started at rest at an outer turning
+# point r_out of a bound energy E < 0, r oscillates between the inner turning
+# point r_in (a bounce: inside r_bounce = 20 a0) and r_out with the period
+#   T_r = 2 int_{r_in}^{r_out} dr / sqrt(2 (E - V(r)) / mu),
+# evaluated by quadrature.  Inner turning points fall at (j + 1/2) T_r, so over
+# [0, K T_r] there are K bounces, the lifetime (first to last bounce, Sec. 4.1)
+# is (K - 1) T_r and the ion sits at |X + (m_atom / M) r_in e| at the first
+# one.  The integrator samples a bounce at its first accepted step after the
+# turning point, so each bounce time is late by less than one local step
+# (about T_r / 130 at RelTol 1e-10 here).
+
+def _no_trap(r_exit):
+    return dataclasses.replace(W.liyb_system(), a=(0.0, 0.0, 0.0), q=(0.0, 0.0, 0.0),
+                               omega_rf=0.0, r_exit=r_exit)
+
+
+def _potential(s):
+    return lambda r: -s.Cn / r**s.n + s.Cm / r**s.m
+
+
+def _bound_orbit(s, E):
+    from scipy import integrate, optimize
+    V = _potential(s)
+    mu = s.m_ion * s.m_atom / (s.m_ion + s.m_atom)
+    r_e = (s.m * s.Cm / (s.n * s.Cn)) ** (1.0 / (s.m - s.n))  # minimum of V
+    r_in = optimize.brentq(lambda r: V(r) - E, 0.5 * r_e, r_e, xtol=1e-15, rtol=1e-15)
+    r_out = optimize.brentq(lambda r: V(r) - E, r_e, 100.0 * r_e, xtol=1e-15, rtol=1e-15)
+
+    def dt(th):  # r = r_in + (r_out - r_in)(1 - cos th)/2 removes both endpoint singularities
+        r = r_in + 0.5 * (r_out - r_in) * (1.0 - math.cos(th))
+        return 0.5 * (r_out - r_in) * math.sin(th) / math.sqrt(max(2.0 * (E - V(r)) / mu, 1e-300))
+
+    period = 2.0 * integrate.quad(dt, 0.0, math.pi, epsabs=0.0, epsrel=1e-13, limit=200)[0]
+    return r_in, r_out, period
+
+
+@pytest.mark.parametrize("K", [2, 5, 12])
+@pytest.mark.parametrize("offset", [0.0, 300.0])
+def test_bound_oscillation_lifetime_and_position(aio, K, offset):
+    s = _no_trap(0.0)                        # no escape exit: the pair stays bound
+    M = s.m_ion + s.m_atom
+    De = 4.1e-3                              # well depth of C4 = 82, C8 = 4.1e5
+    r_in, r_out, T_r = _bound_orbit(s, -0.5 * De)
+    assert r_in < s.r_bounce < r_out or r_out < s.r_bounce
+    e = np.array([0.6, 0.0, 0.8])
+    X = offset * e                           # centre of mass, on the axis of motion
+    y0 = np.zeros(12)
+    y0[0:3] = X + (s.m_atom / M) * r_out * e  # ion
+    y0[6:9] = X - (s.m_ion / M) * r_out * e   # atom, both at rest
+    yf, ob, rc = aio.integrate_one(s, 0.0, K * T_r, y0, 1e-10, 1e-12)
+    assert rc == 0 and ob[O["status"]] == W.ST_TMAX
+    steps_per_period = ob[O["nsteps"]] / K
+    assert ob[O["bounces"]] == K
+    # the two sampled bounce times are each late by less than a local step
+    lifetime = ob[O["lifetime"]]
+    expect = (K - 1) * T_r if K >= 2 else 0.0
+    assert abs(lifetime - expect) < 2.0 * T_r / steps_per_period, (lifetime, expect, T_r)
+    # wrong definitions miss by about T_r / 2 (from t0) or T_r (bounces x T_r)
+    pos = ob[O["position"]]
+    pin = np.linalg.norm(X + (s.m_atom / M) * r_in * e)
+    # r at the sampled step exceeds r_in by a relative ~1e-5 at most here
+    assert abs(pos - pin) < 1e-4 * (s.m_atom / M) * r_in, (pos, pin)
+    # |x_atom| or r itself would be 8.5 a0 off
+    assert abs(pos - np.linalg.norm(X - (s.m_ion / M) * r_in * e)) > 5.0
+    # min distance is the inner turning point, sampled at accepted steps
+    assert r_in <= ob[O["rmin"]] < r_in * (1.0 + 1e-4)
+
+
+@pytest.mark.parametrize("T_atom", [1e-3, 1e-5])
+@pytest.mark.parametrize("side", [1.0, -1.0])
+def test_head_on_position_of_displaced_ion(aio, T_atom, side):
+    # Trap off, ion at rest at X0 = side 300 a0 u, atom at X0 + r0 u moving
+    # towards it at v0 (Sec. 2.1 head-on initial conditions, displaced).  The
+    # centre of mass moves at -(m_atom / M) v0 u and the relative coordinate
+    # falls from r0 to the inner turning point r_in(E) of E = mu v0^2 / 2 + V(r0)
+    # in the time t_b = int_{r_in}^{r0} dr / sqrt(2 (E - V) / mu); so at the
+    # bounce x_ion = X0 + (m_atom / M)(r0 - v0 t_b - r_in) u.
+    from scipy import integrate, optimize
+    s = _no_trap(5000.0)
+    M = s.m_ion + s.m_atom
+    mu = s.m_ion * s.m_atom / M
+    V = _potential(s)
+    r0, th, ph = 5000.0, 0.4, 1.1
+    v0 = math.sqrt(3.0 * W.KB * T_atom / s.m_atom)
+    E = 0.5 * mu * v0 * v0 + V(r0)
+    r_in = optimize.brentq(lambda r: V(r) - E, 5.0, 10.0, xtol=1e-15, rtol=1e-15)
+    t_b = integrate.quad(lambda w: 2.0 * w / math.sqrt(2.0 * (E - V(r_in + w * w)) / mu),
+                         0.0, math.sqrt(r0 - r_in), epsabs=0.0, epsrel=1e-12, limit=400)[0]
+    u = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+    X0 = side * 300.0 * u
+    y0 = W.head_on_state(s, r0, T_atom, th, ph)
+    y0[0:3] += X0
+    y0[6:9] += X0
+    _, ob, rc = aio.integrate_one(s, 0.0, 1e13, y0, 1e-10, 1e-12)
+    assert rc == 0 and ob[O["status"]] == W.ST_ESCAPED and ob[O["bounces"]] == 1
+    assert ob[O["lifetime"]] == 0.0          # one bounce is no complex
+    recoil = (s.m_atom / M) * (r0 - v0 * t_b - r_in)
+    pin = np.linalg.norm(X0 + recoil * u)
+    # the bounce is sampled within a step of t_b: the ion moves ~1e-6 a0 in it
+    assert abs(ob[O["position"]] - pin) < 1e-4, (ob[O["position"]], pin)
+    # the atom sits r_in from the ion: |x_atom| would be ~8.5 a0 off
+    assert abs(ob[O["position"]] - np.linalg.norm(X0 + (recoil - r_in) * u)) > 5.0
