@@ -161,6 +161,18 @@ def full_ensemble() -> Workload:
     return thermal_workload(1 << 20, 0, name="liyb-thermal-1M")
 
 
+def cold_collision_workload(n: int, seed: int = 11) -> Workload:
+    """An ensemble that forms many complexes, for distribution tests: a 10 uK
+    atom aimed with b_max = 1,500 a0 (a few Langevin radii) from R0 = 2e4 a0
+    at an ion cooled to 0.1 uK, otherwise the 1,024-trajectory configuration's
+    system and tolerances.  About 5.5% of the trajectories form a complex
+    (two or more bounces; 906 of 16,384 for seed 11), mostly of two or three
+    bounces with lifetimes below a few RF periods."""
+    wl = thermal_workload(n, seed, T_atom=1e-5, name=f"cold-collisions-n{n}")
+    system = dataclasses.replace(wl.system, r_exit=2e4)
+    return dataclasses.replace(wl, system=system, R0=2e4, b_max=1500.0, T_ion=1e-7)
+
+
 # The batched grid: collision (atom) temperatures log-spaced over 10 uK .. 10 mK
 # and Paul-trap q values (a = 0); ensemble sizes log-uniform in [1024, 262144].
 BATCH_T_ATOM = tuple(float(t) for t in np.logspace(-5.0, -2.0, 8))

@@ -117,15 +117,54 @@ def _report(tag, aio, system, gob, oob, gfin, ofin, direct):
     return rel, raw, same_steps
 
 
-def _check_observables(gob, oob, gfin, sel, tol=1e-6):
-    for name, factor in (("dist", 1.0), ("rmin", 1.0), ("ke", 2.5)):
-        g, o = gob[O[name], sel], oob[O[name], sel]
-        assert np.max(np.abs(g - o) / np.abs(o)) <= factor * tol, name
-    speed = np.linalg.norm(gfin[9:12, sel], axis=0)
-    assert np.max(np.abs(gob[O["angle"], sel] - oob[O["angle"], sel])) <= 2 * tol, "angle"
-    m_atom = W.liyb_system().m_atom
-    dt = np.abs(gob[O["transfer"], sel] - oob[O["transfer"], sel])
-    assert np.max(dt / (m_atom * speed)) <= 2 * tol, "transfer"
+def _rel(g, o):
+    return np.abs(g - o) / np.maximum(np.abs(o), 1e-300)
+
+
+def _check_observables(tag, system, gob, oob, gfin, aligned, sel, tol=1e-6):
+    """Every observable plane (Sec. 4.1) per trajectory on the trajectories
+    `sel` (non-chaotic, direct: at most one bounce).  Counts, statuses and
+    bounces must be equal (step and failure counts on >= 99%: a rounding
+    difference can flip one error test); the end time carries the step
+    sizes' rounding noise; dist and rmin (sampled at the same steps) carry the
+    state's relative difference; the final ion kinetic energy is compared
+    with the time-aligned oracle state (the ion's velocity oscillates with the
+    trap during the end-time offset), at twice the state bar; the atom flies
+    free at the end, so angle and transfer are insensitive to the end time and
+    compared as an absolute difference in units of |v_atom|; position (at a
+    first bounce) and the next step size agree to the state bar and to the
+    rounding noise of the error estimate."""
+    n = int(sel.sum())
+    va0 = np.linalg.norm(gfin[9:12, sel], axis=0)
+    aligned_ke = 0.5 * system.m_ion * np.sum(aligned[3:6, sel] ** 2, axis=0)
+    one = sel & (oob[O["bounces"]] == 1)
+    rows = {
+        "status": np.mean(gob[O["status"], sel] == oob[O["status"], sel]),
+        "bounces": np.mean(gob[O["bounces"], sel] == oob[O["bounces"], sel]),
+        "nsteps": np.mean(gob[O["nsteps"], sel] == oob[O["nsteps"], sel]),
+        "nfailed": np.mean(gob[O["nfailed"], sel] == oob[O["nfailed"], sel]),
+        "tend": _rel(gob[O["tend"], sel], oob[O["tend"], sel]).max(),
+        "dist": _rel(gob[O["dist"], sel], oob[O["dist"], sel]).max(),
+        "rmin": _rel(gob[O["rmin"], sel], oob[O["rmin"], sel]).max(),
+        "ke": _rel(gob[O["ke"], sel], aligned_ke).max(),
+        "angle": (np.abs(gob[O["angle"], sel] - oob[O["angle"], sel])).max(),
+        "transfer": (np.abs(gob[O["transfer"], sel] - oob[O["transfer"], sel])
+                     / (system.m_atom * va0)).max(),
+        "position": _rel(gob[O["position"], one], oob[O["position"], one]).max() if one.any() else 0.0,
+        "lifetime": np.abs(gob[O["lifetime"], sel] - oob[O["lifetime"], sel]).max(),
+        "hnext_p99": np.quantile(_rel(gob[O["hnext"], sel], oob[O["hnext"], sel]), 0.99),
+    }
+    print(f"[{tag} observables] compared on {n} trajectories ({int(one.sum())} with one "
+          f"bounce): " + ", ".join(f"{k} {v:.3g}" for k, v in rows.items()), flush=True)
+    assert rows["status"] == 1.0 and rows["bounces"] == 1.0
+    assert rows["nsteps"] >= 0.99 and rows["nfailed"] >= 0.99
+    assert rows["lifetime"] == 0.0            # bounces <= 1: no complex on either side
+    assert np.all(gob[O["position"], sel & (oob[O["bounces"]] == 0)] == 0.0)
+    assert rows["tend"] <= tol
+    assert rows["dist"] <= tol and rows["rmin"] <= tol and rows["position"] <= tol
+    assert rows["ke"] <= 2 * tol
+    assert rows["angle"] <= tol and rows["transfer"] <= tol
+    assert rows["hnext_p99"] <= 1e-4
 
 
 @pytest.mark.parametrize("rtol,atol", [(1e-10, 1e-12), (1e-8, 1e-10)])
@@ -145,10 +184,9 @@ def test_small_ensemble_parity(ai, torch, aio, rtol, atol):
                           direct)
     assert loose.max() <= 1e-4
     assert (gob[O["status"]] == oob[O["status"]]).mean() >= 0.99
-    # observables follow from the final state: distances carry its relative
-    # error, the kinetic energy twice that, the angle and the momentum
-    # transfer an absolute error of 1e-6 |v_atom|
-    _check_observables(gob, oob, gfin, calm & (gob[O["tend"]] == oob[O["tend"]]))
+    # every observable plane on every non-chaotic direct trajectory
+    al = aligned_oracle_state(aio, wl.system, ofin, oob, gob)
+    _check_observables(f"1k rtol={rtol}", wl.system, gob, oob, gfin, al, calm)
     # with the same step sequence the exit happens at the same step
     same_seq = calm & (gob[O["nsteps"]] == oob[O["nsteps"]])
     np.testing.assert_allclose(gob[O["tend"], same_seq], oob[O["tend"], same_seq], rtol=1e-6)
@@ -604,8 +642,50 @@ def test_full_ensemble_sampled_and_distributions(ai, torch, aio, oracle_full):
     rel, raw, same = _report("1M sample", aio, wl.system, gob[:, idx], oob, gfin[:, idx], ofin,
                              calm)
     assert rel.max() <= 1e-6 and same >= 0.99 and (raw <= 1e-6).mean() >= 0.99
+    al = aligned_oracle_state(aio, wl.system, ofin, oob, gob[:, idx])
+    _check_observables("1M sample", wl.system, gob[:, idx], oob, gfin[:, idx], al, calm)
 
     _check_distributions("1M", wl, gob, ofull)
+
+
+def test_complex_statistics_cold_collisions(ai, torch, aio):
+    """Complex formation where it is frequent: the cold-collision ensemble
+    (10 uK atoms, b_max 1,500 a0; ~900 complexes in 16,384 trajectories).
+    Complexes are chaotic (a 1-ulp change of y0 moves their end states by
+    O(1) and their lifetimes by up to 100% in the oracle itself), so the bar is
+    statistical: complex probability within 3 sigma (two-proportion binomial),
+    KS p > 0.01 on the lifetime of complexes, on the scattering angle and on
+    the ion position at the first bounce, and the bounce-count histogram within
+    3 sigma per count.  Between two seeds of the oracle the same statistics
+    give sigma 0.9 and KS p 0.4-0.8."""
+    from scipy import stats as st
+    wl = W.cold_collision_workload(16384)
+    y0 = wl.initial_states()
+    gfin, gob, grc = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol,
+                             "plain", schedule="longest-first")
+    ofin, oob, orc = run_oracle(aio, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
+    assert grc == orc == 0
+    cg, co = S.complexes(gob), S.complexes(oob)
+    kg, ko = int(cg.sum()), int(co.sum())
+    assert ko >= 100
+    sig = S.two_proportion_sigma(kg, wl.n, ko, wl.n)
+    p_life = st.ks_2samp(gob[O["lifetime"], cg], oob[O["lifetime"], co]).pvalue
+    p_angle = st.ks_2samp(gob[O["angle"]], oob[O["angle"]]).pvalue
+    bg, bo = gob[O["bounces"]] > 0, oob[O["bounces"]] > 0
+    p_pos = st.ks_2samp(gob[O["position"], bg], oob[O["position"], bo]).pvalue
+    hg = np.bincount(gob[O["bounces"]].astype(int), minlength=8)[:8]
+    ho = np.bincount(oob[O["bounces"]].astype(int), minlength=8)[:8]
+    hsig = max(S.two_proportion_sigma(int(a), wl.n, int(b), wl.n) for a, b in zip(hg, ho))
+    print(f"[cold collisions] complexes gpu={kg} oracle={ko} sigma={sig:.2f}; KS lifetime "
+          f"p={p_life:.3f}, angle p={p_angle:.3f}, position p={p_pos:.3f}; bounce counts "
+          f"gpu={hg.tolist()} oracle={ho.tolist()} max sigma={hsig:.2f}", flush=True)
+    assert sig <= 3.0 and hsig <= 3.0
+    assert p_life > 0.01 and p_angle > 0.01 and p_pos > 0.01
+    # direct trajectories (at most one bounce, calm by the oracle) still agree
+    # one by one
+    calm, _ = non_chaotic(aio, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, ofin, oob)
+    rel, _, same = _report("cold collisions", aio, wl.system, gob, oob, gfin, ofin, calm)
+    assert calm.sum() >= 500 and rel.max() <= 1e-6 and same >= 0.99
 
 
 # Single-precision stages (AI_FP32_STAGES).  Each stage operation rounds to a
