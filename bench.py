@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "accepted RK45 steps/s and trajectories/s per MI355X at RelTol 1e-8; p50/p99 latency"
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters.json")
 KERNEL_SYMBOL = {"persistent": "ai_persistent_kernel", "plain": "ai_plain_kernel"}
 
 
@@ -54,6 +55,45 @@ def measured_traffic(kernel: str):
     if not k or rec.get("source_digest") != source_digest():
         return None
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+
+
+def measured_counters(kernel: str):
+    """Per-launch SQ counters of `kernel` from the committed rocprofv3 summary
+    (profiles/counters.json), if it was taken on the current kernel source;
+    else None."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(KERNEL_SYMBOL[kernel])
+    if not k or rec.get("source_digest") != source_digest():
+        return None
+    return k
+
+
+def write_counters(dirs) -> dict:
+    """profiles/counters.json from rocprofv3 --pmc runs of this script (one
+    directory per pass): the mean per launch of every SQ counter, per kernel."""
+    import csv
+    import glob
+    vals = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*_counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                key = (r["Kernel_Name"], r["Dispatch_Id"], r["Counter_Name"])
+                vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+    rec = {"source_digest": source_digest(), "kernels": {}}
+    for sym in KERNEL_SYMBOL.values():
+        per = {}
+        for (k, disp, ctr), v in vals.items():
+            if f"::{sym}(" in k:
+                per.setdefault(ctr, []).append(v)
+        if per:
+            rec["kernels"][sym] = {c: sum(v) / len(v) for c, v in per.items()}
+    with open(COUNTERS_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
 
 
 def write_traffic(fetch_dir: str, write_dir: str, copy_mib: int) -> dict:
@@ -112,7 +152,7 @@ def batched_grid(binding, W, flops, torch, reps: int = 3) -> dict:
             binding.ai_integrate_async(wl.system, d, wl.t0, wl.tmax, wl.rtol, wl.atol, f, o,
                                        "plain", schedule="longest-first")
 
-    def best(fn):
+    def mean_ms(fn):
         fn()
         torch.cuda.synchronize()
         out = []
@@ -124,15 +164,15 @@ def batched_grid(binding, W, flops, torch, reps: int = 3) -> dict:
             b.record()
             torch.cuda.synchronize()
             out.append(a.elapsed_time(b))
-        return min(out)
+        return sum(out) / len(out)
 
-    t_batch = best(batched)
+    t_batch = mean_ms(batched)
     obs = [o.cpu().numpy() for *_, o in dev]
     for _ in range(reps):
         binding.ai_integrate_batch_async(items, schedule="longest-first", time_kernel=True)
     torch.cuda.synchronize()
-    t_kernel = min(binding.ai_kernel_time(back) for back in range(reps))
-    t_sep = best(separate)
+    t_kernel = sum(binding.ai_kernel_time(back) for back in range(reps)) / reps
+    t_sep = mean_ms(separate)
     n = sum(wl.n for wl, *_ in dev)
     steps = float(sum(o[W.OBS["nsteps"]].sum() for o in obs))
     flop = float(sum(flops.algorithmic_flops(o) for o in obs))
@@ -143,7 +183,8 @@ def batched_grid(binding, W, flops, torch, reps: int = 3) -> dict:
             "speedup_vs_separate": t_sep / t_batch,
             "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                         "kernel": "ai_plain_batch_kernel", "kernel_ms": t_kernel}}
+                         "kernel": "ai_plain_batch_kernel", "kernel_ms": t_kernel,
+                         "what": f"means over {reps} timed calls each (kernel: AI_TIME_KERNEL events)"}}
 
 
 def serving(binding, W, torch, count: int, workers: int = 0) -> dict:
@@ -201,20 +242,144 @@ def serving(binding, W, torch, count: int, workers: int = 0) -> dict:
             "mean_launches_in_flight": in_flight / wall, "failed_requests": len(bad)}
 
 
-def cpu_baseline(wl, y0_host, sample: int):
-    """The oracle as it stands, on the first `sample` trajectories of the same
-    ensemble, with the host threads of this process's CPU share."""
-    import oracle
+def host_facts() -> dict:
+    """The host CPU: logical CPUs online, those this process may run on, model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count()
+    return {"host_nproc": os.cpu_count(), "affinity_cpus": allowed, "cpu_model": model}
+
+
+def _rel(a, b):
     import numpy as np
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+
+def _q(x, p):
+    import numpy as np
+    return float(np.quantile(x, p)) if x.size else None
+
+
+def compare_with_oracle(oracle, W, stats, wl, y0_sub, ofin, oob, gfin, gob) -> dict:
+    """Per-observable errors of a GPU run against the oracle on the same
+    trajectories (columns of y0_sub): statuses and bounce counts, accepted-step
+    counts, and on the direct trajectories (oracle: escaped, at most one
+    bounce) the final state (block-relative, after aligning the oracle's end
+    state to the GPU's end time to first order with the paper's f) and each
+    observable plane (median and p99 relative difference; the angle as an
+    absolute difference in radians, the transfer in units of m_atom |v_atom|)."""
+    import numpy as np
+    O = W.OBS
+    direct = (oob[O["bounces"]] <= 1) & (oob[O["status"]] == W.ST_ESCAPED)
+    al = ofin.copy()
+    for i in np.nonzero(gob[O["tend"]] != oob[O["tend"]])[0]:
+        al[:, i] += oracle.force(wl.system, oob[O["tend"], i], ofin[:, i]) * (
+            gob[O["tend"], i] - oob[O["tend"], i])
+    state = stats.block_relative_difference(gfin[:, direct], al[:, direct])
+    dsteps = _rel(gob[O["nsteps"]], np.maximum(oob[O["nsteps"]], 1.0))
+    out = {"trajectories": int(y0_sub.shape[1]), "direct": int(direct.sum()),
+           "status_equal": float(np.mean(gob[O["status"]] == oob[O["status"]])),
+           "bounces_equal": float(np.mean(gob[O["bounces"]] == oob[O["bounces"]])),
+           "nsteps_equal": float(np.mean(gob[O["nsteps"]] == oob[O["nsteps"]])),
+           "nsteps_rel_max": float(dsteps.max()) if dsteps.size else None,
+           "final_state_aligned": {"median": _q(state, 0.5), "p99": _q(state, 0.99),
+                                   "max": float(state.max()) if state.size else None}}
+    speed = np.linalg.norm(ofin[9:12, direct], axis=0) * wl.system.m_atom
+    planes = {}
+    for name in ("tend", "dist", "rmin", "hnext", "ke", "angle", "transfer"):
+        g, o = gob[O[name], direct], oob[O[name], direct]
+        if name == "ke":
+            o = 0.5 * wl.system.m_ion * np.sum(al[3:6, direct] ** 2, axis=0)
+        if name == "angle":
+            d = np.abs(g - o)
+        elif name == "transfer":
+            d = np.abs(g - o) / speed
+        else:
+            d = _rel(g, o)
+        planes[name] = {"median": _q(d, 0.5), "p99": _q(d, 0.99)}
+    out["observables"] = planes
+    return out
+
+
+def distributions_vs_oracle(W, stats, gob, oob) -> dict:
+    """Complex probability (two-proportion sigma) and KS statistics of the
+    scattering angle and of the complex lifetime against the oracle."""
+    from scipy import stats as st
+    cg, co = stats.complexes(gob), stats.complexes(oob)
+    O = W.OBS
+    n = gob.shape[1]
+    out = {"complexes_gpu": int(cg.sum()), "complexes_oracle": int(co.sum()),
+           "complex_sigma": stats.two_proportion_sigma(int(cg.sum()), n, int(co.sum()), n)}
+    ks = st.ks_2samp(gob[O["angle"]], oob[O["angle"]])
+    out["ks_angle"] = {"statistic": float(ks.statistic), "p": float(ks.pvalue)}
+    if min(cg.sum(), co.sum()) >= 2:
+        ks = st.ks_2samp(gob[O["lifetime"], cg], oob[O["lifetime"], co])
+        out["ks_lifetime"] = {"statistic": float(ks.statistic), "p": float(ks.pvalue)}
+    return out
+
+
+def cpu_baseline(wl, y0_host, sample: int, runs: dict, subset: int = 4096):
+    """The oracle as it stands, on the first `sample` trajectories of the same
+    ensemble, with the host threads of this process's CPU share (the CPU
+    baseline), and what the oracle's results say about the GPU runs in `runs`
+    (name -> (final, obs) of the whole ensemble): per-observable errors on the
+    first `subset` trajectories and, when the sample is the whole ensemble, the
+    distributions."""
+    import numpy as np
+
+    import oracle
+    from paper_2509_12381_amd import stats
+    from paper_2509_12381_amd import workload as W
     threads = min(16, os.cpu_count() or 1)
     ys = np.ascontiguousarray(y0_host[:, :sample])
     t = time.perf_counter()
-    _, ob, _ = oracle.integrate(wl.system, ys, wl.t0, wl.tmax, wl.rtol, wl.atol, nthreads=threads)
+    ofin, oob, _ = oracle.integrate(wl.system, ys, wl.t0, wl.tmax, wl.rtol, wl.atol,
+                                    nthreads=threads)
     wall = time.perf_counter() - t
-    steps = float(ob[2].sum())
-    return {"value": steps / wall, "unit": "accepted steps/s", "cores": threads,
-            "kind": "oracle", "sample": f"first {sample} trajectories of the {wl.n}-trajectory "
-            f"ensemble, {wall:.1f} s wall", "trajectories_per_s": sample / wall}
+    steps = float(oob[W.OBS["nsteps"]].sum())
+    rec = {"value": steps / wall, "unit": "accepted steps/s", "cores": threads,
+           "kind": "oracle", "sample": f"first {sample} trajectories of the {wl.n}-trajectory "
+           f"ensemble, {wall:.1f} s wall", "trajectories_per_s": sample / wall, **host_facts()}
+    sub = min(subset, wl.n)
+    if sample < sub:
+        sfin, sob, _ = oracle.integrate(wl.system, np.ascontiguousarray(y0_host[:, :sub]),
+                                        wl.t0, wl.tmax, wl.rtol, wl.atol, nthreads=threads)
+    else:
+        sfin, sob = ofin[:, :sub], oob[:, :sub]
+    vs = {}
+    for name, (gfin, gob) in runs.items():
+        vs[name] = {"subset": compare_with_oracle(oracle, W, stats, wl, y0_host[:, :sub], sfin,
+                                                  sob, gfin[:, :sub], gob[:, :sub])}
+        if sample == wl.n:
+            vs[name]["distributions"] = distributions_vs_oracle(W, stats, gob, oob)
+    rec["gpu_vs_oracle"] = vs
+    return rec
+
+
+def ensemble_statistics(W, stats, ob, tmax) -> dict:
+    """Complex probability and the 64-bin scattering-angle (log10 bins on
+    [1e-10, pi]) and complex-lifetime (linear bins on [0, tmax]) histograms of
+    one ensemble's observables."""
+    import math
+    ha, _ = stats.angle_histogram(ob)
+    hl, _ = stats.lifetime_histogram(ob, tmax)
+    return {"complex_probability": stats.complex_probability(ob),
+            "complexes": int(stats.complexes(ob).sum()),
+            "angle_histogram": {"bins": "64 log10-spaced on [1e-10, pi] rad",
+                                "lo": 1e-10, "hi": math.pi, "counts": ha.tolist()},
+            "lifetime_histogram": {"bins": "64 linear on [0, tmax] (complexes only)",
+                                   "lo": 0.0, "hi": tmax, "unit": "atomic time",
+                                   "counts": hl.tolist()}}
 
 
 def main() -> int:
@@ -241,9 +406,14 @@ def main() -> int:
                     help="run a plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json from two rocprofv3 counter runs and exit")
+    ap.add_argument("--write-counters", nargs="+", metavar="PMC_DIR",
+                    help="write profiles/counters.json from rocprofv3 SQ counter runs and exit")
     args = ap.parse_args()
     if args.write_traffic:
         print(json.dumps(write_traffic(*args.write_traffic, args.copy_calibration_mib or 512)))
+        return 0
+    if args.write_counters:
+        print(json.dumps(write_counters(args.write_counters)))
         return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -256,7 +426,7 @@ def main() -> int:
     import numpy as np
     import torch
 
-    from paper_2509_12381_amd import binding, flops
+    from paper_2509_12381_amd import binding, flops, stats
     from paper_2509_12381_amd import workload as W
 
     if not torch.cuda.is_available():
@@ -312,6 +482,7 @@ def main() -> int:
     total_ms, per_ms, wall = timed(binding.KERNELS[args.kernel] | binding.TIME_KERNEL,
                                    args.steps, args.warmup)
     ob = obs.cpu().numpy()
+    fin64 = fin.cpu().numpy()
     nsteps = float(ob[W.OBS["nsteps"]].sum())
     nfailed = float(ob[W.OBS["nfailed"]].sum())
     flop = flops.algorithmic_flops(ob)
@@ -326,6 +497,7 @@ def main() -> int:
     status = np.bincount(ob[W.OBS["status"]].astype(int), minlength=6)[1:].tolist()
 
     info = binding.ai_get_kernel_info(args.kernel)
+    runs = {"fp64": (fin64, ob)}
     other = None
     if not args.no_compare:
         other = []
@@ -343,10 +515,12 @@ def main() -> int:
         k = max(1, min(args.steps, 5))
         o_total, _, _ = timed("plain", k, 1, "longest-first", 0, "fp32-stages")
         o_ms = o_total / k
+        runs["fp32-stages"] = (fin.cpu().numpy(), obs.cpu().numpy())
         other.append({"kernel": "plain", "schedule": "longest-first",
                       "precision": "fp32-stages", "ms_per_step": o_ms,
                       "accepted_steps_per_call": float(obs[W.OBS["nsteps"]].sum().item()),
-                      "timed_kernel_speedup": o_ms / ms_per_step})
+                      "timed_kernel_speedup": o_ms / ms_per_step,
+                      "ensemble": ensemble_statistics(W, stats, runs["fp32-stages"][1], wl.tmax)})
         if args.sweep_refill:
             for k_ in (1, 8, 16, 32, 64):
                 o_total, _, _ = timed("persistent", 3, 1, "longest-first", k_)
@@ -373,9 +547,21 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, y0_host, min(args.cpu_sample, wl.n))
+        cpu = cpu_baseline(wl, y0_host, min(args.cpu_sample, wl.n), runs)
 
     traffic = measured_traffic(args.kernel)
+    counters = measured_counters(args.kernel)
+    counter_rate = None
+    if counters and counters.get("SQ_INSTS_VALU") and counters.get("SQ_INSTS_VALU_FLOPS_FP64"):
+        util = counters["SQ_THREAD_CYCLES_VALU"] / (64.0 * counters["SQ_INSTS_VALU"])
+        hw_flop = 64.0 * counters["SQ_INSTS_VALU_FLOPS_FP64"] * util
+        counter_rate = {"counter_tflops": hw_flop / (kernel_ms / 1e3) / 1e12,
+                        "counter_frac": hw_flop / (kernel_ms / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                        "counter_flop_per_launch": hw_flop, "lane_utilisation": util,
+                        "valu_insts_per_launch": counters["SQ_INSTS_VALU"],
+                        "counter_what": "hardware FP64 FLOPs per launch = 64 x SQ_INSTS_VALU_FLOPS_FP64 "
+                                        "x lane utilisation (SQ_THREAD_CYCLES_VALU / 64 SQ_INSTS_VALU), "
+                                        "from profiles/counters.json, over this run's kernel_ms"}
     rec = {
         "metric": METRIC,
         "value": value,
@@ -405,9 +591,12 @@ def main() -> int:
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic, "kernel": KERNEL_SYMBOL[args.kernel],
                      "flop_per_launch": flop, "kernel_ms": kernel_ms, "call_ms": call_ms,
-                     "what": "kernel_ms: the integration kernel alone (AI_TIME_KERNEL "
-                             "events on the launch stream); call_ms: the whole call with "
-                             "the schedule and the observables"},
+                     "what": "achieved: algorithmic FLOPs (the 12-component Dormand-Prince "
+                             "attempt, 922 per attempt) over kernel_ms, the integration kernel "
+                             "alone (AI_TIME_KERNEL events on the launch stream); call_ms: the "
+                             "whole call with the schedule and the observables",
+                     **(counter_rate or {"counter_tflops": None})},
+        "ensemble": ensemble_statistics(W, stats, ob, wl.tmax),
         "kernel_info": info,
         "other_variants": other,
         "autotune": tuned,

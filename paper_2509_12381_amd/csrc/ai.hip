@@ -1898,6 +1898,79 @@ int launch_finalize(const Launch& P, double* final_state, double* obs, hipStream
   return e == hipSuccess ? AI_OK : hip_fail(e, "launch(finalize)");
 }
 
+// Pinned host staging for the launch tables that batched calls copy to the
+// device with hipMemcpyAsync.  A copy from pageable memory would have to be
+// staged by the runtime before the call returns; from pinned memory it runs
+// asynchronously, so a block is handed out again only after the event
+// recorded behind its copy on the caller's stream has completed.  Blocks are
+// kept per device and reused; their number grows only with the number of
+// copies in flight at once.
+struct PinnedBlock {
+  int device = -1;
+  char* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t copied = nullptr;  // recorded after the block's last copy
+  bool in_flight = false;
+};
+
+std::mutex g_pinned_mutex;
+std::vector<PinnedBlock*> g_pinned;
+
+// A free pinned block of at least `bytes` on device `dev` (nullptr: out of
+// memory, g_error set).
+PinnedBlock* pinned_acquire(int dev, size_t bytes) {
+  std::lock_guard<std::mutex> lock(g_pinned_mutex);
+  PinnedBlock* best = nullptr;
+  for (PinnedBlock* b : g_pinned) {
+    if (b->device != dev) continue;
+    if (b->in_flight) {
+      const hipError_t q = hipEventQuery(b->copied);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) (void)hipGetLastError();
+      b->in_flight = false;
+    }
+    if (b->cap >= bytes && (!best || b->cap < best->cap)) best = b;
+  }
+  if (!best) {
+    best = new (std::nothrow) PinnedBlock;
+    if (!best) {
+      fail(AI_ENOMEM, "pinned staging block");
+      return nullptr;
+    }
+    best->device = dev;
+    best->cap = bytes < 65536 ? 65536 : bytes;
+    hipError_t e = hipHostMalloc((void**)&best->host, best->cap, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&best->copied, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      if (best->host) (void)hipHostFree(best->host);
+      delete best;
+      fail(AI_ENOMEM, "pinned staging block: %s", hipGetErrorString(e));
+      return nullptr;
+    }
+    g_pinned.push_back(best);
+  }
+  best->in_flight = true;  // reserved until released or its copy completes
+  return best;
+}
+
+// Mark the block's copy as enqueued on s (or give the block back unused).
+hipError_t pinned_release(PinnedBlock* b, hipStream_t s, bool copied) {
+  std::lock_guard<std::mutex> lock(g_pinned_mutex);
+  if (!copied) {
+    b->in_flight = false;
+    return hipSuccess;
+  }
+  const hipError_t e = hipEventRecord(b->copied, s);
+  if (e != hipSuccess) {
+    // the copy's completion cannot be tracked: wait for it before reuse
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(s);
+    b->in_flight = false;
+  }
+  return e;
+}
+
 }  // namespace
 
 int ai_fail(int rc, const char* msg) { return fail(rc, "%s", msg); }
@@ -2299,23 +2372,33 @@ int ai_integrate_batch_async(const ai_batch_item* items, int32_t count, int32_t 
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  // the launch table: entries, then the schedule's items, in one allocation;
-  // the copy from pageable host memory is staged before hipMemcpyAsync returns
+  // the launch table: entries, then the schedule's items, in one allocation,
+  // copied from a pinned staging block that stays reserved until the copy on
+  // s has completed
   const int E = (int)entries.size();
   const size_t ebytes = (sizeof(BatchEntry) * E + 255) & ~size_t(255);
   const size_t kbytes = sizeof(ai_order_item) * E;
-  std::vector<char> host(ebytes + kbytes);
-  std::memcpy(host.data(), entries.data(), sizeof(BatchEntry) * E);
-  std::memcpy(host.data() + ebytes, keys.data(), kbytes);
+  const size_t tbytes = ebytes + kbytes;
+  PinnedBlock* stage = pinned_acquire(dev, tbytes);
+  if (!stage) return AI_ENOMEM;
+  std::memcpy(stage->host, entries.data(), sizeof(BatchEntry) * E);
+  std::memcpy(stage->host + ebytes, keys.data(), kbytes);
   char* table = nullptr;
-  if ((e = hipMallocAsync((void**)&table, host.size(), s)) != hipSuccess) {
+  if ((e = hipMallocAsync((void**)&table, tbytes, s)) != hipSuccess) {
     (void)hipGetLastError();
+    pinned_release(stage, s, false);
     return fail(AI_ENOMEM, "hipMallocAsync(batch table): %s", hipGetErrorString(e));
   }
-  if ((e = hipMemcpyAsync(table, host.data(), host.size(), hipMemcpyHostToDevice, s)) !=
+  if ((e = hipMemcpyAsync(table, stage->host, tbytes, hipMemcpyHostToDevice, s)) !=
       hipSuccess) {
+    (void)hipGetLastError();
+    pinned_release(stage, s, false);
     (void)hipFreeAsync(table, s);
     return hip_fail(e, "hipMemcpyAsync(batch table)");
+  }
+  if ((e = pinned_release(stage, s, true)) != hipSuccess) {
+    (void)hipFreeAsync(table, s);
+    return hip_fail(e, "hipEventRecord(batch table)");
   }
   BatchLaunch B;
   B.entries = (const BatchEntry*)table;
