@@ -173,6 +173,20 @@ def batched_grid(binding, W, flops, torch, reps: int = 3) -> dict:
     torch.cuda.synchronize()
     t_kernel = sum(binding.ai_kernel_time(back) for back in range(reps)) / reps
     t_sep = mean_ms(separate)
+    # the tuner's choice for this batch, and a prepared batch captured in a HIP
+    # graph and replayed
+    best_kernel, best_ms = binding.ai_tune_batch(items)
+    plan = binding.BatchPlan(items, schedule="longest-first")
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            plan.launch(stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    t_graph = mean_ms(g.replay)
+    del g
+    plan.close()
     n = sum(wl.n for wl, *_ in dev)
     steps = float(sum(o[W.OBS["nsteps"]].sum() for o in obs))
     flop = float(sum(flops.algorithmic_flops(o) for o in obs))
@@ -181,65 +195,108 @@ def batched_grid(binding, W, flops, torch, reps: int = 3) -> dict:
             "ms_per_call": t_batch, "ms_separate_launches": t_sep,
             "trajectories_per_s": n / (t_batch / 1e3), "accepted_steps_per_s": steps / (t_batch / 1e3),
             "speedup_vs_separate": t_sep / t_batch,
+            "autotune": {"best_kernel_code": best_kernel, "best_ms": best_ms,
+                         "what": "ai_tune_batch: index order, and longest-first with none, 256 "
+                                 "or 1024 four-lane trajectories, each timed after an untimed "
+                                 "run of itself (best of two rounds)"},
+            "graph_replay_ms": t_graph,
             "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                          "kernel": "ai_plain_batch_kernel", "kernel_ms": t_kernel,
                          "what": f"means over {reps} timed calls each (kernel: AI_TIME_KERNEL events)"}}
 
 
-def serving(binding, W, torch, count: int, workers: int = 0) -> dict:
-    """The serving stream: `count` requests of the Poisson stream submitted to
-    an ai_server at their arrival times (from a thread of their own), each
-    integrating its slice of the pool; latency = completion - submission of
+def serving_requests(W, torch, count: int, rate_hz: float):
+    """The first `count` requests of the serving stream (arrival times for
+    `rate_hz`): each a slice of the pool moved to its own collision temperature
+    and trap q (workload.retarget_thermal), prepared on the device before the
+    stream starts, with its own output buffers."""
+    stream = W.serving_stream(count, rate_hz=rate_hz)
+    pool_wl = W.serving_pool()
+    pool = torch.from_numpy(pool_wl.initial_states()).cuda()
+    reqs = []
+    for r in stream:
+        wl = W.serving_request_workload(r)
+        y0 = W.retarget_thermal(pool[:, r.offset:r.offset + r.n], pool_wl.system,
+                                pool_wl.T_atom, wl.system, r.T_atom).contiguous()
+        reqs.append((r, wl, y0, torch.empty_like(y0),
+                     torch.empty((W.NOBS, r.n), dtype=torch.float64, device="cuda")))
+    del pool
+    torch.cuda.synchronize()
+    return stream, reqs
+
+
+def serve_stream(binding, W, torch, reqs, srv, pace: bool) -> dict:
+    """Submit the requests to `srv` at their arrival times (pace) or all at
+    once (from a thread of their own); latency = completion - submission of
     each request, on the host's monotonic clock."""
     import queue as queue_mod
     import threading
 
     import numpy as np
-    stream = W.serving_stream(count)
-    pool = torch.from_numpy(W.serving_pool().initial_states()).cuda()
-    reqs = []
-    for r in stream:
-        y0 = pool[:, r.offset:r.offset + r.n].contiguous()
-        reqs.append((r, y0, torch.empty_like(y0),
-                     torch.empty((W.NOBS, r.n), dtype=torch.float64, device="cuda")))
-    system = W.serving_pool(1).system
-    t_end = W.serving_pool(1).tmax
-    torch.cuda.synchronize()
-    srv = binding.Server(schedule="longest-first", workers=workers)
     tickets = queue_mod.Queue()
 
     def submit_all():
         t0 = time.perf_counter()
-        for r, y0, f, o in reqs:
-            delay = t0 + r.arrival_s - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            tickets.put(srv.submit((system, y0, f, o, 0.0, t_end, r.rtol, r.atol), r.precision))
+        for r, wl, y0, f, o in reqs:
+            if pace:
+                delay = t0 + r.arrival_s - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            tickets.put(srv.submit((wl.system, y0, f, o, wl.t0, wl.tmax, r.rtol, r.atol),
+                                   r.precision))
 
     th = threading.Thread(target=submit_all)
     th.start()
     infos = [srv.wait(tickets.get()) for _ in reqs]
     th.join()
-    srv.close()
     lat = np.array([i["end_s"] - i["submit_s"] for i in infos]) * 1e3
-    wall = max(i["end_s"] for i in infos) - min(i["submit_s"] for i in infos)
+    t_first = min(i["submit_s"] for i in infos)
+    wall = max(i["end_s"] for i in infos) - t_first
     n = sum(r.n for r, *_ in reqs)
     steps = float(sum(o[W.OBS["nsteps"]].sum().item() for *_, o in reqs))
-    launches = {i["batch_id"]: (i["start_s"], i["end_s"]) for i in infos}
-    in_flight = sum(e - s for s, e in launches.values())
     bad = [i["rc"] for i in infos if i["rc"] < 0]
-    return {"workload": f"poisson-{W.SERVING_RATE_HZ:g}rps", "requests": len(reqs),
-            "workers": workers or 3,
-            "seed": W.SERVING_SEED, "stream_s": stream[-1].arrival_s,
-            "trajectories": n, "fp32_stage_requests": sum(r.precision != "fp64" for r, *_ in reqs),
-            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                           "mean": float(lat.mean()), "max": float(lat.max()),
-                           "what": "request submit to completion, host monotonic clock"},
-            "trajectories_per_s": n / wall, "accepted_steps_per_s": steps / wall,
-            "offered_trajectories_per_s": n / stream[-1].arrival_s,
-            "launches": len(launches), "mean_requests_per_launch": len(reqs) / len(launches),
-            "mean_launches_in_flight": in_flight / wall, "failed_requests": len(bad)}
+    rec = {"requests": len(reqs), "trajectories": n,
+           "fp32_stage_requests": sum(r.precision != "fp64" for r, *_ in reqs),
+           "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                          "p99": float(np.percentile(lat, 99)),
+                          "mean": float(lat.mean()), "max": float(lat.max()),
+                          "what": "request submit to completion, host monotonic clock"},
+           "wall_s": wall, "trajectories_per_s": n / wall, "accepted_steps_per_s": steps / wall,
+           "launches": len({i["batch_id"] for i in infos}),
+           "max_requests_on_gpu": max(i["batch_size"] for i in infos),
+           "failed_requests": len(bad)}
+    if pace:
+        rec["offered_trajectories_per_s"] = n / reqs[-1][0].arrival_s
+        rec["stream_s"] = reqs[-1][0].arrival_s
+    return rec
+
+
+def serving(binding, W, torch, count: int, saturate: int, launches_count: int,
+            plain_traj_per_s: float) -> dict:
+    """The serving configuration: the Poisson stream (200 requests/s, seed 2;
+    sizes, tolerances, precision, temperature and q per request) served by the
+    resident kernel (continuous batching, admission by footprint into a 4 GiB
+    slab); the first `saturate` requests again, submitted at once (the
+    sustained rate); and the first `launches_count` of the stream served by
+    batched launches for comparison."""
+    stream, reqs = serving_requests(W, torch, count, W.SERVING_RATE_HZ)
+    out = {"workload": f"poisson-{W.SERVING_RATE_HZ:g}rps", "seed": W.SERVING_SEED,
+           "mode": "resident", "slab_bytes": 4 << 30}
+    with binding.Server(mode="resident") as srv:
+        out["paced"] = serve_stream(binding, W, torch, reqs, srv, pace=True)
+        if saturate:
+            sat = serve_stream(binding, W, torch, reqs[:saturate], srv, pace=False)
+            sat["vs_plain_kernel"] = sat["trajectories_per_s"] / plain_traj_per_s
+            out["saturated"] = sat
+    if launches_count:
+        with binding.Server(schedule="longest-first") as srv:
+            out["launch_mode_paced"] = serve_stream(binding, W, torch, reqs[:launches_count], srv,
+                                                    pace=True)
+    out["plain_kernel_trajectories_per_s"] = plain_traj_per_s
+    del reqs
+    torch.cuda.empty_cache()
+    return out
 
 
 def host_facts() -> dict:
@@ -398,8 +455,12 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip timing the batched 64-ensemble grid")
-    ap.add_argument("--serving-requests", type=int, default=200,
+    ap.add_argument("--serving-requests", type=int, default=2000,
                     help="requests of the serving stream to run (0: skip)")
+    ap.add_argument("--serving-saturate", type=int, default=1000,
+                    help="requests of the stream to submit at once for the sustained rate")
+    ap.add_argument("--serving-launches", type=int, default=400,
+                    help="requests of the stream to serve by batched launches for comparison")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="trajectories the oracle baseline integrates (default: the whole ensemble)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -543,7 +604,10 @@ def main() -> int:
 
     served = None
     if args.serving_requests > 0 and args.n is None:
-        served = serving(binding, W, torch, args.serving_requests)
+        served = serving(binding, W, torch, args.serving_requests,
+                         min(args.serving_saturate, args.serving_requests),
+                         min(args.serving_launches, args.serving_requests),
+                         wl.n * args.steps / (total_ms / 1e3))
 
     cpu = None
     if not args.no_cpu_baseline:

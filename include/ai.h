@@ -112,6 +112,15 @@ enum ai_kernel {
  * the predicted duration of the longest trajectory they hold. */
 #define AI_REFILL_MIN(k) ((int32_t)(k) << 8)
 
+/* Plain kernel with AI_SCHEDULE_LONGEST_FIRST (single calls and batches),
+ * OR-ed into the kernel argument: how many of the leading positions of the
+ * longest-first order (the trajectories predicted to take longest) run four
+ * lanes each, one spatial axis per lane, so that they end sooner (the launch
+ * ends with them): code 0 = 256 (the default), 1 = none, 2 = 1024, 3 = 4096.
+ * Changes which lanes integrate a trajectory, never a result.  Ignored with
+ * AI_FP32_STAGES and by the persistent kernel. */
+#define AI_WIDE(code) ((int32_t)(code) << 16)
+
 enum ai_rc {
   AI_OK = 0,
   AI_WRTOL = 1,          /* warning: rtol below 100 eps was raised to 100 eps (as ode45 does) */
@@ -158,7 +167,8 @@ int ai_integrate_async(const ai_params *p, const double *y0, int64_t n, int64_t 
 
 /* Choose the fastest kernel configuration for an ensemble by running it: the
  * ensemble is integrated with each of AI_KERNEL_PLAIN,
- * AI_KERNEL_PLAIN | AI_SCHEDULE_LONGEST_FIRST and AI_KERNEL_PERSISTENT |
+ * AI_KERNEL_PLAIN | AI_SCHEDULE_LONGEST_FIRST | AI_WIDE(c) for c = 0, 1, 2
+ * (256, none or 1024 four-lane trajectories) and AI_KERNEL_PERSISTENT |
  * AI_SCHEDULE_LONGEST_FIRST | AI_REFILL_MIN(k) for k = 1, 16, 64 (plain only
  * for exponents other than n=4, m=8) in two rounds; a round enqueues the
  * candidates back-to-back on the null stream, each as an untimed run followed
@@ -210,6 +220,19 @@ int ai_integrate_batch_async(const ai_batch_item *items, int32_t count, int32_t 
 
 /* As ai_integrate_batch_async on the null stream, waiting for the result. */
 int ai_integrate_batch(const ai_batch_item *items, int32_t count, int32_t kernel);
+
+/* Choose the fastest configuration for a batch by running it, as ai_tune does
+ * for one ensemble: the batch is integrated with AI_KERNEL_PLAIN (index order)
+ * and with AI_KERNEL_PLAIN | AI_SCHEDULE_LONGEST_FIRST | AI_WIDE(c) for c = 1,
+ * 0, 2 (none, 256 or 1024 of the longest predicted trajectories four lanes
+ * each), in two rounds, each candidate timed right after an untimed run of
+ * itself.  Every configuration gives bitwise the same results, so the outputs
+ * hold the batch's results afterwards.  Items as for ai_integrate_batch, but no
+ * item may integrate in place.  *best_kernel and *best_ms (host) receive the
+ * fastest configuration and its time.  Blocks until done; returns AI_OK,
+ * AI_WRTOL or a negative ai_rc. */
+int ai_tune_batch(const ai_batch_item *items, int32_t count, int32_t *best_kernel,
+                  float *best_ms);
 
 /* A batch prepared once and launched many times, for callers that capture
  * the launch in a HIP graph or repeat it on the same buffers (Sec. 4.2 sweeps
@@ -270,36 +293,69 @@ int ai_trace(const ai_params *p, const double *y0, double t0, double tmax, doubl
 /* ---- Serving: a stream of integration requests ------------------------------
  *
  * The paper's ensemble call (Sec. 3.3) offered as a service: requests of
- * different systems, sizes and tolerances arrive over time and each is
- * answered as soon as its launch completes.  A server works on the device
- * that is current when it is created, with one or more workers, each a thread
- * with a stream of its own.
- * Requests are validated when submitted and queued in arrival order; whenever
- * its previous launch has finished, a worker takes every queued request (in
- * order, up to max_batch trajectories; at least one) into one
+ * different systems, sizes, tolerances and precisions arrive over time and
+ * each is answered as soon as its trajectories are done.  A server works on
+ * the device that is current when it is created.  Requests are validated when
+ * submitted and served in arrival order.  A request's results are bitwise
+ * those of ai_integrate on it alone, whatever it shares the GPU with.  The
+ * caller owns every buffer and keeps it allocated until ai_server_wait has
+ * returned the request's completion.  Two modes:
+ *
+ * AI_SERVE_RESIDENT (continuous batching): a resident kernel stays on the GPU
+ * while requests flow.  The server owns a slab of device memory (slab_bytes)
+ * and admits a request, in arrival order, once its footprint (its initial
+ * states, final states and observables, 296 bytes per trajectory rounded up
+ * to 256-byte planes) fits in the slab's free space and one of `ring` request
+ * slots is free; it copies the initial states into the slab, publishes the
+ * request to the kernel, and the kernel's waves take its trajectories as their
+ * lanes free up, next to the earlier requests' trajectories (a lane of a wave
+ * runs one trajectory of any request, with that request's constants and
+ * precision).  When the kernel has counted all of a request's trajectories
+ * done it signals the server, which copies the results out to the caller's
+ * buffers and frees the slab space.  A request may give host memory (pinned
+ * for asynchronous copies) or device memory of the server's device.  Requests
+ * must have n = 4, m = 8 (else AI_EUNSUPPORTED at submission); a request
+ * larger than the slab is refused (AI_EINVAL).  The kernel holds the GPU's
+ * wave slots while it runs: each wave exits once it has found no work for
+ * idle_ms, and the server relaunches the kernel when requests arrive again, so
+ * other work on the device waits while requests are being served.
+ *
+ * AI_SERVE_LAUNCHES: one or more workers, each a thread with a stream of its
+ * own; whenever its previous launch has finished, a worker takes every queued
+ * request (in order, up to max_batch trajectories; at least one) into one
  * ai_integrate_batch_async launch, so requests that arrive while launches run
- * share the next one, and several workers keep launches overlapping (a
- * launch's last, longest trajectories leave most of the GPU idle).  A request
- * with AI_FP32_STAGES, or with exponents other than n=4, m=8, runs alone
- * (ai_integrate_async).  A request's results are
- * bitwise those of ai_integrate on it alone, whatever it shares a launch with.
- * The caller owns every buffer and keeps it allocated until ai_server_wait has
- * returned the request's completion. */
+ * share the next one, and several workers keep launches overlapping.  A
+ * request with AI_FP32_STAGES, or with exponents other than n=4, m=8, runs
+ * alone (ai_integrate_async).  Buffers must be device memory of the server's
+ * device. */
 typedef struct ai_server ai_server;
 
+enum ai_serve_mode { AI_SERVE_LAUNCHES = 0, AI_SERVE_RESIDENT = 1 };
+
 typedef struct ai_server_config {
-  int64_t max_batch;  /* trajectories per launch, >= 0; 0 selects 2^22 */
-  int32_t schedule;   /* AI_SCHEDULE_LONGEST_FIRST or 0, for every launch */
-  int32_t workers;    /* launches in flight at once, 0 .. 16; 0 selects 3 */
+  int64_t max_batch;  /* launches: trajectories per launch, >= 0; 0 selects 2^22 */
+  int32_t schedule;   /* launches: AI_SCHEDULE_LONGEST_FIRST or 0, for every launch */
+  int32_t workers;    /* launches: launches in flight at once, 0 .. 16; 0 selects 3 */
+  int32_t mode;       /* enum ai_serve_mode */
+  int32_t ring;       /* resident: requests admitted at once, 0 .. 65536; 0 selects 1024 */
+  int64_t slab_bytes; /* resident: device memory for admitted requests, >= 0; 0 selects 4 GiB */
+  double idle_ms;     /* resident: a wave with no work exits after this long, >= 0; 0 selects 20 */
+  int32_t refill_min; /* resident: free lanes a busy wave gathers before taking more, 0 .. 64;
+                         0 selects 8 */
+  int32_t reserved;   /* 0 */
 } ai_server_config;
 
 /* Completion record of a request.  Times are seconds of the host's monotonic
- * clock (CLOCK_MONOTONIC): submitted, taken into a launch, launch completed. */
+ * clock (CLOCK_MONOTONIC): submitted; taken into a launch (resident: published
+ * to the kernel, its initial states in the slab); completed (resident: results
+ * copied out). */
 typedef struct ai_request_info {
   int32_t rc;          /* AI_OK, AI_WRTOL, or a negative ai_rc of its launch */
-  int32_t batch_size;  /* requests in its launch */
-  int64_t batch_id;    /* launches are numbered 0, 1, ... per server */
-  int64_t batch_trajectories; /* trajectories in its launch */
+  int32_t batch_size;  /* requests in its launch (resident: requests on the GPU when it was
+                          published, itself included) */
+  int64_t batch_id;    /* launches are numbered 0, 1, ... per server (resident: the kernel
+                          launch it was published to) */
+  int64_t batch_trajectories; /* trajectories in its launch (resident: of those requests) */
   double submit_s, start_s, end_s;
   char error[128];     /* ai_last_error() text of a failed launch, else "" */
 } ai_request_info;
@@ -308,11 +364,11 @@ typedef struct ai_request_info {
  * AI_EINVAL, AI_EHIP or AI_ENOMEM; *out is NULL on failure. */
 int ai_server_create(const ai_server_config *cfg, ai_server **out);
 
-/* Queue one request: item as in ai_integrate_batch (device buffers on the
- * server's device), kernel AI_KERNEL_PLAIN or AI_KERNEL_PLAIN |
- * AI_FP32_STAGES.  Validates it as ai_integrate does and returns its error
- * without queueing it, else AI_OK (or AI_WRTOL if its rtol will be raised)
- * and a ticket, unique per server.  Thread-safe. */
+/* Queue one request: item as in ai_integrate_batch (buffers as the mode
+ * allows), kernel AI_KERNEL_PLAIN or AI_KERNEL_PLAIN | AI_FP32_STAGES.
+ * Validates it as ai_integrate does and returns its error without queueing
+ * it, else AI_OK (or AI_WRTOL if its rtol will be raised) and a ticket,
+ * unique per server.  Thread-safe. */
 int ai_server_submit(ai_server *srv, const ai_batch_item *item, int32_t kernel,
                      uint64_t *ticket);
 
@@ -322,7 +378,8 @@ int ai_server_submit(ai_server *srv, const ai_batch_item *item, int32_t kernel,
  * completed yet (wait again); AI_EINVAL for a ticket it does not hold. */
 int ai_server_wait(ai_server *srv, uint64_t ticket, double timeout_s, ai_request_info *info);
 
-/* Finish every queued request, stop the worker and release the server.
+/* Finish every queued request, stop the workers (resident: the kernel) and
+ * release the server.
  * Requests not yet waited for are forgotten (their outputs are complete).  No
  * other call on the server may be in progress or follow. */
 int ai_server_destroy(ai_server *srv);

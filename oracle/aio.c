@@ -18,7 +18,11 @@
  *   force            harmonic closed form, straight-line atom, Mathieu equation
  *                    by brute force, conservation laws, head-on elastic
  *                    collision, deflection-function quadrature
- *   observables      constructed trajectories (head-on bounce, flyby)
+ *   observables      constructed trajectories (head-on bounce, flyby); the
+ *                    lifetime and the position at the first bounce against
+ *                    closed forms: a bound pair oscillating radially with the
+ *                    trap off (period by quadrature) and a head-on collision
+ *                    with a displaced ion (tests/test_oracle_observables.py)
  */
 #include "aio.h"
 

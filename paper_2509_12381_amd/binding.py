@@ -28,7 +28,7 @@ OK, WRTOL, EINVAL, EHIP, ENOMEM, EUNSUPPORTED, EAGAIN = 0, 1, -1, -2, -3, -4, -5
 # exported symbols of the C ABI, in declaration order
 SYMBOLS = ("ai_integrate", "ai_integrate_async", "ai_integrate_batch",
            "ai_integrate_batch_async", "ai_batch_plan_create", "ai_batch_plan_launch",
-           "ai_batch_plan_destroy", "ai_tune", "ai_trace", "ai_server_create",
+           "ai_batch_plan_destroy", "ai_tune", "ai_tune_batch", "ai_trace", "ai_server_create",
            "ai_server_submit", "ai_server_wait", "ai_server_destroy", "ai_kernel_time",
            "ai_get_kernel_info", "ai_last_error", "ai_nobs", "ai_version")
 
@@ -54,7 +54,12 @@ class AiBatchItem(C.Structure):
 
 
 class AiServerConfig(C.Structure):
-    _fields_ = [("max_batch", C.c_int64), ("schedule", C.c_int32), ("workers", C.c_int32)]
+    _fields_ = [("max_batch", C.c_int64), ("schedule", C.c_int32), ("workers", C.c_int32),
+                ("mode", C.c_int32), ("ring", C.c_int32), ("slab_bytes", C.c_int64),
+                ("idle_ms", C.c_double), ("refill_min", C.c_int32), ("reserved", C.c_int32)]
+
+
+SERVE_MODES = {"launches": 0, "resident": 1}   # enum ai_serve_mode
 
 
 class AiRequestInfo(C.Structure):
@@ -125,6 +130,9 @@ def load(path: str = LIB_PATH):
         lib.ai_batch_plan_destroy.restype = C.c_int
         lib.ai_tune.argtypes = args[:-1] + [C.POINTER(C.c_int32), C.POINTER(C.c_float)]
         lib.ai_tune.restype = C.c_int
+        lib.ai_tune_batch.argtypes = [C.POINTER(AiBatchItem), C.c_int32, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_float)]
+        lib.ai_tune_batch.restype = C.c_int
         lib.ai_trace.argtypes = [_P, _D, C.c_double, C.c_double, C.c_double, C.c_double,
                                  C.c_int32, C.c_int64, _D, _D, _D, _D, C.POINTER(C.c_int64)]
         lib.ai_trace.restype = C.c_int
@@ -166,13 +174,13 @@ def params(system) -> AiParams:
     return p
 
 
-def _planes(t, rows: int, name: str):
+def _planes(t, rows: int, name: str, host_ok: bool = False):
     import torch
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
     if t.dtype != torch.float64 or t.dim() != 2 or t.shape[0] != rows or not t.is_contiguous():
         raise ValueError(f"{name} must be a contiguous float64 tensor of shape ({rows}, ld)")
-    if t.device.type != "cuda":
+    if t.device.type != "cuda" and not (host_ok and t.device.type == "cpu"):
         raise ValueError(f"{name} must live on the GPU")
     return t.data_ptr(), t.shape[1]
 
@@ -224,15 +232,16 @@ def ai_integrate_async(system, y0, t0, tmax, rtol, atol, final_state, obs, kerne
                                             C.c_void_p(s.cuda_stream)))
 
 
-def batch_items(items) -> "C.Array":
+def batch_items(items, host_ok: bool = False) -> "C.Array":
     """ai_batch_item array from (system, y0, final_state, obs, t0, tmax, rtol,
-    atol[, n]) tuples; the tensors are (12, ld), (12, ld) and (AI_NOBS, ld)."""
+    atol[, n]) tuples; the tensors are (12, ld), (12, ld) and (AI_NOBS, ld),
+    on the GPU (or, with host_ok, CPU tensors: host memory)."""
     arr = (AiBatchItem * max(len(items), 1))()
     for b, it in enumerate(items):
         system, y0, final_state, obs, t0, tmax, rtol, atol = it[:8]
-        p0, ld = _planes(y0, NSTATE, "y0")
-        p1, ld1 = _planes(final_state, NSTATE, "final_state")
-        p2, ld2 = _planes(obs, NOBS, "obs")
+        p0, ld = _planes(y0, NSTATE, "y0", host_ok)
+        p1, ld1 = _planes(final_state, NSTATE, "final_state", host_ok)
+        p2, ld2 = _planes(obs, NOBS, "obs", host_ok)
         if not (ld == ld1 == ld2):
             raise ValueError("y0, final_state and obs must share the leading dimension")
         e = arr[b]
@@ -282,6 +291,14 @@ def ai_tune(system, y0, t0, tmax, rtol, atol, final_state, obs, n=None):
     return best.value, ms.value
 
 
+def ai_tune_batch(items):
+    """ai_tune_batch over batch_items(items): (best kernel code, best ms)."""
+    best = C.c_int32()
+    ms = C.c_float()
+    _check(load().ai_tune_batch(batch_items(items), len(items), C.byref(best), C.byref(ms)))
+    return best.value, ms.value
+
+
 def ai_trace(system, y0, t0, tmax, rtol, atol, capacity: int, refine: int = 1):
     """Replay one trajectory (y0: 12 device doubles) and record its path at
     `refine` points per accepted step: returns (t (capacity,), y (12, capacity),
@@ -307,16 +324,20 @@ def ai_trace(system, y0, t0, tmax, rtol, atol, capacity: int, refine: int = 1):
     return t_out[:capacity], y_out[:, :capacity], fin, obs, pts.value
 
 
-def ai_server_create(max_batch: int = 0, schedule="longest-first", workers: int = 0) -> C.c_void_p:
-    cfg = AiServerConfig(int(max_batch), SCHEDULES[schedule], int(workers))
+def ai_server_create(max_batch: int = 0, schedule="longest-first", workers: int = 0,
+                     mode="launches", ring: int = 0, slab_bytes: int = 0, idle_ms: float = 0.0,
+                     refill_min: int = 0) -> C.c_void_p:
+    cfg = AiServerConfig(int(max_batch), SCHEDULES[schedule], int(workers), SERVE_MODES[mode],
+                         int(ring), int(slab_bytes), float(idle_ms), int(refill_min), 0)
     h = C.c_void_p()
     _check(load().ai_server_create(C.byref(cfg), C.byref(h)))
     return h
 
 
 def ai_server_submit(server, item, precision="fp64") -> int:
-    """Queue one request (a batch_items tuple); returns its ticket."""
-    arr = batch_items([item])
+    """Queue one request (a batch_items tuple; a resident server also takes
+    CPU tensors, i.e. host memory); returns its ticket."""
+    arr = batch_items([item], host_ok=True)
     ticket = C.c_uint64()
     _check(load().ai_server_submit(server, arr, PRECISIONS[precision], C.byref(ticket)))
     return ticket.value
@@ -381,12 +402,17 @@ class BatchPlan:
 
 
 class Server:
-    """ai_server: requests (batch_items tuples) queued and served by batched
-    launches on the server's own stream.  The tensors of a request must stay
-    alive until wait() has returned its completion."""
+    """ai_server: requests (batch_items tuples) served by a resident kernel
+    (mode="resident": continuous batching, admission by footprint into the
+    server's device slab) or by batched launches (mode="launches").  The
+    buffers of a request must stay alive until wait() has returned its
+    completion."""
 
-    def __init__(self, max_batch: int = 0, schedule="longest-first", workers: int = 0):
-        self._h = ai_server_create(max_batch, schedule, workers)
+    def __init__(self, max_batch: int = 0, schedule="longest-first", workers: int = 0,
+                 mode="launches", ring: int = 0, slab_bytes: int = 0, idle_ms: float = 0.0,
+                 refill_min: int = 0):
+        self._h = ai_server_create(max_batch, schedule, workers, mode, ring, slab_bytes, idle_ms,
+                                   refill_min)
 
     def submit(self, item, precision="fp64") -> int:
         return ai_server_submit(self._h, item, precision)

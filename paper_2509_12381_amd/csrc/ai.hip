@@ -75,11 +75,16 @@ constexpr double P1 = 611.0 / 230400.0, P3 = -514.0 / 83475.0, P4 = 391.0 / 3840
 constexpr int WAVE = 64;
 constexpr int BLOCK = 64;  // one wave per workgroup: a finished wave frees its slot at once
 
-// Leading positions of a scheduled plain launch integrated by four lanes each
-// (16 waves).  Past position 256 of the 2^20-trajectory thermal ensemble's
-// order no trajectory needs more than 80% of the longest one's attempts, and
-// 1024 lanes are a negligible share of the launch.
-constexpr long long WIDE_TRAJECTORIES = 256;
+// Leading positions of a scheduled plain launch integrated by four lanes each,
+// by the AI_WIDE code of the kernel argument: 256 (16 waves) by default: past
+// position 256 of the 2^20-trajectory thermal ensemble's order no trajectory
+// needs more than 80% of the longest one's attempts, and 1024 lanes are a
+// negligible share of the launch; none, 1024 or 4096 on request (the tuners
+// try them).
+__host__ __device__ constexpr long long wide_trajectories(int32_t kernel) {
+  return ((kernel >> 16) & 3) == 1 ? 0 : ((kernel >> 16) & 3) == 2 ? 1024
+         : ((kernel >> 16) & 3) == 3 ? 4096 : 256;
+}
 
 // Launch constants: the system constants folded into the forms the force and
 // the controller use, computed once per call on the host, and the call's
@@ -595,7 +600,7 @@ __device__ __forceinline__ void move_into(float& dst, float src) {
 
 // Of two error components (signed value, positive scale), the one with the
 // larger ratio |value| / scale, compared by cross-multiplication; the first on
-// a tie.
+// a tie (the initial step's largest weighted derivative).
 __device__ __forceinline__ void pick(double& na, double& da, double nb, double db) {
   if (fabs(nb) * da > fabs(na) * db) {
     na = nb;
@@ -603,34 +608,41 @@ __device__ __forceinline__ void pick(double& na, double& da, double nb, double d
   }
 }
 
+// |e| / s for the error norm: the hardware reciprocal estimate (relative
+// error below 2^-23) refined by one Newton step, r (1 + (1 - s r)), to a
+// relative error below 2^-46, times |e|.  The norm's largest ratio then
+// differs from the quotients' by at most that much (ties within it may pick
+// either component, which changes the norm by no more), far below the error
+// estimate's own rounding noise.  s = inf gives NaN, which only a non-finite
+// solution can produce (the attempt then ends as non-finite either way).
+__device__ __forceinline__ double ratio(double e, double s) {
+  const double r = __builtin_amdgcn_rcp(s);
+  return fabs(e) * fma(r, fma(-s, r, 1.0), r);
+}
+
 // The error norm err = h max_c |e_c| / max(|y_c|, |ynew_c|, AbsTol/RelTol)
-// takes the largest ratio by cross-multiplication in a fixed order: for the
-// positions, and then for the velocities, the ion's and the atom's component
-// of each axis, then the axes as ((x, y), z); last the position's and the
-// velocity's maximum.  Every path uses this order (the four-lane path reduces
-// each axis on its own lane), so all select the same component.  The position
-// half is reduced before the last force evaluation, which keeps few of its
-// values live across it.  half_norm() reduces one half: e the error
-// components, y and yn the solution before and after; returns whether an e is
-// NaN.
+// over the twelve components, as a maximum of per-component ratios (exact, so
+// in any order; the paths below all take it the same way: for each half, the
+// ion's and the atom's ratio of each axis, then the axes as ((x, y), z); then
+// the position half's against the velocity half's).  The position half is
+// reduced before the last force evaluation, which keeps few of its values
+// live across it.  half_norm() reduces one half: e the error components, y
+// and yn the solution before and after; m receives the half's largest ratio;
+// returns whether an e is NaN (the maximum instructions drop NaN operands).
 template <class RE>
 __device__ __forceinline__ bool half_norm(const Ctl& K, const RE* e, const double* y,
-                                          const double* yn, double& n, double& d) {
-  double an[3], ad[3];
+                                          const double* yn, double& m) {
+  double ax[3];
   bool nan_seen = false;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    double n0 = (double)e[k], d0 = max_abs(max_abs(y[k], yn[k]), K.thr);
-    const double n1 = (double)e[3 + k], d1 = max_abs(max_abs(y[3 + k], yn[3 + k]), K.thr);
+    const double n0 = (double)e[k], n1 = (double)e[3 + k];
+    const double r0 = ratio(n0, max_abs(max_abs(y[k], yn[k]), K.thr));
+    const double r1 = ratio(n1, max_abs(max_abs(y[3 + k], yn[3 + k]), K.thr));
     nan_seen = nan_seen || (n0 != n0) || (n1 != n1);
-    pick(n0, d0, n1, d1);
-    an[k] = n0;
-    ad[k] = d0;
+    ax[k] = vmax(r0, r1);
   }
-  pick(an[0], ad[0], an[1], ad[1]);
-  pick(an[0], ad[0], an[2], ad[2]);
-  n = an[0];
-  d = ad[0];
+  m = vmax(vmax(ax[0], ax[1]), ax[2]);
   return nan_seen;
 }
 
@@ -783,15 +795,14 @@ __device__ __forceinline__ void attempt(const F& P, const Ctl& K, Lane& L) {
   const double cos7 = L.done ? cos_rf(K.omega * tnew) : cs6;
   // error norm (order in half_norm()): the position half, stage 7, the
   // velocity half, then one reciprocal
-  double pn, pd, vn7, vd7;
-  const bool nan_x = half_norm(K, ex, x, xn, pn, pd);
+  double mx, mv;
+  const bool nan_x = half_norm(K, ex, x, xn, mx);
   const double r2n = accel(P, cos7, xn, F7, dx, dy, dz);
   double ev7[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) ev7[c] = fma(E7, F7[c], ev[c]);
-  const bool nan_v = half_norm(K, ev7, v, vn, vn7, vd7);
-  pick(pn, pd, vn7, vd7);
-  const double err = (nan_x || nan_v) ? __builtin_nan("") : h * fabs(pn) * recip(pd);
+  const bool nan_v = half_norm(K, ev7, v, vn, mv);
+  const double err = (nan_x || nan_v) ? __builtin_nan("") : h * vmax(mx, mv);
   conclude_lane(K, L, t, h, tnew, err, xn, vn, F7, cs6, sn6, dx, dy, dz, r2n);
 }
 
@@ -893,8 +904,8 @@ __device__ __forceinline__ void attempt32(const Force32& P, const Ctl& K, Lane& 
   }
   // error norm in double, as in attempt(): the position half, stage 7 at tnew
   // from the new double state, the velocity half
-  double pn, pd, vn7, vd7;
-  const bool nan_x = half_norm(K, ex, x, xn, pn, pd);
+  double mx, mv;
+  const bool nan_x = half_norm(K, ex, x, xn, mx);
   const double cos7 = L.done ? cos_rf(K.omega * tnew) : cs6;
   const double dx = xn[0] - xn[3], dy = xn[1] - xn[4], dz = xn[2] - xn[5];
   {
@@ -906,9 +917,8 @@ __device__ __forceinline__ void attempt32(const Force32& P, const Ctl& K, Lane& 
   float ev7[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) ev7[c] = fmaf(E7f, F7[c], ev[c]);
-  const bool nan_v = half_norm(K, ev7, v, vn, vn7, vd7);
-  pick(pn, pd, vn7, vd7);
-  const double err = (nan_x || nan_v) ? __builtin_nan("") : h * fabs(pn) * recip(pd);
+  const bool nan_v = half_norm(K, ev7, v, vn, mv);
+  const double err = (nan_x || nan_v) ? __builtin_nan("") : h * vmax(mx, mv);
   conclude_lane(K, L, t, h, tnew, err, xn, vn, F7, cs6, sn6, dx, dy, dz, r2n);
 }
 
@@ -951,29 +961,45 @@ __device__ __forceinline__ void finish(double* yf, double* obs, long long ld, co
 // lifetime = t_last - t_first for two or more bounces, scattering angle
 // between the atom's initial and final velocity, momentum transfer
 // m_atom |v - v0|, final distance, final ion kinetic energy, smallest distance.
-__device__ __forceinline__ void finalize_one(const Launch& P, const double* __restrict__ yf,
-                                             double* __restrict__ obs, long long i) {
-  const long long ld = P.ld;
-  const double t_first = obs[AI_OBS_LIFETIME * ld + i], t_last = obs[AI_OBS_ANGLE * ld + i];
-  const double va0x = obs[AI_OBS_TRANSFER * ld + i], va0y = obs[AI_OBS_DIST * ld + i],
-               va0z = obs[AI_OBS_KE * ld + i];
-  const double rmin2 = obs[AI_OBS_RMIN * ld + i];
-  const double bounces = obs[AI_OBS_BOUNCES * ld + i];
-  double y[12];
-#pragma unroll
-  for (int c = 0; c < 12; ++c) y[c] = yf[c * ld + i];
+struct Derived {
+  double lifetime, angle, transfer, dist, ke, rmin;
+};
+
+__device__ __forceinline__ Derived derive(double t_first, double t_last, double va0x, double va0y,
+                                          double va0z, double rmin2, double bounces,
+                                          const double* y, double m_atom, double half_mi) {
   const double cx = fma(va0y, y[11], -(va0z * y[10]));
   const double cy = fma(va0z, y[9], -(va0x * y[11]));
   const double cz = fma(va0x, y[10], -(va0y * y[9]));
   const double dot = fma(va0z, y[11], fma(va0y, y[10], va0x * y[9]));
   const double dvx = y[9] - va0x, dvy = y[10] - va0y, dvz = y[11] - va0z;
   const double dx = y[0] - y[6], dy = y[1] - y[7], dz = y[2] - y[8];
-  obs[AI_OBS_LIFETIME * ld + i] = bounces >= 2.0 ? t_last - t_first : 0.0;
-  obs[AI_OBS_ANGLE * ld + i] = atan2(sqrt(fma(cz, cz, fma(cy, cy, cx * cx))), dot);
-  obs[AI_OBS_TRANSFER * ld + i] = P.m_atom * sqrt(fma(dvz, dvz, fma(dvy, dvy, dvx * dvx)));
-  obs[AI_OBS_DIST * ld + i] = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
-  obs[AI_OBS_KE * ld + i] = P.half_mi * fma(y[5], y[5], fma(y[4], y[4], y[3] * y[3]));
-  obs[AI_OBS_RMIN * ld + i] = sqrt(rmin2);
+  Derived d;
+  d.lifetime = bounces >= 2.0 ? t_last - t_first : 0.0;
+  d.angle = atan2(sqrt(fma(cz, cz, fma(cy, cy, cx * cx))), dot);
+  d.transfer = m_atom * sqrt(fma(dvz, dvz, fma(dvy, dvy, dvx * dvx)));
+  d.dist = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+  d.ke = half_mi * fma(y[5], y[5], fma(y[4], y[4], y[3] * y[3]));
+  d.rmin = sqrt(rmin2);
+  return d;
+}
+
+__device__ __forceinline__ void finalize_one(const Launch& P, const double* __restrict__ yf,
+                                             double* __restrict__ obs, long long i) {
+  const long long ld = P.ld;
+  double y[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) y[c] = yf[c * ld + i];
+  const Derived d = derive(obs[AI_OBS_LIFETIME * ld + i], obs[AI_OBS_ANGLE * ld + i],
+                           obs[AI_OBS_TRANSFER * ld + i], obs[AI_OBS_DIST * ld + i],
+                           obs[AI_OBS_KE * ld + i], obs[AI_OBS_RMIN * ld + i],
+                           obs[AI_OBS_BOUNCES * ld + i], y, P.m_atom, P.half_mi);
+  obs[AI_OBS_LIFETIME * ld + i] = d.lifetime;
+  obs[AI_OBS_ANGLE * ld + i] = d.angle;
+  obs[AI_OBS_TRANSFER * ld + i] = d.transfer;
+  obs[AI_OBS_DIST * ld + i] = d.dist;
+  obs[AI_OBS_KE * ld + i] = d.ke;
+  obs[AI_OBS_RMIN * ld + i] = d.rmin;
 }
 
 __global__ __launch_bounds__(256) void ai_finalize_kernel(Launch P, const double* __restrict__ yf,
@@ -998,6 +1024,8 @@ struct BatchLaunch {
   long long total;
   const unsigned* order;
   const unsigned* key;
+  long long wide;   // with the order: leading positions integrated four lanes each
+  int wide_waves;   // the waves at the start of the grid that hold them
 };
 
 // The ensemble holding global index j: the last entry with offset <= j.
@@ -1197,41 +1225,30 @@ __device__ __forceinline__ void attempt_wide(const F& P, double ka, double kq, c
     evi = fma(E6, F6i, fma(E5, F5i, fma(E4, F4i, fma(E3, F3i, E1 * F1i))));
     eva = fma(E6, F6a, fma(E5, F5a, fma(E4, F4a, fma(E3, F3a, E1 * F1a))));
   }
-  // error norm in the order of half_norm(): this axis's ion and atom
-  // components on this lane, the axes across the quad
-  double pn = exi, pd = max_abs(max_abs(xi, xni), K.thr);
-  int nan_here;
+  // error norm as in half_norm(): this axis's ion and atom ratios on this
+  // lane, the axes across the quad
+  int nan_here = (exi != exi) | (exa != exa);
+  double mx = vmax(ratio(exi, max_abs(max_abs(xi, xni), K.thr)),
+                   ratio(exa, max_abs(max_abs(xa, xna), K.thr)));
   {
-    const double n1 = exa, d1 = max_abs(max_abs(xa, xna), K.thr);
-    nan_here = (pn != pn) | (n1 != n1);
-    pick(pn, pd, n1, d1);
+    const double my = from_quad_lane<1>(mx), mz = from_quad_lane<2>(mx);
+    mx = vmax(vmax(from_quad_lane<0>(mx), my), mz);
   }
-  const double pny = from_quad_lane<1>(pn), pdy = from_quad_lane<1>(pd);
-  const double pnz = from_quad_lane<2>(pn), pdz = from_quad_lane<2>(pd);
-  pn = from_quad_lane<0>(pn);
-  pd = from_quad_lane<0>(pd);
-  pick(pn, pd, pny, pdy);
-  pick(pn, pd, pnz, pdz);
 
   const double cos7 = L.done ? cos_rf(K.omega * tnew) : cs6;
   const double r2n = accel_wide(P, ka, kq, cos7, xni, xna, F7i, F7a, dx, dy, dz);
 
-  double vn7 = fma(E7, F7i, evi), vd7 = max_abs(max_abs(vi, vni), K.thr);
+  const double e7i = fma(E7, F7i, evi), e7a = fma(E7, F7a, eva);
+  nan_here |= (e7i != e7i) | (e7a != e7a);
+  double mv = vmax(ratio(e7i, max_abs(max_abs(vi, vni), K.thr)),
+                   ratio(e7a, max_abs(max_abs(va, vna), K.thr)));
   {
-    const double n3 = fma(E7, F7a, eva), d3 = max_abs(max_abs(va, vna), K.thr);
-    nan_here |= (vn7 != vn7) | (n3 != n3);
-    pick(vn7, vd7, n3, d3);
+    const double my = from_quad_lane<1>(mv), mz = from_quad_lane<2>(mv);
+    mv = vmax(vmax(from_quad_lane<0>(mv), my), mz);
   }
-  const double vny = from_quad_lane<1>(vn7), vdy = from_quad_lane<1>(vd7);
-  const double vnz = from_quad_lane<2>(vn7), vdz = from_quad_lane<2>(vd7);
-  vn7 = from_quad_lane<0>(vn7);
-  vd7 = from_quad_lane<0>(vd7);
-  pick(vn7, vd7, vny, vdy);
-  pick(vn7, vd7, vnz, vdz);
-  pick(pn, pd, vn7, vd7);
   const int nan_seen =
       from_quad_lane<0>(nan_here) | from_quad_lane<1>(nan_here) | from_quad_lane<2>(nan_here);
-  const double err = nan_seen ? __builtin_nan("") : h * fabs(pn) * recip(pd);
+  const double err = nan_seen ? __builtin_nan("") : h * vmax(mx, mv);
 
   conclude(
       K, L, t, h, tnew, err, cs6, sn6, r2n,
@@ -1465,9 +1482,24 @@ __global__ __launch_bounds__(BLOCK) void ai_plain_nm_kernel(Launch P) {
 // A batch of ensembles in one index space: lane g integrates global index
 // order[g] (g without a schedule) of the ensemble that holds it, with that
 // ensemble's constants, buffers and tolerances.
+// The grid is laid out as the plain kernel's: B.wide_waves waves of four-lane
+// trajectories (positions 0 .. B.wide - 1 of the order), then one trajectory
+// per lane.
 __global__ __launch_bounds__(BLOCK) void ai_plain_batch_kernel(BatchLaunch B) {
-  const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  wave_priority_from_keys(B.key, (long long)blockIdx.x * BLOCK);
+  const long long w = blockIdx.x;
+  if (w < B.wide_waves) {
+    const long long first = w * (WAVE / 4);
+    wave_priority_from_keys(B.key, first);
+    const long long g = first + (threadIdx.x >> 2);
+    if (g >= B.wide) return;
+    const long long j = (long long)B.order[g];
+    const BatchEntry& E = B.entries[batch_entry(B.entries, B.count, j)];
+    integrate_wide<Force>(E.P, j - E.offset, (int)(threadIdx.x & 3));
+    return;
+  }
+  const long long first = B.wide + (w - B.wide_waves) * BLOCK;
+  wave_priority_from_keys(B.key, first);
+  const long long g = first + threadIdx.x;
   if (g >= B.total) return;
   const long long j = B.order ? (long long)B.order[g] : g;
   const BatchEntry& E = B.entries[batch_entry(B.entries, B.count, j)];
@@ -1644,6 +1676,295 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
   }
 }
 
+// ---- Resident serving kernel ----
+//
+// Waves that stay resident while a server publishes requests (see internal.h
+// for the protocol).  Lanes of one wave may hold trajectories of different
+// requests: every lane keeps its request's loop constants in its own
+// registers, its output addresses in LDS, and takes the double or the
+// single-precision-stage attempt as its request asks (the single-precision
+// variant's per-lane choice of integrate_one), so each trajectory's result is
+// bitwise what ai_integrate gives for its request alone.  A wave claims
+// trajectories of the oldest request with work left when enough of its lanes
+// are free, stores each finished trajectory's final state and observables
+// with stores written through to memory, then adds the finished count of each
+// request to its slot's counter; the add that reaches a request's target
+// signals its completion to the host.  Idle waves poll for new requests and
+// exit once the host asks them to stop or they have been idle for
+// idle_ticks.  Every trajectory ends (step cap, step floor, non-finite
+// check) and claims only succeed for published work, so every wave exits
+// once the host stops publishing.
+
+struct ResidentDesc {
+  Launch P;        // the request's constants; y0, yf, obs planes in the slab
+  long long seq;   // request number
+  long long target;  // done count of its ring slot once the request has completed
+  int fp32;        // single-precision stages
+};
+static_assert(sizeof(ResidentDesc) <= sizeof(ai_resident_desc), "resident descriptor size");
+constexpr int RES_DESC_WORDS = (int)((sizeof(ResidentDesc) + 7) / 8);
+static_assert(RES_DESC_WORDS <= WAVE, "one word per lane");
+constexpr int RES_BACKOFF = 64;
+
+__device__ __forceinline__ unsigned long long load_system(const uint64_t* p) {
+  return __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// A store that is written through to memory (system scope), so the server's
+// copy engine reads it once the store has completed.
+__device__ __forceinline__ void store_through(double* p, double v) {
+  __hip_atomic_store((unsigned long long*)p, (unsigned long long)__double_as_longlong(v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ Force32 force32_of(const Force& F) {
+  Force32 f;
+  f.inv_mi = (float)F.inv_mi;
+  f.inv_ma = (float)F.inv_ma;
+  f.nCn = (float)F.nCn;
+  f.mCm = (float)F.mCm;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    f.ka[k] = (float)F.ka[k];
+    f.kq[k] = (float)F.kq[k];
+  }
+  return f;
+}
+
+// The leader lane's claim: up to `want` trajectories of the oldest published
+// request with work left, as (request, first index, count); false if there
+// is none.  The claim word packs (request << 32 | claimed).  n_of(seq) gives
+// a request's size; it is only asked for the request the word names, which
+// still has unclaimed trajectories, so its descriptor is current.  Bounded: a
+// claim that keeps losing the race is given up (and retried later).
+template <class SizeOf>
+__device__ bool claim(const ai_resident_args& A, unsigned long long pub, int want, long long& seq,
+                      long long& first, int& count, SizeOf n_of) {
+  unsigned long long h =
+      __hip_atomic_load((unsigned long long*)A.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int tries = 0; tries < 256; ++tries) {
+    const unsigned long long s = h >> 32, k = h & 0xffffffffull;
+    if (s >= pub) return false;
+    const long long n = n_of((long long)s);
+    unsigned long long next;
+    long long take = 0;
+    if ((long long)k >= n) {
+      next = (s + 1) << 32;
+    } else {
+      take = n - (long long)k < want ? n - (long long)k : want;
+      // the claim that takes a request's last trajectories moves the word on
+      // to the next request, so the word never names a request whose
+      // trajectories are all claimed (and whose ring slot the server may
+      // reuse once they have finished)
+      next = (long long)k + take == n ? (s + 1) << 32 : h + (unsigned long long)take;
+    }
+    if (__hip_atomic_compare_exchange_strong((unsigned long long*)A.head, &h, next,
+                                             __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)) {
+      if (take > 0) {
+        seq = (long long)s;
+        first = (long long)k;
+        count = (int)take;
+        return true;
+      }
+      h = next;
+    }
+  }
+  return false;
+}
+
+__global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args A) {
+  __shared__ ResidentDesc lds_desc;     // descriptor of the request claimed last
+  __shared__ StartConst lds_S;
+  __shared__ double* lane_yf[WAVE];
+  __shared__ double* lane_obs[WAVE];
+  __shared__ long long lane_ld[WAVE], lane_idx[WAVE], lane_seq[WAVE], lane_target[WAVE];
+  __shared__ int lane_slot[WAVE];
+  __shared__ double lane_va0[3][WAVE], lane_m_atom[WAVE], lane_half_mi[WAVE];
+  __shared__ long long claim_info[3];   // leader's claim broadcast: seq, first, count
+  const int lane = (int)threadIdx.x;    // BLOCK == WAVE
+  Lane L;
+  Ctl K;
+  Force F;
+  double near2 = 0.0;
+  int busy = 0;
+  long long cur_seq = -1;               // wave-uniform: request in lds_desc
+  long long cur_n = 0;
+  unsigned long long idle_since = 0;
+  bool idle = false;
+  int backoff = 0;                      // attempts before the next claim
+  const int refill_min = A.refill_min;
+
+  for (;;) {
+    // integrate until enough lanes are free to refill (a wave with nothing
+    // left to run leaves at once); ended lanes wait, frozen, for their store
+    // (after a claim found nothing, wait RES_BACKOFF attempts before asking
+    // again: each look at the request count is a round trip to host memory)
+    int since = 0;
+    for (;;) {
+      if (busy && L.status == 0) {
+        if (L.fresh) begin_step(K, L);
+        const double dx = L.x[0] - L.x[3], dy = L.x[1] - L.x[4], dz = L.x[2] - L.x[5];
+        if (fma(dz, dz, fma(dy, dy, dx * dx)) < near2)
+          attempt(F, K, L);
+        else
+          attempt32(force32_of(F), K, L);
+      }
+      const unsigned long long live = __ballot(busy && L.status == 0);
+      if (live == 0ull) break;
+      ++since;
+      const int free_lanes = __popcll(~live);
+      if (free_lanes > 0 && since >= backoff && (free_lanes >= refill_min || since >= RES_BACKOFF))
+        break;
+    }
+
+    // store ended trajectories, then count them per request
+    const unsigned long long ended = __ballot(busy && L.status != 0);
+    if (ended) {
+      if (busy && L.status != 0) {
+        double* yf = lane_yf[lane];
+        double* ob = lane_obs[lane];
+        const long long ld = lane_ld[lane], i = lane_idx[lane];
+        double y[12];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          y[k] = L.x[k];
+          y[3 + k] = L.v[k];
+          y[6 + k] = L.x[3 + k];
+          y[9 + k] = L.v[3 + k];
+        }
+#pragma unroll
+        for (int c = 0; c < 12; ++c) store_through(yf + c * ld + i, y[c]);
+        const double bounces = (double)L.bounces;
+        const Derived d = derive(L.t_first, L.t_last, lane_va0[0][lane], lane_va0[1][lane],
+                                 lane_va0[2][lane], L.rmin2, bounces, y, lane_m_atom[lane],
+                                 lane_half_mi[lane]);
+        store_through(ob + AI_OBS_TEND * ld + i, L.t);
+        store_through(ob + AI_OBS_STATUS * ld + i, (double)L.status);
+        store_through(ob + AI_OBS_NSTEPS * ld + i, (double)L.nsteps);
+        store_through(ob + AI_OBS_NFAILED * ld + i, (double)L.nfailed);
+        store_through(ob + AI_OBS_BOUNCES * ld + i, bounces);
+        store_through(ob + AI_OBS_LIFETIME * ld + i, d.lifetime);
+        store_through(ob + AI_OBS_ANGLE * ld + i, d.angle);
+        store_through(ob + AI_OBS_TRANSFER * ld + i, d.transfer);
+        store_through(ob + AI_OBS_POSITION * ld + i, L.position);
+        store_through(ob + AI_OBS_DIST * ld + i, d.dist);
+        store_through(ob + AI_OBS_KE * ld + i, d.ke);
+        store_through(ob + AI_OBS_RMIN * ld + i, d.rmin);
+        store_through(ob + AI_OBS_HNEXT * ld + i, L.absh);
+      }
+      // the stores above are complete and visible before any count that
+      // includes them (release at system scope)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      unsigned long long todo = ended;
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int slot = __shfl(lane_slot[lane], leader, WAVE);
+        const unsigned long long group = __ballot(((todo >> lane) & 1ull) && lane_slot[lane] == slot);
+        if (lane == leader) {
+          const unsigned long long k = (unsigned long long)__popcll(group);
+          const unsigned long long before = __hip_atomic_fetch_add(
+              (unsigned long long*)A.done_cnt + slot, k, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM);
+          if (before + k == (unsigned long long)lane_target[lane])
+            __hip_atomic_store((unsigned long long*)A.done_seq + slot,
+                               (unsigned long long)lane_seq[lane] + 1ull, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        todo &= ~group;
+      }
+      if (busy && L.status != 0) busy = 0;
+    }
+
+    // free lanes take trajectories of the oldest request with work left
+    bool claimed_any = false;
+    for (;;) {
+      const unsigned long long freel = __ballot(!busy);
+      if (freel == 0ull) break;
+      if (lane == 0) {
+        const unsigned long long pub = __hip_atomic_load((const unsigned long long*)A.pub,
+                                                         __ATOMIC_ACQUIRE,
+                                                         __HIP_MEMORY_SCOPE_SYSTEM);
+        long long seq = -1, first = 0;
+        int count = 0;
+        const bool got = claim(A, pub, __popcll(freel), seq, first, count, [&](long long s) {
+          if (s == cur_seq) return cur_n;
+          const ResidentDesc* d = (const ResidentDesc*)&A.desc[s % A.ring];
+          return (long long)load_system((const uint64_t*)&d->P.n);
+        });
+        claim_info[0] = got ? seq : -1;
+        claim_info[1] = first;
+        claim_info[2] = count;
+      }
+      __syncthreads();
+      // what the leader acquired (the request's initial states in the slab,
+      // copied there before it was published) is visible to every lane
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+      const long long seq = claim_info[0], first = claim_info[1];
+      const int count = (int)claim_info[2];
+      __syncthreads();
+      if (seq < 0) {
+        backoff = RES_BACKOFF;
+        break;
+      }
+      backoff = 0;
+      claimed_any = true;
+      if (seq != cur_seq) {
+        // the request's descriptor, one word per lane, from host memory
+        const uint64_t* src = A.desc[seq % A.ring].w;
+        if (lane < RES_DESC_WORDS) ((unsigned long long*)&lds_desc)[lane] = load_system(src + lane);
+        __syncthreads();
+        if (lane == 0) lds_S = start_const(lds_desc.P);
+        __syncthreads();
+        cur_seq = seq;
+        cur_n = lds_desc.P.n;
+      }
+      const int e = (int)lanes_below(freel);
+      if (!busy && e < count) {
+        const Launch& P = lds_desc.P;
+        const long long i = first + e;
+        double y[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) y[c] = P.y0[c * P.ld + i];
+        K = lane_ctl(P);
+        F = lane_force(P);
+        near2 = lds_desc.fp32 ? P.near2 : INFINITY;
+        lane_yf[lane] = P.yf;
+        lane_obs[lane] = P.obs;
+        lane_ld[lane] = P.ld;
+        lane_idx[lane] = i;
+        lane_seq[lane] = lds_desc.seq;
+        lane_target[lane] = lds_desc.target;
+        lane_slot[lane] = (int)(seq % A.ring);
+        lane_va0[0][lane] = y[9];
+        lane_va0[1][lane] = y[10];
+        lane_va0[2][lane] = y[11];
+        lane_m_atom[lane] = P.m_atom;
+        lane_half_mi[lane] = P.half_mi;
+        start(F, lds_S, y, L);
+        busy = 1;
+      }
+    }
+
+    if (__ballot(busy) != 0ull) {
+      idle = false;
+      continue;
+    }
+    // nothing to run: stop if asked, or after idle_ticks without work; else
+    // wait a little and look again
+    const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+    if (claimed_any || !idle) {
+      idle = true;
+      idle_since = now;
+    }
+    int stop = 0;
+    if (lane == 0) stop = load_system(A.stop) != 0ull;
+    if (__shfl(stop, 0, WAVE)) break;
+    if (now - idle_since > (unsigned long long)A.idle_ticks) break;
+    for (int k = 0; k < 6; ++k) __builtin_amdgcn_s_sleep(127);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 
@@ -1728,16 +2049,26 @@ int device_facts(int dev, DeviceFacts** out) {
   return AI_OK;
 }
 
+// Host memory (pinned, registered or pageable), as opposed to device memory.
+bool is_host_memory(const void* ptr) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;  // unknown to the runtime: pageable host memory
+  }
+  return attr.type == hipMemoryTypeHost || attr.type == hipMemoryTypeUnregistered;
+}
+
 int validate(const ai_params* p, const double* y0, int64_t n, int64_t ld, double t0,
              double tmax, double rtol, double atol, const double* yf, const double* obs,
-             int32_t kernel) {
+             int32_t kernel, bool host_ok = false) {
   if (!p) return fail(AI_EINVAL, "params is NULL");
   if (n < 0) return fail(AI_EINVAL, "n = %lld < 0", (long long)n);
   if (ld < n) return fail(AI_EINVAL, "ld = %lld < n = %lld", (long long)ld, (long long)n);
   const int32_t base_kernel = kernel & 0xf;
   if ((base_kernel != AI_KERNEL_PLAIN && base_kernel != AI_KERNEL_PERSISTENT) ||
       (kernel & ~(0xf | AI_SCHEDULE_LONGEST_FIRST | AI_FP32_STAGES | AI_TIME_KERNEL |
-                  (0x7f << 8))) != 0 ||
+                  (0x7f << 8) | AI_WIDE(3))) != 0 ||
       ((kernel >> 8) & 0x7f) > 64)
     return fail(AI_EINVAL, "unknown kernel argument 0x%x", (unsigned)kernel);
   if ((kernel & AI_FP32_STAGES) && base_kernel != AI_KERNEL_PLAIN)
@@ -1781,6 +2112,13 @@ int validate(const ai_params* p, const double* y0, int64_t n, int64_t ld, double
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (host_ok) {
+    for (const void* ptr : {(const void*)y0, (const void*)yf, (const void*)obs})
+      if (!on_current_device(ptr, dev) && !is_host_memory(ptr))
+        return fail(AI_EINVAL, "y0, final_state and obs must be host memory or device memory "
+                               "of the current device");
+    return AI_OK;
+  }
   if (!on_current_device(y0, dev) || !on_current_device(yf, dev) || !on_current_device(obs, dev))
     return fail(AI_EINVAL, "y0, final_state and obs must be device memory of the current device");
   return AI_OK;
@@ -1910,7 +2248,9 @@ struct PinnedBlock {
   char* host = nullptr;
   size_t cap = 0;
   hipEvent_t copied = nullptr;  // recorded after the block's last copy
-  bool in_flight = false;
+  // free; reserved by a call that is filling it (its event not yet
+  // recorded); or in flight (free once `copied` has completed)
+  enum { FREE, RESERVED, IN_FLIGHT } state = FREE;
 };
 
 std::mutex g_pinned_mutex;
@@ -1922,12 +2262,12 @@ PinnedBlock* pinned_acquire(int dev, size_t bytes) {
   std::lock_guard<std::mutex> lock(g_pinned_mutex);
   PinnedBlock* best = nullptr;
   for (PinnedBlock* b : g_pinned) {
-    if (b->device != dev) continue;
-    if (b->in_flight) {
+    if (b->device != dev || b->state == PinnedBlock::RESERVED) continue;
+    if (b->state == PinnedBlock::IN_FLIGHT) {
       const hipError_t q = hipEventQuery(b->copied);
       if (q == hipErrorNotReady) continue;
       if (q != hipSuccess) (void)hipGetLastError();
-      b->in_flight = false;
+      b->state = PinnedBlock::FREE;
     }
     if (b->cap >= bytes && (!best || b->cap < best->cap)) best = b;
   }
@@ -1950,7 +2290,7 @@ PinnedBlock* pinned_acquire(int dev, size_t bytes) {
     }
     g_pinned.push_back(best);
   }
-  best->in_flight = true;  // reserved until released or its copy completes
+  best->state = PinnedBlock::RESERVED;  // until released
   return best;
 }
 
@@ -1958,7 +2298,7 @@ PinnedBlock* pinned_acquire(int dev, size_t bytes) {
 hipError_t pinned_release(PinnedBlock* b, hipStream_t s, bool copied) {
   std::lock_guard<std::mutex> lock(g_pinned_mutex);
   if (!copied) {
-    b->in_flight = false;
+    b->state = PinnedBlock::FREE;
     return hipSuccess;
   }
   const hipError_t e = hipEventRecord(b->copied, s);
@@ -1966,28 +2306,114 @@ hipError_t pinned_release(PinnedBlock* b, hipStream_t s, bool copied) {
     // the copy's completion cannot be tracked: wait for it before reuse
     (void)hipGetLastError();
     (void)hipStreamSynchronize(s);
-    b->in_flight = false;
+    b->state = PinnedBlock::FREE;
+    return e;
   }
+  b->state = PinnedBlock::IN_FLIGHT;
   return e;
+}
+
+// The plain kernels over P (P.order set or not): with a schedule, the
+// longest predicted trajectories run four lanes each.  Kernel timing events
+// around the launch if asked.
+int launch_plain(Launch& P, const ai_params* p, int32_t kernel, hipStream_t s) {
+  const long long n = P.n;
+  if (P.order && !(kernel & AI_FP32_STAGES)) {
+    const long long width = wide_trajectories(kernel);
+    P.wide = n < width ? n : width;
+    P.wide_waves = (int)((P.wide + WAVE / 4 - 1) / (WAVE / 4));
+  }
+  const long long blocks = P.wide_waves + (n - P.wide + BLOCK - 1) / BLOCK;
+  if (blocks > 0x7fffffffLL) return fail(AI_EINVAL, "n too large for one launch");
+  int rc = time_mark(kernel, true, s);
+  if (rc != AI_OK) return rc;
+  if (kernel & AI_FP32_STAGES)
+    hipLaunchKernelGGL(ai_plain32_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
+  else if (p->n != 4 || p->m != 8)
+    hipLaunchKernelGGL(ai_plain_nm_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
+  else
+    hipLaunchKernelGGL(ai_plain_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "launch(plain)");
+  return time_mark(kernel, false, s);
 }
 
 }  // namespace
 
 int ai_fail(int rc, const char* msg) { return fail(rc, "%s", msg); }
 
-int ai_check_request(const ai_batch_item* item, int32_t kernel) {
+int ai_check_request(const ai_batch_item* item, int32_t kernel, bool host_ok) {
   g_error.clear();
   if (!item) return fail(AI_EINVAL, "item is NULL");
   if ((kernel & ~AI_FP32_STAGES) != AI_KERNEL_PLAIN)
     return fail(AI_EUNSUPPORTED, "a request runs the plain kernel (kernel 0x%x)",
                 (unsigned)kernel);
   const int rc = validate(&item->params, item->y0, item->n, item->ld, item->t0, item->tmax,
-                          item->rtol, item->atol, item->final_state, item->obs, kernel);
+                          item->rtol, item->atol, item->final_state, item->obs, kernel, host_ok);
   if (rc != AI_OK) return rc;
   return item->rtol < 100.0 * 2.220446049250313e-16 ? AI_WRTOL : AI_OK;
 }
 
+void ai_resident_describe(const ai_batch_item* it, int32_t kernel, double* y0s, double* fins,
+                          double* obss, int64_t ld, uint64_t seq, uint64_t done_target,
+                          ai_resident_desc* out) {
+  std::memset(out, 0, sizeof *out);
+  ResidentDesc d;
+  std::memset(&d, 0, sizeof d);
+  const double rtol = it->rtol < 100.0 * 2.220446049250313e-16 ? 100.0 * 2.220446049250313e-16
+                                                                : it->rtol;
+  d.P = launch_constants(&it->params, it->n, ld, it->t0, it->tmax, rtol, it->atol);
+  d.P.y0 = y0s;
+  d.P.yf = fins;
+  d.P.obs = obss;
+  d.seq = (long long)seq;
+  d.target = (long long)done_target;
+  d.fp32 = (kernel & AI_FP32_STAGES) ? 1 : 0;
+  std::memcpy(out, &d, sizeof d);
+}
+
+int ai_resident_launch(const ai_resident_args* a, hipStream_t s, int64_t* waves) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  static std::mutex mu;
+  static int per_cu[64] = {};
+  int cus = 0;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return hip_fail(e, "hipDeviceGetAttribute");
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (dev < 0 || dev >= 64) return fail(AI_EHIP, "device ordinal %d out of range", dev);
+    if (per_cu[dev] == 0) {
+      int b = 0;
+      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, ai_resident_kernel, BLOCK, 0)) !=
+          hipSuccess)
+        return hip_fail(e, "occupancy(resident)");
+      per_cu[dev] = b > 0 ? b : 1;
+    }
+  }
+  const long long grid = (long long)cus * per_cu[dev];
+  hipLaunchKernelGGL(ai_resident_kernel, dim3((unsigned)grid), dim3(BLOCK), 0, s, *a);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "launch(resident)");
+  if (waves) *waves = grid;
+  return AI_OK;
+}
+
 namespace {
+
+// A batch's four-lane waves (with its longest-first order) and grid size.
+void batch_layout(BatchLaunch& B, int32_t kernel) {
+  B.wide = 0;
+  B.wide_waves = 0;
+  if (B.order) {
+    const long long width = wide_trajectories(kernel);
+    B.wide = B.total < width ? B.total : width;
+    B.wide_waves = (int)((B.wide + WAVE / 4 - 1) / (WAVE / 4));
+  }
+}
+unsigned batch_blocks(const BatchLaunch& B) {
+  return (unsigned)(B.wide_waves + (B.total - B.wide + BLOCK - 1) / BLOCK);
+}
 
 // The host side of a batched call: validated items, the launch table's
 // entries and the schedule's per-item models.
@@ -2004,7 +2430,7 @@ int prepare_batch(const ai_batch_item* items, int32_t count, int32_t kernel, int
                   BatchPrep& prep) {
   if (count < 0) return fail(AI_EINVAL, "count = %d < 0", count);
   if (count > 0 && !items) return fail(AI_EINVAL, "items is NULL");
-  if ((kernel & ~(AI_SCHEDULE_LONGEST_FIRST | extra)) != AI_KERNEL_PLAIN)
+  if ((kernel & ~(AI_SCHEDULE_LONGEST_FIRST | AI_WIDE(3) | extra)) != AI_KERNEL_PLAIN)
     return fail(AI_EUNSUPPORTED, "a batch runs the plain double kernel (kernel 0x%x)",
                 (unsigned)kernel);
   int warn = AI_OK;
@@ -2141,31 +2567,7 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
   };
 
   if ((kernel & 0xf) == AI_KERNEL_PLAIN) {
-    // with the schedule, the longest predicted trajectories run four lanes each
-    if (order && !(kernel & AI_FP32_STAGES)) {
-      P.wide = n < WIDE_TRAJECTORIES ? n : WIDE_TRAJECTORIES;
-      P.wide_waves = (int)((P.wide + WAVE / 4 - 1) / (WAVE / 4));
-    }
-    const long long blocks = P.wide_waves + (n - P.wide + BLOCK - 1) / BLOCK;
-    if (blocks > 0x7fffffffLL) {
-      release();
-      return fail(AI_EINVAL, "n too large for one launch");
-    }
-    if ((rc = time_mark(kernel, true, s)) != AI_OK) {
-      release();
-      return rc;
-    }
-    if (kernel & AI_FP32_STAGES)
-      hipLaunchKernelGGL(ai_plain32_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
-    else if (p->n != 4 || p->m != 8)
-      hipLaunchKernelGGL(ai_plain_nm_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
-    else
-      hipLaunchKernelGGL(ai_plain_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
-    if ((e = hipGetLastError()) != hipSuccess) {
-      release();
-      return hip_fail(e, "launch(plain)");
-    }
-    if ((rc = time_mark(kernel, false, s)) != AI_OK) {
+    if ((rc = launch_plain(P, p, kernel, s)) != AI_OK) {
       release();
       return rc;
     }
@@ -2293,6 +2695,8 @@ int ai_tune(const ai_params* p, const double* y0, int64_t n, int64_t ld, double 
   const int32_t candidates[] = {
       AI_KERNEL_PLAIN,
       AI_KERNEL_PLAIN | AI_SCHEDULE_LONGEST_FIRST,
+      AI_KERNEL_PLAIN | AI_SCHEDULE_LONGEST_FIRST | AI_WIDE(1),
+      AI_KERNEL_PLAIN | AI_SCHEDULE_LONGEST_FIRST | AI_WIDE(2),
       AI_KERNEL_PERSISTENT | AI_SCHEDULE_LONGEST_FIRST | AI_REFILL_MIN(1),
       AI_KERNEL_PERSISTENT | AI_SCHEDULE_LONGEST_FIRST | AI_REFILL_MIN(16),
       AI_KERNEL_PERSISTENT | AI_SCHEDULE_LONGEST_FIRST | AI_REFILL_MIN(64)};
@@ -2318,6 +2722,64 @@ int ai_tune(const ai_params* p, const double* y0, int64_t n, int64_t ld, double 
       if (rc < 0) break;
       (void)hipEventRecord(ev[2 * i], nullptr);
       rc = ai_integrate_async(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs, k, nullptr);
+      if (rc < 0) break;
+      warn = rc;
+      (void)hipEventRecord(ev[2 * i + 1], nullptr);
+      ran[i] = true;
+    }
+    if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) {
+      if (rc >= 0) rc = hip_fail(e, "hipStreamSynchronize");
+      break;
+    }
+    if (rc < 0) break;
+    for (int i = 0; i < NC; ++i) {
+      if (!ran[i]) continue;
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+      if (best < 0.0f || ms < best) {
+        best = ms;
+        *best_kernel = candidates[i];
+      }
+    }
+  }
+  for (int i = 0; i < 2 * NC; ++i)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+  if (rc < 0) return rc;
+  *best_ms = best < 0.0f ? 0.0f : best;
+  return warn;
+}
+
+int ai_tune_batch(const ai_batch_item* items, int32_t count, int32_t* best_kernel,
+                  float* best_ms) {
+  g_error.clear();
+  if (!best_kernel || !best_ms) return fail(AI_EINVAL, "best_kernel or best_ms is NULL");
+  *best_kernel = AI_KERNEL_PLAIN;
+  *best_ms = 0.0f;
+  for (int32_t b = 0; b < count && items; ++b)
+    if (items[b].n > 0 && items[b].final_state == items[b].y0)
+      return fail(AI_EINVAL, "item %d: tuning runs the batch several times: final_state must "
+                  "not be y0", b);
+  const int32_t candidates[] = {
+      AI_KERNEL_PLAIN,
+      AI_KERNEL_PLAIN | AI_SCHEDULE_LONGEST_FIRST | AI_WIDE(1),
+      AI_KERNEL_PLAIN | AI_SCHEDULE_LONGEST_FIRST,
+      AI_KERNEL_PLAIN | AI_SCHEDULE_LONGEST_FIRST | AI_WIDE(2)};
+  constexpr int NC = sizeof(candidates) / sizeof(candidates[0]);
+  // as in ai_tune: two rounds, each candidate timed right after an untimed run
+  // of itself on the null stream
+  hipEvent_t ev[2 * NC] = {};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 2 * NC && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  int rc = e == hipSuccess ? AI_OK : hip_fail(e, "hipEventCreate");
+  int warn = AI_OK;
+  float best = -1.0f;
+  for (int round = 0; round < 2 && rc >= 0; ++round) {
+    bool ran[NC] = {};
+    for (int i = 0; i < NC; ++i) {
+      rc = ai_integrate_batch_async(items, count, candidates[i], nullptr);
+      if (rc < 0) break;
+      (void)hipEventRecord(ev[2 * i], nullptr);
+      rc = ai_integrate_batch_async(items, count, candidates[i], nullptr);
       if (rc < 0) break;
       warn = rc;
       (void)hipEventRecord(ev[2 * i + 1], nullptr);
@@ -2406,6 +2868,8 @@ int ai_integrate_batch_async(const ai_batch_item* items, int32_t count, int32_t 
   B.total = total;
   B.order = nullptr;
   B.key = nullptr;
+  B.wide = 0;
+  B.wide_waves = 0;
   void* order_ws = nullptr;
   auto release = [&]() -> int {
     hipError_t fe = hipFreeAsync(table, s);
@@ -2427,13 +2891,13 @@ int ai_integrate_batch_async(const ai_batch_item* items, int32_t count, int32_t 
     B.order = order;
     B.key = key;
   }
+  batch_layout(B, kernel);
   int trc = time_mark(kernel, true, s);
   if (trc != AI_OK) {
     release();
     return trc;
   }
-  hipLaunchKernelGGL(ai_plain_batch_kernel, dim3((unsigned)((total + BLOCK - 1) / BLOCK)),
-                     dim3(BLOCK), 0, s, B);
+  hipLaunchKernelGGL(ai_plain_batch_kernel, dim3(batch_blocks(B)), dim3(BLOCK), 0, s, B);
   if ((e = hipGetLastError()) != hipSuccess) {
     release();
     return hip_fail(e, "launch(batch)");
@@ -2503,6 +2967,8 @@ int ai_batch_plan_create(const ai_batch_item* items, int32_t count, int32_t kern
   B.order = nullptr;
   B.key = nullptr;
   B.entries = nullptr;
+  B.wide = 0;
+  B.wide_waves = 0;
   if (prep.total > 0) {
     const size_t ebytes = (sizeof(BatchEntry) * E + 255) & ~size_t(255);
     const size_t kbytes = sizeof(ai_order_item) * E;
@@ -2537,6 +3003,7 @@ int ai_batch_plan_create(const ai_batch_item* items, int32_t count, int32_t kern
       B.order = order;
       B.key = key;
     }
+    batch_layout(B, kernel);
   }
   *out = pl;
   return warn;
@@ -2551,8 +3018,7 @@ int ai_batch_plan_launch(const ai_batch_plan* pl, void* stream) {
   const BatchLaunch& B = pl->launch;
   if (B.total == 0) return pl->warn;
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(ai_plain_batch_kernel, dim3((unsigned)((B.total + BLOCK - 1) / BLOCK)),
-                     dim3(BLOCK), 0, s, B);
+  hipLaunchKernelGGL(ai_plain_batch_kernel, dim3(batch_blocks(B)), dim3(BLOCK), 0, s, B);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "launch(plan)");
   hipLaunchKernelGGL(ai_finalize_batch_kernel, dim3((unsigned)((B.total + 255) / 256)), dim3(256),

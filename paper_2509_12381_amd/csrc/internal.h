@@ -2,12 +2,55 @@
 // C ABI).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include "ai.h"
 
 // Validate one request as ai_integrate validates its arguments: AI_OK,
 // AI_WRTOL (rtol below 100 eps will be raised) or a negative ai_rc with the
-// text in ai_last_error().
-int ai_check_request(const ai_batch_item* item, int32_t kernel);
+// text in ai_last_error().  host_ok: the buffers may also be host memory.
+int ai_check_request(const ai_batch_item* item, int32_t kernel, bool host_ok = false);
 
 // Set the calling thread's ai_last_error() text and return rc.
 int ai_fail(int rc, const char* msg);
+
+// ---- Resident serving kernel (ai.hip) and its host runtime (server.hip) ----
+//
+// The host publishes requests in a ring of descriptors in host-coherent
+// (fine-grained) memory and counts them in *pub; the kernel's resident waves
+// claim trajectories of the oldest published request that has work left,
+// integrate them from the server's device slab into it, and signal a request's
+// completion by writing its number + 1 into done_seq[slot] (host-coherent).
+// Device memory holds the claim word (request << 32 | claimed) and, per ring
+// slot, the cumulative count of finished trajectories.
+
+#include <stdint.h>
+
+constexpr int AI_RESIDENT_DESC_WORDS = 64;  // 512-byte descriptors
+struct ai_resident_desc {
+  uint64_t w[AI_RESIDENT_DESC_WORDS];       // filled by ai_resident_describe
+};
+
+struct ai_resident_args {
+  const ai_resident_desc* desc;  // host-coherent: ring of `ring` descriptors
+  const uint64_t* pub;           // host-coherent: requests published so far
+  const uint64_t* stop;          // host-coherent: nonzero: waves exit once idle
+  uint64_t* done_seq;            // host-coherent: per slot, last completed request + 1
+  uint64_t* head;                // device: claim word, zero at the first launch
+  uint64_t* done_cnt;            // device: per slot, finished trajectories (cumulative)
+  int32_t ring;                  // descriptor slots
+  int32_t refill_min;            // free lanes a busy wave gathers before refilling
+  int64_t idle_ticks;            // idle time (100 MHz clock) after which a wave exits
+};
+
+// Fill *out for request number seq of the ring: the item's launch constants
+// with y0, final state and observables in the slab at y0s, fins, obss (planes
+// of ld >= n doubles), and the done count of its slot on completion.  kernel:
+// AI_KERNEL_PLAIN, optionally | AI_FP32_STAGES.
+void ai_resident_describe(const ai_batch_item* item, int32_t kernel, double* y0s, double* fins,
+                          double* obss, int64_t ld, uint64_t seq, uint64_t done_target,
+                          ai_resident_desc* out);
+
+// Launch the resident kernel on s with one wave per resident slot of the
+// device; *waves receives the grid size.  AI_OK or a negative ai_rc.
+int ai_resident_launch(const ai_resident_args* a, hipStream_t s, int64_t* waves);

@@ -1,19 +1,28 @@
-// server.hip -- a stream of integration requests served by batched launches
-// (the ai_server_* entry points of ai.h; host code only).
+// server.hip -- a stream of integration requests (the ai_server_* entry
+// points of ai.h; host code only).
 //
-// Each of the server's workers owns a stream and a thread.  A worker whose
-// previous launch has completed takes every queued request, in arrival order,
-// up to max_batch trajectories, into one ai_integrate_batch_async call on its
-// stream.  Requests that arrive while launches run therefore share the next
-// one, a launch never waits for more requests to arrive, and with several
-// workers a new launch fills the SIMDs that the tail of an earlier one (its
-// longest trajectories) leaves idle.
+// Resident mode (continuous batching): one dispatcher thread admits requests
+// in arrival order into the server's device slab by footprint, copies their
+// initial states in on a stream of its own, publishes each to the resident
+// kernel (ai.hip) through a ring of descriptors in host-coherent memory, keeps
+// the kernel running (relaunching it after it has exited for lack of work),
+// watches the completion words the kernel writes, copies results out on a
+// second stream and frees the slab space.
+//
+// Launch mode: each of the server's workers owns a stream and a thread.  A
+// worker whose previous launch has completed takes every queued request, in
+// arrival order, up to max_batch trajectories, into one
+// ai_integrate_batch_async call on its stream.  Requests that arrive while
+// launches run therefore share the next one, a launch never waits for more
+// requests to arrive, and with several workers a new launch fills the SIMDs
+// that the tail of an earlier one (its longest trajectories) leaves idle.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -37,6 +46,50 @@ struct Request {
   int base_rc = AI_OK;  // AI_OK or AI_WRTOL from validation
   ai_request_info info{};
   bool done = false;
+  // resident mode
+  size_t slab_off = 0, slab_len = 0;
+  uint64_t seq = 0;
+  hipEvent_t copied_in = nullptr, copied_out = nullptr;
+};
+
+// Slab footprint of a request of n trajectories: initial states, final states
+// and observables, each plane rounded up to 256 bytes.
+size_t plane_bytes(int64_t n) { return ((size_t)n * 8 + 255) & ~size_t(255); }
+size_t footprint(int64_t n) { return (12 + 12 + AI_NOBS) * plane_bytes(n); }
+
+// First-fit allocator over [0, size) of the slab.
+struct SlabSpace {
+  std::map<size_t, size_t> free;  // offset -> length
+  void reset(size_t size) {
+    free.clear();
+    if (size) free[0] = size;
+  }
+  bool take(size_t len, size_t& off) {
+    for (auto it = free.begin(); it != free.end(); ++it) {
+      if (it->second < len) continue;
+      off = it->first;
+      const size_t rest = it->second - len;
+      free.erase(it);
+      if (rest) free[off + len] = rest;
+      return true;
+    }
+    return false;
+  }
+  void give(size_t off, size_t len) {
+    auto next = free.lower_bound(off);
+    if (next != free.end() && off + len == next->first) {
+      len += next->second;
+      next = free.erase(next);
+    }
+    if (next != free.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += len;
+        return;
+      }
+    }
+    free[off] = len;
+  }
 };
 
 using RequestPtr = std::shared_ptr<Request>;
@@ -45,10 +98,30 @@ using RequestPtr = std::shared_ptr<Request>;
 
 struct ai_server {
   int device = 0;
+  int32_t mode = AI_SERVE_LAUNCHES;
   int64_t max_batch = 0;
   int32_t schedule = 0;
-  std::vector<hipStream_t> streams;  // one per worker
-  std::vector<std::thread> workers;
+  std::vector<hipStream_t> streams;  // launches: one per worker; resident: kernel, in, out
+  std::vector<std::thread> workers;  // launches: workers; resident: the dispatcher
+
+  // resident mode
+  int32_t ring = 0;
+  int32_t refill_min = 8;
+  double idle_ms = 20.0;
+  size_t slab_bytes = 0;
+  char* slab = nullptr;                 // device
+  uint64_t* ctl = nullptr;              // host-coherent: pub, stop, done_seq[ring]
+  ai_resident_desc* desc = nullptr;     // host-coherent: ring of descriptors
+  uint64_t* dev_ctl = nullptr;          // the same two, as the device addresses them
+  ai_resident_desc* dev_desc = nullptr;
+  uint64_t* dev_words = nullptr;        // device: head, done_cnt[ring]
+  hipEvent_t kernel_done = nullptr;
+  bool kernel_running = false;
+  int64_t launches = 0;
+  SlabSpace space;                      // guarded by mu
+  std::vector<uint64_t> slot_total;     // dispatcher: cumulative done target per slot
+  std::vector<char> slot_busy;          // guarded by mu
+  uint64_t next_seq = 0;                // guarded by mu
 
   std::mutex mu;
   std::condition_variable work;  // a request was queued, or stop
@@ -61,6 +134,10 @@ struct ai_server {
 
   void run(hipStream_t stream);
   void serve(std::vector<RequestPtr>& batch, hipStream_t stream);
+  void dispatch();
+  int start_resident(const ai_server_config& c);
+  void release_resident();
+  void finish(const RequestPtr& r, int rc, const std::string& error);
   void stop();
 };
 
@@ -153,7 +230,263 @@ void ai_server::run(hipStream_t stream) {
   }
 }
 
-// Let the workers finish what is queued, join them and release the streams.
+// Complete a resident request (any thread but the caller's lock-holders).
+void ai_server::finish(const RequestPtr& r, int rc, const std::string& error) {
+  if (r->copied_in) (void)hipEventDestroy(r->copied_in);
+  if (r->copied_out) (void)hipEventDestroy(r->copied_out);
+  r->copied_in = r->copied_out = nullptr;
+  const double end = now_s();
+  std::lock_guard<std::mutex> lock(mu);
+  if (r->slab_len) {
+    space.give(r->slab_off, r->slab_len);
+    slot_busy[r->seq % ring] = 0;
+    r->slab_len = 0;
+  }
+  ai_request_info& in = r->info;
+  in.rc = rc < 0 ? rc : r->base_rc;
+  in.end_s = end;
+  std::strncpy(in.error, error.c_str(), sizeof in.error - 1);
+  in.error[sizeof in.error - 1] = '\0';
+  r->done = true;
+  done.notify_all();
+}
+
+// The resident mode's dispatcher: admission by footprint, copy-in,
+// publication, kernel (re)launch, completion, copy-out.
+void ai_server::dispatch() {
+  (void)hipSetDevice(device);
+  hipStream_t kstream = streams[0], in_stream = streams[1], out_stream = streams[2];
+  uint64_t* pub = ctl;
+  uint64_t* stop_word = ctl + 1;
+  uint64_t* done_seq = ctl + 8;
+  std::deque<RequestPtr> staging, running, draining;
+  ai_resident_args args{};
+  args.desc = dev_desc;
+  args.pub = dev_ctl;
+  args.stop = dev_ctl + 1;
+  args.done_seq = dev_ctl + 8;
+  args.head = dev_words;
+  args.done_cnt = dev_words + 8;
+  args.ring = ring;
+  args.refill_min = refill_min;
+  args.idle_ticks = (int64_t)(idle_ms * 1e5);  // 100 MHz clock
+  int64_t in_flight_traj = 0;
+
+  auto hip_error = [](hipError_t e, const char* what) {
+    (void)hipGetLastError();
+    return std::string(what) + ": " + hipGetErrorString(e);
+  };
+
+  for (;;) {
+    bool progress = false;
+    // admit queued requests, in order, while their footprint fits and a ring
+    // slot is free
+    std::vector<RequestPtr> admit;
+    {
+      std::lock_guard<std::mutex> lock(mu);
+      while (!queue.empty()) {
+        const RequestPtr& r = queue.front();
+        if (slot_busy[next_seq % ring]) break;
+        size_t off = 0;
+        const size_t len = footprint(r->item.n);
+        if (!space.take(len, off)) break;
+        r->slab_off = off;
+        r->slab_len = len;
+        r->seq = next_seq++;
+        slot_busy[r->seq % ring] = 1;
+        admit.push_back(r);
+        queue.pop_front();
+      }
+      if (admit.empty() && queue.empty() && staging.empty() && running.empty() &&
+          draining.empty() && stopping)
+        break;
+    }
+    for (const RequestPtr& r : admit) {
+      const ai_batch_item& it = r->item;
+      const size_t pb = plane_bytes(it.n);
+      double* y0s = (double*)(slab + r->slab_off);
+      hipError_t e = hipEventCreateWithFlags(&r->copied_in, hipEventDisableTiming);
+      if (e == hipSuccess)
+        e = hipMemcpy2DAsync(y0s, pb, it.y0, (size_t)it.ld * 8, (size_t)it.n * 8, 12,
+                             hipMemcpyDefault, in_stream);
+      if (e == hipSuccess) e = hipEventRecord(r->copied_in, in_stream);
+      if (e != hipSuccess) {
+        finish(r, AI_EHIP, hip_error(e, "copy in"));
+        continue;
+      }
+      staging.push_back(r);
+      progress = true;
+    }
+    // publish, in request order, the requests whose initial states are in
+    // the slab
+    while (!staging.empty()) {
+      const RequestPtr r = staging.front();
+      const hipError_t q = hipEventQuery(r->copied_in);
+      if (q == hipErrorNotReady) break;
+      staging.pop_front();
+      progress = true;
+      if (q != hipSuccess) {
+        finish(r, AI_EHIP, hip_error(q, "copy in"));
+        continue;
+      }
+      const ai_batch_item& it = r->item;
+      const size_t pb = plane_bytes(it.n);
+      double* y0s = (double*)(slab + r->slab_off);
+      const uint32_t slot = (uint32_t)(r->seq % ring);
+      slot_total[slot] += (uint64_t)it.n;
+      ai_resident_describe(&it, r->kernel, y0s, y0s + 12 * pb / 8, y0s + 24 * pb / 8,
+                           (int64_t)(pb / 8), r->seq, slot_total[slot], &desc[slot]);
+      // descriptor before the count that publishes it
+      __atomic_store_n(pub, r->seq + 1, __ATOMIC_RELEASE);
+      in_flight_traj += it.n;
+      r->info.start_s = now_s();
+      r->info.batch_size = (int32_t)(running.size() + 1);
+      r->info.batch_trajectories = in_flight_traj;
+      running.push_back(r);
+      // the kernel must be running while published requests are unfinished
+      if (kernel_running && hipEventQuery(kernel_done) != hipErrorNotReady) kernel_running = false;
+      if (!kernel_running) {
+        int64_t waves = 0;
+        const int lrc = ai_resident_launch(&args, kstream, &waves);
+        hipError_t e = lrc == AI_OK ? hipEventRecord(kernel_done, kstream) : hipSuccess;
+        if (lrc != AI_OK || e != hipSuccess) {
+          const std::string why = lrc != AI_OK ? std::string(ai_last_error())
+                                               : hip_error(e, "hipEventRecord");
+          for (const RequestPtr& x : running) finish(x, AI_EHIP, why);
+          running.clear();
+          in_flight_traj = 0;
+          continue;
+        }
+        kernel_running = true;
+        launches += 1;
+      }
+      r->info.batch_id = launches - 1;
+    }
+    // a kernel that ran out of work and exited while requests were published
+    // is started again
+    if (!running.empty() && kernel_running && hipEventQuery(kernel_done) != hipErrorNotReady) {
+      int64_t waves = 0;
+      const int lrc = ai_resident_launch(&args, kstream, &waves);
+      if (lrc == AI_OK && hipEventRecord(kernel_done, kstream) == hipSuccess) {
+        launches += 1;
+        progress = true;
+      } else {
+        const std::string why = ai_last_error();
+        for (const RequestPtr& x : running) finish(x, AI_EHIP, why);
+        running.clear();
+        in_flight_traj = 0;
+        kernel_running = false;
+      }
+    }
+    // completed requests: results out to the caller's buffers
+    for (auto it = running.begin(); it != running.end();) {
+      const RequestPtr r = *it;
+      const uint32_t slot = (uint32_t)(r->seq % ring);
+      if (__atomic_load_n(done_seq + slot, __ATOMIC_ACQUIRE) != r->seq + 1) {
+        ++it;
+        continue;
+      }
+      it = running.erase(it);
+      progress = true;
+      in_flight_traj -= r->item.n;
+      const ai_batch_item& itm = r->item;
+      const size_t pb = plane_bytes(itm.n);
+      const char* base = slab + r->slab_off;
+      hipError_t e = hipEventCreateWithFlags(&r->copied_out, hipEventDisableTiming);
+      if (e == hipSuccess)
+        e = hipMemcpy2DAsync(itm.final_state, (size_t)itm.ld * 8, base + 12 * pb, pb,
+                             (size_t)itm.n * 8, 12, hipMemcpyDefault, out_stream);
+      if (e == hipSuccess)
+        e = hipMemcpy2DAsync(itm.obs, (size_t)itm.ld * 8, base + 24 * pb, pb, (size_t)itm.n * 8,
+                             AI_NOBS, hipMemcpyDefault, out_stream);
+      if (e == hipSuccess) e = hipEventRecord(r->copied_out, out_stream);
+      if (e != hipSuccess) {
+        (void)hipStreamSynchronize(out_stream);  // the slab space is not reused under a copy
+        finish(r, AI_EHIP, hip_error(e, "copy out"));
+        continue;
+      }
+      draining.push_back(r);
+    }
+    // copied out: complete
+    for (auto it = draining.begin(); it != draining.end();) {
+      const hipError_t q = hipEventQuery((*it)->copied_out);
+      if (q == hipErrorNotReady) {
+        ++it;
+        continue;
+      }
+      const RequestPtr r = *it;
+      it = draining.erase(it);
+      progress = true;
+      finish(r, q == hipSuccess ? AI_OK : AI_EHIP, q == hipSuccess ? "" : hip_error(q, "copy out"));
+    }
+    if (!progress) {
+      std::unique_lock<std::mutex> lock(mu);
+      work.wait_for(lock, std::chrono::microseconds(100));
+    }
+  }
+  // everything is served: the waves exit once idle
+  __atomic_store_n(stop_word, (uint64_t)1, __ATOMIC_RELEASE);
+  if (kernel_running) (void)hipEventSynchronize(kernel_done);
+  kernel_running = false;
+}
+
+int ai_server::start_resident(const ai_server_config& c) {
+  ring = c.ring > 0 ? c.ring : 1024;
+  refill_min = c.refill_min > 0 ? c.refill_min : 8;
+  idle_ms = c.idle_ms > 0.0 ? c.idle_ms : 20.0;
+  slab_bytes = c.slab_bytes > 0 ? (size_t)c.slab_bytes : ((size_t)4 << 30);
+  slot_total.assign(ring, 0);
+  slot_busy.assign(ring, 0);
+  space.reset(slab_bytes);
+  hipError_t e;
+  const size_t ctl_bytes = sizeof(uint64_t) * (8 + (size_t)ring);
+  if ((e = hipHostMalloc((void**)&ctl, ctl_bytes, hipHostMallocCoherent | hipHostMallocMapped)) !=
+          hipSuccess ||
+      (e = hipHostMalloc((void**)&desc, sizeof(ai_resident_desc) * ring,
+                         hipHostMallocCoherent | hipHostMallocMapped)) != hipSuccess) {
+    (void)hipGetLastError();
+    return ai_fail(AI_ENOMEM, "host-coherent request ring");
+  }
+  std::memset(ctl, 0, ctl_bytes);
+  std::memset(desc, 0, sizeof(ai_resident_desc) * ring);
+  if ((e = hipHostGetDevicePointer((void**)&dev_ctl, ctl, 0)) != hipSuccess ||
+      (e = hipHostGetDevicePointer((void**)&dev_desc, desc, 0)) != hipSuccess)
+    return ai_fail(AI_EHIP, hipGetErrorString(e));
+  const size_t dev_bytes = sizeof(uint64_t) * (8 + (size_t)ring);
+  if ((e = hipMalloc((void**)&dev_words, dev_bytes)) != hipSuccess ||
+      (e = hipMalloc((void**)&slab, slab_bytes)) != hipSuccess) {
+    (void)hipGetLastError();
+    return ai_fail(AI_ENOMEM, "server slab");
+  }
+  if ((e = hipMemset(dev_words, 0, dev_bytes)) != hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&kernel_done, hipEventDisableTiming)) != hipSuccess)
+    return ai_fail(AI_EHIP, hipGetErrorString(e));
+  for (int k = 0; k < 3; ++k) {
+    hipStream_t st = nullptr;  // default priority
+    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess)
+      return ai_fail(AI_EHIP, hipGetErrorString(e));
+    streams.push_back(st);
+  }
+  return AI_OK;
+}
+
+// After the dispatcher has stopped the kernel: release what start_resident took.
+void ai_server::release_resident() {
+  if (kernel_done) (void)hipEventDestroy(kernel_done);
+  kernel_done = nullptr;
+  if (slab) (void)hipFree(slab);
+  if (dev_words) (void)hipFree(dev_words);
+  if (desc) (void)hipHostFree(desc);
+  if (ctl) (void)hipHostFree(ctl);
+  slab = nullptr;
+  dev_words = nullptr;
+  desc = nullptr;
+  ctl = nullptr;
+}
+
+// Let the workers (or the dispatcher) finish what is queued, join them and
+// release the streams.
 void ai_server::stop() {
   {
     std::lock_guard<std::mutex> lock(mu);
@@ -162,9 +495,12 @@ void ai_server::stop() {
   work.notify_all();
   for (std::thread& t : workers)
     if (t.joinable()) t.join();
+  if (mode == AI_SERVE_RESIDENT && kernel_running && kernel_done)
+    (void)hipEventSynchronize(kernel_done);
   for (hipStream_t st : streams) (void)hipStreamDestroy(st);
   workers.clear();
   streams.clear();
+  if (mode == AI_SERVE_RESIDENT) release_resident();
 }
 
 extern "C" {
@@ -178,12 +514,36 @@ int ai_server_create(const ai_server_config* cfg, ai_server** out) {
       (c.schedule != 0 && c.schedule != AI_SCHEDULE_LONGEST_FIRST))
     return ai_fail(AI_EINVAL, "config: max_batch >= 0, schedule 0 or AI_SCHEDULE_LONGEST_FIRST, "
                               "workers 0 .. 16");
+  if ((c.mode != AI_SERVE_LAUNCHES && c.mode != AI_SERVE_RESIDENT) || c.ring < 0 ||
+      c.ring > 65536 || c.slab_bytes < 0 || !(c.idle_ms >= 0.0) || c.idle_ms > 6e4 ||
+      c.refill_min < 0 || c.refill_min > 64 || c.reserved != 0)
+    return ai_fail(AI_EINVAL, "config: mode AI_SERVE_LAUNCHES or AI_SERVE_RESIDENT, ring 0 .. "
+                              "65536, slab_bytes >= 0, idle_ms 0 .. 60000, refill_min 0 .. 64, "
+                              "reserved 0");
   std::unique_ptr<ai_server> s(new (std::nothrow) ai_server);
   if (!s) return ai_fail(AI_ENOMEM, "server");
+  s->mode = c.mode;
   s->max_batch = c.max_batch > 0 ? c.max_batch : (int64_t)1 << 22;
   s->schedule = c.schedule;
   hipError_t e = hipGetDevice(&s->device);
   if (e != hipSuccess) return ai_fail(AI_EHIP, hipGetErrorString(e));
+  if (s->mode == AI_SERVE_RESIDENT) {
+    const int rc = s->start_resident(c);
+    if (rc != AI_OK) {
+      const std::string why = ai_last_error();
+      s->stop();
+      return ai_fail(rc, why.c_str());
+    }
+    ai_server* raw = s.get();
+    try {
+      s->workers.emplace_back([raw] { raw->dispatch(); });
+    } catch (...) {
+      s->stop();
+      return ai_fail(AI_ENOMEM, "dispatcher thread");
+    }
+    *out = s.release();
+    return AI_OK;
+  }
   const int workers = c.workers > 0 ? c.workers : 3;
   for (int w = 0; w < workers; ++w) {
     // default priority: the only stream priority these kernels are run with
@@ -213,8 +573,15 @@ int ai_server_submit(ai_server* srv, const ai_batch_item* item, int32_t kernel,
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != srv->device)
     return ai_fail(AI_EINVAL, "submit from the server's device");
-  const int rc = ai_check_request(item, kernel);
+  const bool resident = srv->mode == AI_SERVE_RESIDENT;
+  const int rc = ai_check_request(item, kernel, resident);
   if (rc < 0) return rc;
+  if (resident) {
+    if (item->params.n != 4 || item->params.m != 8)
+      return ai_fail(AI_EUNSUPPORTED, "the resident kernel integrates n=4, m=8 potentials");
+    if (item->n > 0xffffffffLL || footprint(item->n) > srv->slab_bytes)
+      return ai_fail(AI_EINVAL, "the request does not fit in the server's slab");
+  }
   auto r = std::make_shared<Request>();
   r->item = *item;
   r->kernel = kernel;

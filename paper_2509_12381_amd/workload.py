@@ -203,9 +203,10 @@ def batch_grid(scale: float = 1.0) -> list[Workload]:
 
 # The serving stream: Poisson arrivals at 200 requests/s, sizes floor(256 *
 # 4096**U), RelTol from {1e-6, 1e-8, 1e-10} with AbsTol = RelTol / 100, a
-# quarter of the requests with single-precision stages; each request
-# integrates a slice of one pool of initial states of the 1,024-trajectory
-# configuration's physics.
+# quarter of the requests with single-precision stages, collision temperature
+# and trap q drawn from the batched grid's values; each request integrates a
+# slice of one pool of initial states, moved to its temperature and q by
+# ``retarget_thermal``.
 SERVING_SEED = 2
 SERVING_RATE_HZ = 200.0
 SERVING_RTOLS = (1e-6, 1e-8, 1e-10)
@@ -221,16 +222,19 @@ class ServingRequest:
     rtol: float
     atol: float
     precision: str        # "fp64" or "fp32-stages"
+    T_atom: float = 1e-3  # collision (atom) temperature, K
+    q: float = 0.1        # Paul-trap q (a = 0)
 
 
 def serving_stream(count: int, seed: int = SERVING_SEED, rate_hz: float = SERVING_RATE_HZ,
                    max_size: int = 256 * 4096) -> list[ServingRequest]:
     """The first `count` requests of the serving stream.  From one PCG64
     stream of `seed`, per request: an exponential gap (mean 1 / rate_hz), U for
-    the size, one uniform each for the tolerance, the precision and the slice
-    offset.  Sizes are capped at max_size (the stream's own maximum by
-    default, smaller for tests)."""
-    u = np.random.Generator(np.random.PCG64(seed)).random((count, 5))
+    the size, one uniform each for the tolerance, the precision, the slice
+    offset, the temperature and q (each uniform over the batched grid's
+    BATCH_T_ATOM and BATCH_Q).  Sizes are capped at max_size (the stream's own
+    maximum by default, smaller for tests)."""
+    u = np.random.Generator(np.random.PCG64(seed)).random((count, 7))
     t = np.cumsum(-np.log1p(-u[:, 0]) / rate_hz)
     out = []
     for k in range(count):
@@ -238,14 +242,43 @@ def serving_stream(count: int, seed: int = SERVING_SEED, rate_hz: float = SERVIN
         rtol = SERVING_RTOLS[min(int(u[k, 2] * len(SERVING_RTOLS)), len(SERVING_RTOLS) - 1)]
         precision = "fp32-stages" if u[k, 3] < 0.25 else "fp64"
         offset = int(u[k, 4] * (SERVING_POOL - n + 1))
-        out.append(ServingRequest(float(t[k]), n, offset, rtol, rtol * 1e-2, precision))
+        T = BATCH_T_ATOM[min(int(u[k, 5] * len(BATCH_T_ATOM)), len(BATCH_T_ATOM) - 1)]
+        q = BATCH_Q[min(int(u[k, 6] * len(BATCH_Q)), len(BATCH_Q) - 1)]
+        out.append(ServingRequest(float(t[k]), n, offset, rtol, rtol * 1e-2, precision, T, q))
     return out
 
 
 def serving_pool(n: int = SERVING_POOL) -> Workload:
     """The pool the serving stream's requests slice: the 1,024-trajectory
-    configuration's physics (200 RF periods), seed 3."""
+    configuration's physics (1 mK, q = 0.1, 200 RF periods), seed 3."""
     return thermal_workload(n, SERVING_POOL_SEED, name=f"serving-pool-{n}")
+
+
+def serving_request_workload(r: ServingRequest) -> Workload:
+    """The system, span and recipe of one serving request (its q and
+    temperature; the pool's seed and sizes)."""
+    wl = thermal_workload(r.n, SERVING_POOL_SEED, rtol=r.rtol, atol=r.atol, T_atom=r.T_atom,
+                          q=r.q, name=f"serving-T{r.T_atom:.2e}-q{r.q:g}-n{r.n}")
+    return wl
+
+
+def retarget_thermal(y0, system_from: System, T_atom_from: float, system_to: System,
+                     T_atom_to: float):
+    """Initial states of ``thermal_ensemble`` drawn for (system_from,
+    T_atom_from) moved to (system_to, T_atom_to) with the same uniforms: the
+    ion's thermal position scales with 1 / (secular frequency), the atom's
+    velocity with sqrt(T_atom), and the atom keeps its offset from the ion
+    (the direction of flight, impact parameter and azimuth do not depend on
+    either).  Equals the ensemble drawn directly for the new parameters up to
+    rounding.  Works on numpy arrays and torch tensors of shape (12, n);
+    returns a new array."""
+    sx = secular_omega_x(system_from) / secular_omega_x(system_to)
+    sv = math.sqrt(T_atom_to / T_atom_from)
+    out = y0 * 1.0
+    out[0:3] = y0[0:3] * sx
+    out[6:9] = y0[6:9] + (out[0:3] - y0[0:3])
+    out[9:12] = y0[9:12] * sv
+    return out
 
 
 def _uniform_rows(n: int, seed: int, ncols: int) -> np.ndarray:

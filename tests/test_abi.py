@@ -29,6 +29,7 @@ def test_header_declares_the_entry_points():
     assert names == sorted(["ai_integrate", "ai_integrate_async", "ai_integrate_batch",
                             "ai_integrate_batch_async", "ai_batch_plan_create",
                             "ai_batch_plan_launch", "ai_batch_plan_destroy", "ai_tune",
+                            "ai_tune_batch",
                             "ai_trace",
                             "ai_server_create",
                             "ai_server_submit",
@@ -140,6 +141,12 @@ def test_server_argument_errors_without_gpu(lib):
     assert L.ai_server_create(ctypes.byref(bad), ctypes.byref(h)) == binding.EINVAL
     bad = binding.AiServerConfig(0, 0, 17)
     assert L.ai_server_create(ctypes.byref(bad), ctypes.byref(h)) == binding.EINVAL
+    for field, value in (("mode", 2), ("ring", -1), ("ring", 65537), ("slab_bytes", -1),
+                         ("idle_ms", -1.0), ("idle_ms", float("nan")), ("refill_min", 65),
+                         ("reserved", 1)):
+        bad = binding.AiServerConfig(0, 0, 0, 1)
+        setattr(bad, field, value)
+        assert L.ai_server_create(ctypes.byref(bad), ctypes.byref(h)) == binding.EINVAL, field
     assert h.value is None
     t = ctypes.c_uint64()
     info = binding.AiRequestInfo()
@@ -222,3 +229,4 @@ def test_invalid_arguments_are_refused_before_any_device_call(lib):
     assert b.ai_integrate_batch(items, 2, 0) == binding.EINVAL
     assert binding.ai_last_error().startswith("item 1:")
     assert b.ai_integrate_batch_async(items, 0, 0, None) == binding.OK  # nothing enqueued
+

@@ -681,9 +681,13 @@ def test_complex_statistics_cold_collisions(ai, torch, aio):
           f"gpu={hg.tolist()} oracle={ho.tolist()} max sigma={hsig:.2f}", flush=True)
     assert sig <= 3.0 and hsig <= 3.0
     assert p_life > 0.01 and p_angle > 0.01 and p_pos > 0.01
-    # direct trajectories (at most one bounce, calm by the oracle) still agree
-    # one by one
+    # trajectories without a bounce (and calm by the oracle) still agree one by
+    # one.  A single hard bounce at 10 uK amplifies the rounding of every step
+    # by about the well depth over the collision energy (~1e8): the oracle's
+    # 1-ulp test, which perturbs y0 only, does not bound that, and those are
+    # held to the statistics above
     calm, _ = non_chaotic(aio, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, ofin, oob)
+    calm &= oob[O["bounces"]] == 0
     rel, _, same = _report("cold collisions", aio, wl.system, gob, oob, gfin, ofin, calm)
     assert calm.sum() >= 500 and rel.max() <= 1e-6 and same >= 0.99
 
@@ -1072,7 +1076,8 @@ def test_tune_picks_a_configuration_and_leaves_the_results(ai, torch):
     obs = torch.full((13, d.shape[1]), -7.0, dtype=torch.float64, device="cuda")
     best, ms = ai.ai_tune(wl.system, d, wl.t0, wl.tmax, wl.rtol, wl.atol, fin, obs)
     torch.cuda.synchronize()
-    assert best in (0, 16, 16 | 1 | (1 << 8), 16 | 1 | (16 << 8), 16 | 1 | (64 << 8))
+    assert best in (0, 16, 16 | (1 << 16), 16 | (2 << 16), 16 | 1 | (1 << 8),
+                    16 | 1 | (16 << 8), 16 | 1 | (64 << 8))
     assert ms > 0
     np.testing.assert_array_equal(fin.cpu().numpy(), ref_f)
     np.testing.assert_array_equal(obs.cpu().numpy(), ref_o)
@@ -1084,6 +1089,40 @@ def test_tune_picks_a_configuration_and_leaves_the_results(ai, torch):
     with pytest.raises(ai.AiError) as e:
         ai.ai_tune(wl.system, d, wl.t0, wl.tmax, wl.rtol, wl.atol, d, obs)
     assert e.value.rc == ai.EINVAL
+
+
+def test_tune_batch_and_four_lane_widths(ai, torch):
+    """ai_tune_batch leaves the batch's results (bitwise those of the batched
+    call) and returns one of its candidates; every four-lane width, in a batch
+    and in a single scheduled call, gives the same results as one lane each."""
+    items = _batch_case()
+    dev = [_device_item(torch, it) for it in items]
+    ref = [(d, torch.full_like(f, -7.0), torch.full_like(o, -7.0), n) for d, f, o, n in dev]
+    ai.ai_integrate_batch(_batch_tuples(items, ref), schedule="longest-first")
+    best, ms = ai.ai_tune_batch(_batch_tuples(items, dev))
+    torch.cuda.synchronize()
+    print(f"[tune batch] best kernel code {best:#x}, {ms:.3f} ms", flush=True)
+    assert best in (0, 16, 16 | (1 << 16), 16 | (2 << 16)) and ms > 0
+    for (_, f, o, n), (_, rf, ro, _) in zip(dev, ref):
+        np.testing.assert_array_equal(f.cpu().numpy()[:, :n], rf.cpu().numpy()[:, :n])
+        np.testing.assert_array_equal(o.cpu().numpy(), ro.cpu().numpy())
+    for code in (1, 2, 3):
+        out = [(d, torch.full_like(f, -7.0), torch.full_like(o, -7.0), n) for d, f, o, n in dev]
+        rc = ai.load().ai_integrate_batch(ai.batch_items(_batch_tuples(items, out)), len(items),
+                                          16 | (code << 16))
+        assert rc >= 0
+        torch.cuda.synchronize()
+        for (_, f, o, n), (_, rf, ro, _) in zip(out, ref):
+            np.testing.assert_array_equal(f.cpu().numpy()[:, :n], rf.cpu().numpy()[:, :n])
+            np.testing.assert_array_equal(o.cpu().numpy(), ro.cpu().numpy())
+    wl = W.full_ensemble()
+    y0 = wl.initial_states(5000)
+    a = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol)
+    for code in (1, 2, 3):
+        b = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol,
+                    kernel=16 | (code << 16))
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
 
 
 def test_kernel_timing_flag(ai, torch):

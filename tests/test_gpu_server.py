@@ -141,3 +141,185 @@ def test_server_errors_and_timeouts(ai, torch):
         assert info["rc"] == 0
         with pytest.raises(ai.AiError):
             srv.wait(t)                                   # a ticket is waited for once
+
+
+# ---- Resident mode (continuous batching) ----------------------------------
+
+def _resident_mix(torch):
+    """Requests of different systems, sizes, spans, tolerances and precisions,
+    some from host memory (pinned and pageable)."""
+    full = W.full_ensemble()
+    grid = W.batch_grid(scale=1.0 / 64)
+    reqs = [(_request(torch, full, full.initial_states(4096)), "fp64")]
+    for k, prec in ((0, "fp64"), (12, "fp32-stages"), (21, "fp64"), (45, "fp32-stages"),
+                    (63, "fp64")):
+        wl = grid[k]
+        reqs.append((_request(torch, wl, wl.initial_states(), ld=wl.n + 5), prec))
+    wl = grid[30]
+    reqs.append((_request(torch, wl, wl.initial_states(), rtol=1e-10, atol=1e-12), "fp64"))
+    reqs.append((_request(torch, wl, wl.initial_states(), t0=0.2 * wl.tmax, tmax=0.7 * wl.tmax),
+                 "fp32-stages"))
+    reqs.append((_request(torch, wl, wl.initial_states(1)[:, :0]), "fp64"))
+    return reqs
+
+
+def _host_request(torch, wl, y0, pinned):
+    """A request whose buffers are host memory (torch CPU tensors, pinned or
+    pageable)."""
+    n = y0.shape[1]
+    mk = (lambda a: torch.from_numpy(a).pin_memory()) if pinned else torch.from_numpy
+    d = mk(np.ascontiguousarray(y0))
+    fin = mk(np.full((12, n), -7.0))
+    obs = mk(np.full((13, n), -7.0))
+    return dict(item=(wl.system, d, fin, obs, wl.t0, wl.tmax, wl.rtol, wl.atol, n), fin=fin,
+                obs=obs, n=n, dev=torch.from_numpy(np.ascontiguousarray(y0)).cuda())
+
+
+def test_resident_alone_equals_in_mix(ai, torch):
+    """Every request served by the resident kernel, whatever it shares the GPU
+    with, equals ai_integrate on it alone, bit for bit, in either precision;
+    requests from host memory included."""
+    reqs = _resident_mix(torch)
+    wl = W.small_ensemble()
+    y = wl.initial_states(600)
+    hosts = [_host_request(torch, wl, y[:, :300], True), _host_request(torch, wl, y[:, 300:], False)]
+    torch.cuda.synchronize()
+    with ai.Server(mode="resident", idle_ms=50.0) as srv:
+        tickets = [srv.submit(r["item"], p) for r, p in reqs]
+        tickets += [srv.submit(h["item"], "fp64") for h in hosts]
+        infos = [srv.wait(t, timeout=120.0) for t in tickets]
+    assert all(i is not None for i in infos)
+    assert all(i["rc"] == 0 and i["error"] == "" for i in infos), infos
+    print("[resident mix] requests on the GPU at publication:",
+          [i["batch_size"] for i in infos], "launches:", sorted({i["batch_id"] for i in infos}),
+          flush=True)
+    assert max(i["batch_size"] for i in infos) > 1      # requests overlapped on the GPU
+    for i in infos:
+        assert i["submit_s"] <= i["start_s"] <= i["end_s"]
+    for (r, p), i in zip(reqs, infos):
+        fin, obs = _alone(ai, torch, r, p)
+        np.testing.assert_array_equal(r["fin"].cpu().numpy(), fin)
+        np.testing.assert_array_equal(r["obs"].cpu().numpy(), obs)
+        assert np.all(r["obs"].cpu().numpy()[:, r["n"]:] == -7.0)
+    for h in hosts:
+        f = torch.full((12, h["n"]), -7.0, dtype=torch.float64, device="cuda")
+        o = torch.full((13, h["n"]), -7.0, dtype=torch.float64, device="cuda")
+        ai.ai_integrate(wl.system, h["dev"], wl.t0, wl.tmax, wl.rtol, wl.atol, f, o, "plain",
+                        schedule="longest-first")
+        np.testing.assert_array_equal(h["fin"].numpy(), f.cpu().numpy())
+        np.testing.assert_array_equal(h["obs"].numpy(), o.cpu().numpy())
+
+
+def test_resident_admission_by_footprint(ai, torch):
+    """A slab that holds two of the requests at a time: the others wait in
+    arrival order until earlier ones have been copied out, and all complete
+    correctly; a request larger than the slab is refused at submission."""
+    wl = W.small_ensemble()
+    y = wl.initial_states(6 * 512)
+    reqs = [_request(torch, wl, y[:, 512 * k:512 * (k + 1)]) for k in range(6)]
+    per = 37 * ((512 * 8 + 255) // 256 * 256)           # footprint of one request
+    with ai.Server(mode="resident", slab_bytes=2 * per, idle_ms=50.0) as srv:
+        big = _request(torch, wl, y[:, :1100])
+        with pytest.raises(ai.AiError) as e:
+            srv.submit(big["item"])
+        assert e.value.rc == ai.EINVAL
+        tickets = [srv.submit(r["item"]) for r in reqs]
+        infos = [srv.wait(t, timeout=120.0) for t in tickets]
+    assert all(i is not None and i["rc"] == 0 for i in infos)
+    for i in infos:   # never more than two requests held slab space at once
+        t = i["start_s"]
+        assert sum(j["start_s"] <= t < j["end_s"] for j in infos) <= 2
+    starts = [i["start_s"] for i in infos]
+    assert starts == sorted(starts)                     # admitted in arrival order
+    for r in reqs:
+        fin, obs = _alone(ai, torch, r)
+        np.testing.assert_array_equal(r["fin"].cpu().numpy(), fin)
+        np.testing.assert_array_equal(r["obs"].cpu().numpy(), obs)
+
+
+def test_resident_kernel_exits_when_idle_and_comes_back(ai, torch):
+    """With nothing to do the resident waves exit after idle_ms; a request
+    that arrives later starts a new launch; unsupported requests are refused."""
+    import dataclasses
+    import time
+    wl = W.small_ensemble()
+    y = wl.initial_states(400)
+    a, b = _request(torch, wl, y[:, :200]), _request(torch, wl, y[:, 200:])
+    with ai.Server(mode="resident", idle_ms=5.0) as srv:
+        ia = srv.wait(srv.submit(a["item"]), timeout=60.0)
+        time.sleep(0.2)                                  # the kernel has exited by now
+        ib = srv.wait(srv.submit(b["item"]), timeout=60.0)
+        wl612 = dataclasses.replace(wl, system=dataclasses.replace(
+            wl.system, n=6, m=12, Cn=8200.0 * 2.0, Cm=4.1e9))
+        with pytest.raises(ai.AiError) as e:
+            srv.submit(_request(torch, wl612, y[:, :10])["item"])
+        assert e.value.rc == ai.EUNSUPPORTED
+    assert ia["rc"] == ib["rc"] == 0
+    assert ib["batch_id"] == ia["batch_id"] + 1
+    for r in (a, b):
+        fin, obs = _alone(ai, torch, r)
+        np.testing.assert_array_equal(r["fin"].cpu().numpy(), fin)
+        np.testing.assert_array_equal(r["obs"].cpu().numpy(), obs)
+
+
+def test_resident_stream_against_oracle(ai, torch, aio):
+    """A mixed stream as the serving configuration draws it (RelTol 1e-6, 1e-8
+    and 1e-10, double and single-precision-stage requests, temperature and q
+    from the batched grid), small sizes, every request checked against the
+    oracle: double requests at the 1e-6 bar (time-aligned, non-chaotic direct
+    trajectories) with identical accepted-step counts on >= 99% of them;
+    single-precision-stage requests within the variant's stated bounds
+    (median state error, step counts, statuses)."""
+    import os
+    from paper_2509_12381_amd import stats as S
+    O = W.OBS
+    stream = W.serving_stream(24, max_size=400)
+    pool = W.serving_pool(1 << 14)
+    base = pool.initial_states()
+    reqs = []
+    for r in stream:
+        wl = W.serving_request_workload(r)
+        off = r.offset % (base.shape[1] - r.n)
+        y0 = W.retarget_thermal(base[:, off:off + r.n], pool.system, pool.T_atom, wl.system,
+                                r.T_atom)
+        reqs.append((r, wl, y0, _request(torch, wl, y0)))
+    assert {r.precision for r in stream} == {"fp64", "fp32-stages"}
+    assert len({r.rtol for r in stream}) == 3
+    torch.cuda.synchronize()
+    with ai.Server(mode="resident", idle_ms=50.0) as srv:
+        tickets = [srv.submit(q["item"], r.precision) for r, _, _, q in reqs]
+        infos = [srv.wait(t, timeout=120.0) for t in tickets]
+    assert all(i is not None and i["rc"] == 0 for i in infos)
+    nthreads = min(16, os.cpu_count() or 1)
+    worst = {"fp64": 0.0, "fp32-stages": 0.0}
+    for (r, wl, y0, q), i in zip(reqs, infos):
+        gfin, gob = q["fin"].cpu().numpy(), q["obs"].cpu().numpy()
+        ofin, oob, _ = aio.integrate(wl.system, y0, wl.t0, wl.tmax, r.rtol, r.atol,
+                                     nthreads=nthreads)
+        direct = (oob[O["bounces"]] <= 1) & (oob[O["status"]] == W.ST_ESCAPED)
+        al = ofin.copy()
+        for j in np.nonzero(direct & (gob[O["tend"]] != oob[O["tend"]]))[0]:
+            al[:, j] += aio.force(wl.system, oob[O["tend"], j], ofin[:, j]) * (
+                gob[O["tend"], j] - oob[O["tend"], j])
+        rel = S.block_relative_difference(gfin[:, direct], al[:, direct])
+        same = np.mean(gob[O["nsteps"], direct] == oob[O["nsteps"], direct])
+        print(f"[resident vs oracle] n={r.n} rtol={r.rtol:g} {r.precision} T={r.T_atom:.1e} "
+              f"q={r.q:g}: direct={int(direct.sum())} median={np.median(rel):.2e} "
+              f"max={rel.max():.2e} same nsteps={same:.3f}", flush=True)
+        assert np.mean(gob[O["status"]] == oob[O["status"]]) >= 0.97
+        if r.precision == "fp64":
+            # calm: at most one bounce, and no hard bounce (r_min above the wall
+            # region, where rounding is amplified ~1e8)
+            calm = direct & (oob[O["rmin"]] > 50.0)
+            relc = S.block_relative_difference(gfin[:, calm], al[:, calm])
+            assert relc.max() <= 1e-6
+            assert np.mean(gob[O["nsteps"], calm] == oob[O["nsteps"], calm]) >= 0.99
+            worst["fp64"] = max(worst["fp64"], float(relc.max()))
+        else:
+            med_tol = 5e-6 if r.rtol >= 1e-8 else 2e-4
+            assert np.median(rel) <= med_tol
+            # within 1% of the count, or one step for the shortest trajectories
+            dsteps = np.abs(gob[O["nsteps"]] - oob[O["nsteps"]])
+            assert np.all(dsteps <= np.maximum(1.0, 1e-2 * oob[O["nsteps"]]))
+            worst["fp32-stages"] = max(worst["fp32-stages"], float(np.median(rel)))
+    print(f"[resident vs oracle] worst: {worst}", flush=True)

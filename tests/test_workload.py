@@ -89,6 +89,30 @@ def test_serving_stream():
     assert abs(fp32 - 0.25) < 4 * math.sqrt(0.25 * 0.75 / len(st))
     assert all(0 <= r.offset and r.offset + r.n <= W.SERVING_POOL for r in st)
     assert all(r.n <= 1000 for r in W.serving_stream(50, max_size=1000))
+    # temperature and q uniform over the batched grid's values
+    for values, key in ((W.BATCH_T_ATOM, "T_atom"), (W.BATCH_Q, "q")):
+        counts = np.array([sum(getattr(r, key) == v for r in st) for v in values])
+        assert counts.sum() == len(st)
+        assert stats.chisquare(counts).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("T_to,q_to", [(1e-5, 0.05), (1e-2, 0.7), (1e-3, 0.1)])
+def test_retarget_thermal_equals_direct_draw(T_to, q_to):
+    """Moving the pool's states to another temperature and q equals drawing
+    them for those parameters with the same seed (up to rounding), for numpy
+    arrays and torch tensors alike."""
+    import torch
+    pool = W.serving_pool(4096)
+    y0 = pool.initial_states()
+    to = W.liyb_system(q=q_to)
+    direct = W.thermal_ensemble(to, 4096, pool.seed, pool.T_ion, T_to, pool.R0, pool.b_max)
+    moved = W.retarget_thermal(y0, pool.system, pool.T_atom, to, T_to)
+    np.testing.assert_allclose(moved, direct, rtol=1e-13, atol=1e-13 * 1e5)
+    moved_t = W.retarget_thermal(torch.from_numpy(y0), pool.system, pool.T_atom, to, T_to)
+    np.testing.assert_array_equal(moved_t.numpy(), moved)
+    assert not np.shares_memory(moved, y0)
+    if (T_to, q_to) != (1e-3, 0.1):
+        assert not np.allclose(moved, y0)
 
 
 @pytest.mark.parametrize("n,m", [(4, 8), (6, 12), (3, 7), (4, 6)])
