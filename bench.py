@@ -34,6 +34,15 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters.json")
 KERNEL_SYMBOL = {"persistent": "ai_persistent_kernel", "plain": "ai_plain_kernel"}
 
 
+_T0 = time.perf_counter()
+
+
+def progress(msg: str) -> None:
+    """One line on stderr as each part of the run ends (stdout carries only the
+    JSON record)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
     for p in ("paper_2509_12381_amd/csrc/ai.hip", "paper_2509_12381_amd/csrc/schedule.hip",
@@ -248,7 +257,11 @@ def serve_stream(binding, W, torch, reqs, srv, pace: bool) -> dict:
 
     th = threading.Thread(target=submit_all)
     th.start()
-    infos = [srv.wait(tickets.get()) for _ in reqs]
+    infos = []
+    for k in range(len(reqs)):
+        infos.append(srv.wait(tickets.get()))
+        if (k + 1) % 250 == 0:
+            progress(f"serving: {k + 1} of {len(reqs)} requests completed")
     th.join()
     lat = np.array([i["end_s"] - i["submit_s"] for i in infos]) * 1e3
     t_first = min(i["submit_s"] for i in infos)
@@ -281,18 +294,23 @@ def serving(binding, W, torch, count: int, saturate: int, launches_count: int,
     sustained rate); and the first `launches_count` of the stream served by
     batched launches for comparison."""
     stream, reqs = serving_requests(W, torch, count, W.SERVING_RATE_HZ)
+    progress(f"serving: {len(reqs)} requests prepared")
     out = {"workload": f"poisson-{W.SERVING_RATE_HZ:g}rps", "seed": W.SERVING_SEED,
            "mode": "resident", "slab_bytes": 4 << 30}
     with binding.Server(mode="resident") as srv:
         out["paced"] = serve_stream(binding, W, torch, reqs, srv, pace=True)
+        progress(f"serving: paced stream, p50 {out['paced']['latency_ms']['p50']:.1f} ms, "
+                 f"p99 {out['paced']['latency_ms']['p99']:.1f} ms")
         if saturate:
             sat = serve_stream(binding, W, torch, reqs[:saturate], srv, pace=False)
             sat["vs_plain_kernel"] = sat["trajectories_per_s"] / plain_traj_per_s
             out["saturated"] = sat
+            progress(f"serving: saturated, {sat['trajectories_per_s']:.3g} trajectories/s")
     if launches_count:
         with binding.Server(schedule="longest-first") as srv:
             out["launch_mode_paced"] = serve_stream(binding, W, torch, reqs[:launches_count], srv,
                                                     pace=True)
+            progress("serving: launch mode done")
     out["plain_kernel_trajectories_per_s"] = plain_traj_per_s
     del reqs
     torch.cuda.empty_cache()
@@ -540,8 +558,10 @@ def main() -> int:
         per = [a.elapsed_time(b) for a, b in ev]
         return t_start.elapsed_time(t_end), per, wall
 
+    progress(f"{wl.name}: inputs on the device")
     total_ms, per_ms, wall = timed(binding.KERNELS[args.kernel] | binding.TIME_KERNEL,
                                    args.steps, args.warmup)
+    progress(f"timed {args.steps} calls: {total_ms / args.steps:.3f} ms each")
     ob = obs.cpu().numpy()
     fin64 = fin.cpu().numpy()
     nsteps = float(ob[W.OBS["nsteps"]].sum())
@@ -572,6 +592,7 @@ def main() -> int:
                 other.append({"kernel": okernel, "schedule": osched, "ms_per_step": o_ms,
                               "steps_per_s": nsteps / (o_ms / 1e3),
                               "timed_kernel_speedup": o_ms / ms_per_step})
+                progress(f"{okernel}/{osched}: {o_ms:.3f} ms per call")
         # the precision variant: single-precision stages (plain kernel)
         k = max(1, min(args.steps, 5))
         o_total, _, _ = timed("plain", k, 1, "longest-first", 0, "fp32-stages")
@@ -594,6 +615,7 @@ def main() -> int:
         t_obs = torch.empty_like(obs)
         best, best_ms = binding.ai_tune(wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol,
                                         t_fin, t_obs)
+        progress(f"ai_tune: kernel code {best}, {best_ms:.3f} ms")
         tuned = {"best_kernel_code": best, "best_ms": best_ms,
                  "what": "ai_tune: each configuration timed twice on this ensemble, each after an untimed run of itself"}
         del t_fin, t_obs
@@ -601,6 +623,7 @@ def main() -> int:
     batched = None
     if not args.no_batch and args.n is None:
         batched = batched_grid(binding, W, flops, torch)
+        progress("batched grid done")
 
     served = None
     if args.serving_requests > 0 and args.n is None:
@@ -608,10 +631,12 @@ def main() -> int:
                          min(args.serving_saturate, args.serving_requests),
                          min(args.serving_launches, args.serving_requests),
                          wl.n * args.steps / (total_ms / 1e3))
+        progress("serving done")
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, y0_host, min(args.cpu_sample, wl.n), runs)
+        progress("cpu baseline done")
 
     traffic = measured_traffic(args.kernel)
     counters = measured_counters(args.kernel)

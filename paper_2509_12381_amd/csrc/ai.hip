@@ -100,6 +100,7 @@ struct Launch {
   double r_exit2, r_bounce2;
   double half_mi, m_atom;    // for the observables
   double t0, tf, hmax, rtol, inv_rtol, thr;
+  double vbound;             // (RelTol/AbsTol)(1 + 2^-20): bound on a velocity ratio per |e|
   double hinit_den;          // 0.8 rtol^(1/5)
   long long n, ld;
   long long first_dynamic;   // persistent kernel: first index handed out by the queue
@@ -149,7 +150,7 @@ using Lane32 = LaneT<float>;
 // (one VALU slot) at every use inside the loop.  The empty asm gives each
 // value a vector-register definition, so it stays there.
 struct Ctl {
-  double tf, hmax, rtol, inv_rtol, thr, r_exit2, r_bounce2, omega;
+  double tf, hmax, rtol, inv_rtol, thr, vbound, r_exit2, r_bounce2, omega;
   int max_steps, exit_on;
 };
 
@@ -236,6 +237,7 @@ __device__ __forceinline__ Ctl lane_ctl(const Launch& P) {
   c.rtol = in_vgpr(P.rtol);
   c.inv_rtol = in_vgpr(P.inv_rtol);
   c.thr = in_vgpr(P.thr);
+  c.vbound = in_vgpr(P.vbound);
   c.r_exit2 = in_vgpr(P.r_exit2);
   c.r_bounce2 = in_vgpr(P.r_bounce2);
   c.omega = in_vgpr(P.omega);
@@ -419,9 +421,11 @@ __device__ __forceinline__ double accel(const C& P, double cosrf, const double* 
   const double s = recip(r2);
   const double g = force_g(P, s);
   const double gi = g * P.inv_mi, ga = g * P.inv_ma;
-  F[0] = -fma(gi, dx, fma(P.kq[0], cosrf, P.ka[0]) * X[0]);
-  F[1] = -fma(gi, dy, fma(P.kq[1], cosrf, P.ka[1]) * X[1]);
-  F[2] = -fma(gi, dz, fma(P.kq[2], cosrf, P.ka[2]) * X[2]);
+  // -(gi d + kappa x) written as (-gi) d + kappa (-x): the same value (the
+  // rounding is symmetric), with the negations as free operand modifiers
+  F[0] = fma(-gi, dx, fma(P.kq[0], cosrf, P.ka[0]) * -X[0]);
+  F[1] = fma(-gi, dy, fma(P.kq[1], cosrf, P.ka[1]) * -X[1]);
+  F[2] = fma(-gi, dz, fma(P.kq[2], cosrf, P.ka[2]) * -X[2]);
   F[3] = ga * dx;
   F[4] = ga * dy;
   F[5] = ga * dz;
@@ -646,6 +650,29 @@ __device__ __forceinline__ bool half_norm(const Ctl& K, const RE* e, const doubl
   return nan_seen;
 }
 
+// The error norm's largest ratio given the position half's, mx: mx against
+// the velocity half's.  Every velocity scale is at least AbsTol/RelTol, so a
+// velocity ratio as ratio() forms it (within 2^-45 of |e| RelTol/AbsTol) is
+// below max_c |e_c| vbound; when that bound is at most mx the maximum is mx
+// itself, and the velocity half's scales and reciprocals are not formed (for
+// thermal collisions the velocity scales sit at the floor AbsTol/RelTol, far
+// above |v|, and the position half decides every step).  The result is the
+// same either way.  nan_v: whether an e is NaN.
+template <class RE>
+__device__ __forceinline__ double with_velocity_half(const Ctl& K, const RE* e, const double* v,
+                                                     const double* vn, double mx, bool& nan_v) {
+  double a[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) a[c] = (double)e[c];
+  nan_v = (a[0] != a[0]) || (a[3] != a[3]) || (a[1] != a[1]) || (a[4] != a[4]) ||
+          (a[2] != a[2]) || (a[5] != a[5]);
+  const double big = max_abs(max_abs(max_abs(a[0], a[3]), max_abs(a[1], a[4])), max_abs(a[2], a[5]));
+  if (big * K.vbound <= mx) return mx;
+  double mv;
+  half_norm(K, e, v, vn, mv);
+  return vmax(mx, mv);
+}
+
 // The rest of an attempt, the same in every path: the error test and ode45's
 // step-size control; on acceptance advance() moves the lane's state to tnew
 // (the phase is rotated here), and the observables and exits are updated from
@@ -794,15 +821,16 @@ __device__ __forceinline__ void attempt(const F& P, const Ctl& K, Lane& L) {
   // stage 7 at tnew; tnew == t + h unless the step was stretched onto tf
   const double cos7 = L.done ? cos_rf(K.omega * tnew) : cs6;
   // error norm (order in half_norm()): the position half, stage 7, the
-  // velocity half, then one reciprocal
-  double mx, mv;
+  // velocity half
+  double mx;
   const bool nan_x = half_norm(K, ex, x, xn, mx);
   const double r2n = accel(P, cos7, xn, F7, dx, dy, dz);
   double ev7[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) ev7[c] = fma(E7, F7[c], ev[c]);
-  const bool nan_v = half_norm(K, ev7, v, vn, mv);
-  const double err = (nan_x || nan_v) ? __builtin_nan("") : h * vmax(mx, mv);
+  bool nan_v;
+  const double m = with_velocity_half(K, ev7, v, vn, mx, nan_v);
+  const double err = (nan_x || nan_v) ? __builtin_nan("") : h * m;
   conclude_lane(K, L, t, h, tnew, err, xn, vn, F7, cs6, sn6, dx, dy, dz, r2n);
 }
 
@@ -904,7 +932,7 @@ __device__ __forceinline__ void attempt32(const Force32& P, const Ctl& K, Lane& 
   }
   // error norm in double, as in attempt(): the position half, stage 7 at tnew
   // from the new double state, the velocity half
-  double mx, mv;
+  double mx;
   const bool nan_x = half_norm(K, ex, x, xn, mx);
   const double cos7 = L.done ? cos_rf(K.omega * tnew) : cs6;
   const double dx = xn[0] - xn[3], dy = xn[1] - xn[4], dz = xn[2] - xn[5];
@@ -917,8 +945,9 @@ __device__ __forceinline__ void attempt32(const Force32& P, const Ctl& K, Lane& 
   float ev7[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) ev7[c] = fmaf(E7f, F7[c], ev[c]);
-  const bool nan_v = half_norm(K, ev7, v, vn, mv);
-  const double err = (nan_x || nan_v) ? __builtin_nan("") : h * vmax(mx, mv);
+  bool nan_v;
+  const double m = with_velocity_half(K, ev7, v, vn, mx, nan_v);
+  const double err = (nan_x || nan_v) ? __builtin_nan("") : h * m;
   conclude_lane(K, L, t, h, tnew, err, xn, vn, F7, cs6, sn6, dx, dy, dz, r2n);
 }
 
@@ -1240,15 +1269,22 @@ __device__ __forceinline__ void attempt_wide(const F& P, double ka, double kq, c
 
   const double e7i = fma(E7, F7i, evi), e7a = fma(E7, F7a, eva);
   nan_here |= (e7i != e7i) | (e7a != e7a);
-  double mv = vmax(ratio(e7i, max_abs(max_abs(vi, vni), K.thr)),
-                   ratio(e7a, max_abs(max_abs(va, vna), K.thr)));
-  {
+  // the velocity half as in with_velocity_half(): skipped when each axis's
+  // bound max(|e|) vbound is at most mx (decided per quad, so that the quad's
+  // lanes stay together for the exchanges below)
+  int need_v = !(max_abs(e7i, e7a) * K.vbound <= mx);
+  need_v = from_quad_lane<0>(need_v) | from_quad_lane<1>(need_v) | from_quad_lane<2>(need_v);
+  double m = mx;
+  if (need_v) {
+    double mv = vmax(ratio(e7i, max_abs(max_abs(vi, vni), K.thr)),
+                     ratio(e7a, max_abs(max_abs(va, vna), K.thr)));
     const double my = from_quad_lane<1>(mv), mz = from_quad_lane<2>(mv);
     mv = vmax(vmax(from_quad_lane<0>(mv), my), mz);
+    m = vmax(mx, mv);
   }
   const int nan_seen =
       from_quad_lane<0>(nan_here) | from_quad_lane<1>(nan_here) | from_quad_lane<2>(nan_here);
-  const double err = nan_seen ? __builtin_nan("") : h * vmax(mx, mv);
+  const double err = nan_seen ? __builtin_nan("") : h * m;
 
   conclude(
       K, L, t, h, tnew, err, cs6, sn6, r2n,
@@ -2149,6 +2185,7 @@ Launch launch_constants(const ai_params* p, int64_t n, int64_t ld, double t0, do
   P.rtol = rtol;
   P.inv_rtol = 1.0 / rtol;
   P.thr = atol / rtol;
+  P.vbound = (rtol / atol) * (1.0 + 0x1p-20);
   P.hinit_den = 0.8 * std::pow(rtol, 0.2);
   P.max_steps = (int)p->max_steps;
   P.n = n;

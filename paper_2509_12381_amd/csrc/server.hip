@@ -94,6 +94,34 @@ struct SlabSpace {
 
 using RequestPtr = std::shared_ptr<Request>;
 
+// The copy kind between the slab and a caller's buffer.  A copy within
+// device memory goes to a DMA engine: a copy kernel would need wave slots,
+// and the resident kernel holds all of them while it has work (idle waves
+// leave only after idle_ms), so such a copy could wait for a lull in the
+// stream.  Host buffers are copied as the runtime sees fit.
+hipMemcpyKind copy_kind(const void* user) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, user) != hipSuccess) {
+    (void)hipGetLastError();
+    return hipMemcpyDefault;
+  }
+  return attr.type == hipMemoryTypeDevice ? hipMemcpyDeviceToDeviceNoCU : hipMemcpyDefault;
+}
+
+// `planes` rows of `width` bytes between pitched buffers: one 2-D copy, or
+// plane by plane for the DMA engines' device-to-device kind.
+hipError_t copy_planes(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
+                       size_t planes, hipMemcpyKind kind, hipStream_t s) {
+  if (kind != hipMemcpyDeviceToDeviceNoCU)
+    return hipMemcpy2DAsync(dst, dpitch, src, spitch, width, planes, kind, s);
+  for (size_t c = 0; c < planes; ++c) {
+    const hipError_t e = hipMemcpyAsync((char*)dst + c * dpitch, (const char*)src + c * spitch,
+                                        width, kind, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace
 
 struct ai_server {
@@ -307,8 +335,8 @@ void ai_server::dispatch() {
       double* y0s = (double*)(slab + r->slab_off);
       hipError_t e = hipEventCreateWithFlags(&r->copied_in, hipEventDisableTiming);
       if (e == hipSuccess)
-        e = hipMemcpy2DAsync(y0s, pb, it.y0, (size_t)it.ld * 8, (size_t)it.n * 8, 12,
-                             hipMemcpyDefault, in_stream);
+        e = copy_planes(y0s, pb, it.y0, (size_t)it.ld * 8, (size_t)it.n * 8, 12,
+                        copy_kind(it.y0), in_stream);
       if (e == hipSuccess) e = hipEventRecord(r->copied_in, in_stream);
       if (e != hipSuccess) {
         finish(r, AI_EHIP, hip_error(e, "copy in"));
@@ -394,11 +422,11 @@ void ai_server::dispatch() {
       const char* base = slab + r->slab_off;
       hipError_t e = hipEventCreateWithFlags(&r->copied_out, hipEventDisableTiming);
       if (e == hipSuccess)
-        e = hipMemcpy2DAsync(itm.final_state, (size_t)itm.ld * 8, base + 12 * pb, pb,
-                             (size_t)itm.n * 8, 12, hipMemcpyDefault, out_stream);
+        e = copy_planes(itm.final_state, (size_t)itm.ld * 8, base + 12 * pb, pb,
+                        (size_t)itm.n * 8, 12, copy_kind(itm.final_state), out_stream);
       if (e == hipSuccess)
-        e = hipMemcpy2DAsync(itm.obs, (size_t)itm.ld * 8, base + 24 * pb, pb, (size_t)itm.n * 8,
-                             AI_NOBS, hipMemcpyDefault, out_stream);
+        e = copy_planes(itm.obs, (size_t)itm.ld * 8, base + 24 * pb, pb, (size_t)itm.n * 8,
+                        AI_NOBS, copy_kind(itm.obs), out_stream);
       if (e == hipSuccess) e = hipEventRecord(r->copied_out, out_stream);
       if (e != hipSuccess) {
         (void)hipStreamSynchronize(out_stream);  // the slab space is not reused under a copy
