@@ -165,6 +165,25 @@ int ai_integrate_async(const ai_params *p, const double *y0, int64_t n, int64_t 
                        double tmax, double rtol, double atol, double *final_state, double *obs,
                        int32_t kernel, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): as
+ * ai_integrate_async, but the schedule's workspace and the persistent kernel's
+ * queue counter come from a scratch array of AI_STATIC_SCRATCH_BYTES that the
+ * library holds in each device's memory until the process ends, so the call
+ * allocates nothing.  A scheduled call takes at most AI_STATIC_MAX_SCHEDULED
+ * trajectories (AI_EINVAL beyond; unscheduled calls take any n), and
+ * AI_TIME_KERNEL is refused (AI_EINVAL).  Every call on a device shares that
+ * device's scratch and it keeps the last call's contents (the queue counter
+ * is cleared by a kernel at the start of each persistent call), so calls
+ * whose work overlaps on one device, from any stream or thread, race: the
+ * caller orders them.  The schedule's sort clears buffers with memsets, so
+ * only unscheduled calls are for graph capture. */
+#define AI_STATIC_SCRATCH_BYTES (32ull << 20)
+#define AI_STATIC_MAX_SCHEDULED (1 << 20)
+int ai_integrate_static_async(const ai_params *p, const double *y0, int64_t n, int64_t ld,
+                              double t0, double tmax, double rtol, double atol,
+                              double *final_state, double *obs, int32_t kernel, void *stream);
+
 /* Choose the fastest kernel configuration for an ensemble by running it: the
  * ensemble is integrated with each of AI_KERNEL_PLAIN,
  * AI_KERNEL_PLAIN | AI_SCHEDULE_LONGEST_FIRST | AI_WIDE(c) for c = 0, 1, 2

@@ -26,7 +26,7 @@ TIME_KERNEL = 64                      # AI_TIME_KERNEL
 OK, WRTOL, EINVAL, EHIP, ENOMEM, EUNSUPPORTED, EAGAIN = 0, 1, -1, -2, -3, -4, -5
 
 # exported symbols of the C ABI, in declaration order
-SYMBOLS = ("ai_integrate", "ai_integrate_async", "ai_integrate_batch",
+SYMBOLS = ("ai_integrate", "ai_integrate_async", "ai_integrate_static_async", "ai_integrate_batch",
            "ai_integrate_batch_async", "ai_batch_plan_create", "ai_batch_plan_launch",
            "ai_batch_plan_destroy", "ai_tune", "ai_tune_batch", "ai_trace", "ai_server_create",
            "ai_server_submit", "ai_server_wait", "ai_server_destroy", "ai_kernel_time",
@@ -116,6 +116,8 @@ def load(path: str = LIB_PATH):
         lib.ai_integrate.restype = C.c_int
         lib.ai_integrate_async.argtypes = args + [C.c_void_p]
         lib.ai_integrate_async.restype = C.c_int
+        lib.ai_integrate_static_async.argtypes = args + [C.c_void_p]
+        lib.ai_integrate_static_async.restype = C.c_int
         lib.ai_integrate_batch.argtypes = [C.POINTER(AiBatchItem), C.c_int32, C.c_int32]
         lib.ai_integrate_batch.restype = C.c_int
         lib.ai_integrate_batch_async.argtypes = [C.POINTER(AiBatchItem), C.c_int32, C.c_int32,
@@ -230,6 +232,19 @@ def ai_integrate_async(system, y0, t0, tmax, rtol, atol, final_state, obs, kerne
     return _check(load().ai_integrate_async(*_args(system, y0, n, t0, tmax, rtol, atol,
                                                    final_state, obs, k),
                                             C.c_void_p(s.cuda_stream)))
+
+
+def ai_integrate_static_async(system, y0, t0, tmax, rtol, atol, final_state, obs,
+                              kernel="plain", n=None, stream=None, schedule=None, refill_min=0,
+                              precision="fp64"):
+    """ai_integrate_static_async (no device allocation: the library's static
+    scratch) on `stream` (default: torch's current stream)."""
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    k = kernel_code(kernel, schedule, refill_min, precision)
+    return _check(load().ai_integrate_static_async(*_args(system, y0, n, t0, tmax, rtol, atol,
+                                                          final_state, obs, k),
+                                                   C.c_void_p(s.cuda_stream)))
 
 
 def batch_items(items, host_ok: bool = False) -> "C.Array":

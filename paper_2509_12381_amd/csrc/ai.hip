@@ -2085,6 +2085,37 @@ int device_facts(int dev, DeviceFacts** out) {
   return AI_OK;
 }
 
+// The static scratch of ai_integrate_static_async: its first
+// AI_STATIC_QUEUE_BYTES hold the persistent kernel's queue counter, the rest
+// the schedule's workspace.  Each device holds its own copy until the process
+// ends; host code addresses it only through the device address
+// hipGetSymbolAddress gives on that device (the array's host-side name is a
+// stand-in, not device memory).
+constexpr size_t AI_STATIC_QUEUE_BYTES = 256;
+static_assert(AI_STATIC_SCRATCH_BYTES > AI_STATIC_QUEUE_BYTES, "scratch size");
+static __device__ __align__(256) unsigned char scratch[AI_STATIC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mutex;
+char* g_scratch[64] = {};
+
+// The device address of this device's static scratch, looked up once per
+// device (dev must be the current device).
+int static_scratch(int dev, char** out) {
+  if (dev < 0 || dev >= 64) return fail(AI_EHIP, "device ordinal %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    }
+    g_scratch[dev] = (char*)ptr;
+  }
+  *out = g_scratch[dev];
+  return AI_OK;
+}
+
 // Host memory (pinned, registered or pageable), as opposed to device memory.
 bool is_host_memory(const void* ptr) {
   hipPointerAttribute_t attr;
@@ -2547,12 +2578,19 @@ int ai_get_kernel_info(int32_t kernel, ai_kernel_info* info) {
   return AI_OK;
 }
 
-int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t ld, double t0,
-                       double tmax, double rtol, double atol, double* final_state, double* obs,
-                       int32_t kernel, void* stream) {
-  g_error.clear();
-  int rc = validate(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs, kernel);
-  if (rc != AI_OK) return rc;
+}  // extern "C"
+
+namespace {
+
+// ai_integrate_async's work.  scratch: NULL, or the library's static device
+// scratch of this device (AI_STATIC_SCRATCH_BYTES), from which the schedule's
+// workspace and the persistent kernel's queue counter are taken instead of the
+// stream-ordered allocator; the caller has validated the arguments and checked
+// what needs checking against the scratch's capacity.
+int integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t ld, double t0,
+                    double tmax, double rtol, double atol, double* final_state, double* obs,
+                    int32_t kernel, void* stream, char* scratch_ptr) {
+  int rc = AI_OK;
   int warn = AI_OK;
   if (rtol < 100.0 * 2.220446049250313e-16) {
     rtol = 100.0 * 2.220446049250313e-16;
@@ -2579,7 +2617,9 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
   void* order_ws = nullptr;
   if ((kernel & AI_SCHEDULE_LONGEST_FIRST) && n <= 0xffffffffLL) {
     e = ai_longest_first_order(y0, n, ld, order_model(p, t0, tmax, rtol, false), &order, &key,
-                               &order_ws, s);
+                               &order_ws, s, scratch_ptr ? scratch_ptr + AI_STATIC_QUEUE_BYTES
+                                                         : nullptr,
+                               scratch_ptr ? AI_STATIC_SCRATCH_BYTES - AI_STATIC_QUEUE_BYTES : 0);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return e == hipErrorOutOfMemory ? fail(AI_ENOMEM, "schedule workspace: %s",
@@ -2617,40 +2657,88 @@ int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t 
   const long long need = (n + BLOCK - 1) / BLOCK;
   if (blocks > need) blocks = need;
   P.first_dynamic = blocks * BLOCK;
-  unsigned long long* queue = nullptr;
-  if ((e = hipMallocAsync((void**)&queue, sizeof(unsigned long long), s)) != hipSuccess) {
+  unsigned long long* queue = (unsigned long long*)scratch_ptr;
+  // the queue counter: from the static scratch, else stream-ordered (released
+  // by free_queue)
+  auto free_queue = [&]() -> hipError_t {
+    return scratch_ptr ? hipSuccess : hipFreeAsync(queue, s);
+  };
+  if (!queue && (e = hipMallocAsync((void**)&queue, sizeof(unsigned long long), s)) != hipSuccess) {
     (void)hipGetLastError();
     release();
     return fail(AI_ENOMEM, "hipMallocAsync(queue): %s", hipGetErrorString(e));
   }
   hipLaunchKernelGGL(ai_queue_reset_kernel, dim3(1), dim3(1), 0, s, queue);
   if ((e = hipGetLastError()) != hipSuccess) {
-    (void)hipFreeAsync(queue, s);
+    (void)free_queue();
     release();
     return hip_fail(e, "launch(queue reset)");
   }
   P.queue = queue;
   if ((rc = time_mark(kernel, true, s)) != AI_OK) {
-    (void)hipFreeAsync(queue, s);
+    (void)free_queue();
     release();
     return rc;
   }
   hipLaunchKernelGGL(ai_persistent_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, P);
   if ((e = hipGetLastError()) != hipSuccess) {
-    (void)hipFreeAsync(queue, s);
+    (void)free_queue();
     release();
     return hip_fail(e, "launch(persistent)");
   }
   if ((rc = time_mark(kernel, false, s)) != AI_OK) {
-    (void)hipFreeAsync(queue, s);
+    (void)free_queue();
     release();
     return rc;
   }
-  if ((e = hipFreeAsync(queue, s)) != hipSuccess) {
+  if ((e = free_queue()) != hipSuccess) {
     release();
     return hip_fail(e, "hipFreeAsync(queue)");
   }
   return conclude();
+}
+
+}  // namespace
+
+extern "C" {
+
+int ai_integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t ld, double t0,
+                       double tmax, double rtol, double atol, double* final_state, double* obs,
+                       int32_t kernel, void* stream) {
+  g_error.clear();
+  const int rc = validate(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs, kernel);
+  if (rc != AI_OK) return rc;
+  return integrate_async(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs, kernel, stream,
+                         nullptr);
+}
+
+int ai_integrate_static_async(const ai_params* p, const double* y0, int64_t n, int64_t ld,
+                              double t0, double tmax, double rtol, double atol,
+                              double* final_state, double* obs, int32_t kernel, void* stream) {
+  g_error.clear();
+  const int rc = validate(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs, kernel);
+  if (rc != AI_OK) return rc;
+  if (kernel & AI_TIME_KERNEL)
+    return fail(AI_EINVAL, "AI_TIME_KERNEL needs events of its own: not in the static variant");
+  if ((kernel & AI_SCHEDULE_LONGEST_FIRST) && n > AI_STATIC_MAX_SCHEDULED)
+    return fail(AI_EINVAL, "n = %lld: a scheduled call takes at most %d trajectories here",
+                (long long)n, AI_STATIC_MAX_SCHEDULED);
+  if (n == 0) return integrate_async(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs,
+                                     kernel, stream, nullptr);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  char* scratch_ptr = nullptr;
+  int frc = static_scratch(dev, &scratch_ptr);
+  if (frc != AI_OK) return frc;
+  if (kernel & AI_SCHEDULE_LONGEST_FIRST) {
+    const size_t need = ai_order_workspace_bytes(n, (hipStream_t)stream);
+    if (need == 0 || need > AI_STATIC_SCRATCH_BYTES - AI_STATIC_QUEUE_BYTES)
+      return fail(AI_EINVAL, "the schedule of %lld trajectories needs %zu bytes of scratch; %zu held",
+                  (long long)n, need, (size_t)(AI_STATIC_SCRATCH_BYTES - AI_STATIC_QUEUE_BYTES));
+  }
+  return integrate_async(p, y0, n, ld, t0, tmax, rtol, atol, final_state, obs, kernel, stream,
+                         scratch_ptr);
 }
 
 int ai_trace(const ai_params* p, const double* y0, double t0, double tmax, double rtol,

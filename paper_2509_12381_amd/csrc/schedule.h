@@ -83,10 +83,18 @@ ai_order_model ai_make_order_model(const double a[3], const double q[3], double 
 // *workspace, which the caller releases with hipFreeAsync on the same stream
 // once the consumer has been enqueued.  The keys are the costs' codes
 // (AI_ORDER_CODES levels up to horizon x rate), equal codes in index order.
-// Needs n < 2^32.
+// Needs n < 2^32.  With ext (device memory of ext_bytes, at least
+// ai_order_workspace_bytes(n), 256-byte aligned) the work uses that buffer
+// instead, allocates nothing and leaves *workspace NULL; the buffer must stay
+// untouched until the consumer of *order and *key has run.
 hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld,
                                   const ai_order_model& model, unsigned** order, unsigned** key,
-                                  void** workspace, hipStream_t stream);
+                                  void** workspace, hipStream_t stream, void* ext = nullptr,
+                                  size_t ext_bytes = 0);
+
+// Bytes of the workspace ai_longest_first_order needs for n trajectories (0
+// if n is out of range).
+size_t ai_order_workspace_bytes(int64_t n, hipStream_t stream);
 
 // One ensemble of a batched ordering: its initial states and what the
 // prediction needs; its trajectories hold the global indices

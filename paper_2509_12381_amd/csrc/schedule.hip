@@ -282,24 +282,41 @@ namespace {
 using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
                                               rocprim::default_config, 4096>;
 
+// Bytes of the workspace for n keys (the four arrays and the sort's scratch),
+// or 0 if rocPRIM cannot size it.
+size_t workspace_bytes(int64_t n, size_t* temp_out, hipStream_t stream) {
+  size_t temp_bytes = 0;
+  if (rocprim::radix_sort_pairs_desc<SortConfig>(nullptr, temp_bytes, (unsigned*)nullptr,
+                                                 (unsigned*)nullptr, (unsigned*)nullptr,
+                                                 (unsigned*)nullptr, (unsigned)n, 0,
+                                                 AI_ORDER_CODE_BITS, stream) != hipSuccess)
+    return 0;
+  if (temp_out) *temp_out = temp_bytes;
+  return 4 * align256(sizeof(unsigned) * (size_t)n) + align256(temp_bytes);
+}
+
+// ext: a caller's workspace of ext_bytes (nothing is allocated, *workspace
+// stays NULL), or NULL to allocate one on the stream.
 template <class Launch>
 hipError_t sort_by_key(int64_t n, unsigned** order, unsigned** key, void** workspace,
-                       hipStream_t stream, Launch launch) {
+                       hipStream_t stream, Launch launch, char* ext = nullptr,
+                       size_t ext_bytes = 0) {
   *order = nullptr;
   *key = nullptr;
   *workspace = nullptr;
   if (n <= 0 || n > 0xffffffffLL) return hipErrorInvalidValue;
   const unsigned size = (unsigned)n;
   size_t temp_bytes = 0;
-  hipError_t e = rocprim::radix_sort_pairs_desc<SortConfig>(nullptr, temp_bytes, (unsigned*)nullptr,
-                                                (unsigned*)nullptr, (unsigned*)nullptr,
-                                                (unsigned*)nullptr, size, 0, AI_ORDER_CODE_BITS,
-                                                stream);
-  if (e != hipSuccess) return e;
+  const size_t total = workspace_bytes(n, &temp_bytes, stream);
+  if (total == 0) return hipErrorInvalidValue;
   const size_t ubytes = align256(sizeof(unsigned) * (size_t)n);
-  const size_t total = 4 * ubytes + align256(temp_bytes);
-  char* base = nullptr;
-  if ((e = hipMallocAsync((void**)&base, total, stream)) != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  char* base = ext;
+  if (ext) {
+    if (total > ext_bytes) return hipErrorInvalidValue;
+  } else if ((e = hipMallocAsync((void**)&base, total, stream)) != hipSuccess) {
+    return e;
+  }
   unsigned* key_in = (unsigned*)base;
   unsigned* key_out = (unsigned*)(base + ubytes);
   unsigned* idx_in = (unsigned*)(base + 2 * ubytes);
@@ -310,12 +327,12 @@ hipError_t sort_by_key(int64_t n, unsigned** order, unsigned** key, void** works
     e = rocprim::radix_sort_pairs_desc<SortConfig>(temp, temp_bytes, key_in, key_out, idx_in,
                                                    idx_out, size, 0, AI_ORDER_CODE_BITS, stream);
   if (e != hipSuccess) {
-    (void)hipFreeAsync(base, stream);
+    if (!ext) (void)hipFreeAsync(base, stream);
     return e;
   }
   *order = idx_out;
   *key = key_out;
-  *workspace = base;
+  *workspace = ext ? nullptr : base;
   return hipSuccess;
 }
 
@@ -443,16 +460,24 @@ ai_order_model ai_make_order_model(const double a[3], const double q[3], double 
   return m;
 }
 
+size_t ai_order_workspace_bytes(int64_t n, hipStream_t stream) {
+  return n > 0 && n <= 0xffffffffLL ? workspace_bytes(n, nullptr, stream) : 0;
+}
+
 hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld,
                                   const ai_order_model& model, unsigned** order, unsigned** key,
-                                  void** workspace, hipStream_t stream) {
+                                  void** workspace, hipStream_t stream, void* ext,
+                                  size_t ext_bytes) {
   const float scale = code_scale((double)model.horizon * model.rate);
   const unsigned threads = 256;
   const unsigned blocks = (unsigned)((n + threads - 1) / threads);
-  return sort_by_key(n, order, key, workspace, stream, [&](unsigned* key_in, unsigned* idx_in) {
-    hipLaunchKernelGGL(ai_cost_key_kernel, dim3(blocks), dim3(threads), 0, stream, y0,
-                       (long long)n, (long long)ld, model, scale, key_in, idx_in);
-  });
+  return sort_by_key(
+      n, order, key, workspace, stream,
+      [&](unsigned* key_in, unsigned* idx_in) {
+        hipLaunchKernelGGL(ai_cost_key_kernel, dim3(blocks), dim3(threads), 0, stream, y0,
+                           (long long)n, (long long)ld, model, scale, key_in, idx_in);
+      },
+      (char*)ext, ext_bytes);
 }
 
 hipError_t ai_longest_first_order_batch(const ai_order_item* items, int count, int64_t total,

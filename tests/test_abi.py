@@ -26,7 +26,8 @@ def lib():
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    assert names == sorted(["ai_integrate", "ai_integrate_async", "ai_integrate_batch",
+    assert names == sorted(["ai_integrate", "ai_integrate_async", "ai_integrate_static_async",
+                            "ai_integrate_batch",
                             "ai_integrate_batch_async", "ai_batch_plan_create",
                             "ai_batch_plan_launch", "ai_batch_plan_destroy", "ai_tune",
                             "ai_tune_batch",
@@ -230,3 +231,17 @@ def test_invalid_arguments_are_refused_before_any_device_call(lib):
     assert binding.ai_last_error().startswith("item 1:")
     assert b.ai_integrate_batch_async(items, 0, 0, None) == binding.OK  # nothing enqueued
 
+
+
+def test_static_entry_point_argument_errors_without_gpu(lib):
+    """ai_integrate_static_async refuses what ai_integrate refuses (NULL
+    parameters, n < 0, ld < n) before any device call."""
+    from paper_2509_12381_amd import binding, workload as W
+    L = binding.load()
+    p = binding.params(W.small_ensemble().system)
+    f = L.ai_integrate_static_async
+    assert f(None, None, 0, 0, 0.0, 1.0, 1e-8, 1e-10, None, None, 0, None) == binding.EINVAL
+    assert f(ctypes.byref(p), None, -1, 0, 0.0, 1.0, 1e-8, 1e-10, None, None, 0,
+             None) == binding.EINVAL
+    assert f(ctypes.byref(p), None, 5, 4, 0.0, 1.0, 1e-8, 1e-10, None, None, 0,
+             None) == binding.EINVAL
