@@ -112,13 +112,13 @@ enum ai_kernel {
  * the predicted duration of the longest trajectory they hold. */
 #define AI_REFILL_MIN(k) ((int32_t)(k) << 8)
 
-/* Plain kernel with AI_SCHEDULE_LONGEST_FIRST (single calls and batches),
- * OR-ed into the kernel argument: how many of the leading positions of the
- * longest-first order (the trajectories predicted to take longest) run four
- * lanes each, one spatial axis per lane, so that they end sooner (the launch
- * ends with them): code 0 = 256 (the default), 1 = none, 2 = 1024, 3 = 4096.
- * Changes which lanes integrate a trajectory, never a result.  Ignored with
- * AI_FP32_STAGES and by the persistent kernel. */
+/* With AI_SCHEDULE_LONGEST_FIRST (single calls with either kernel, and
+ * batches), OR-ed into the kernel argument: how many of the leading positions
+ * of the longest-first order (the trajectories predicted to take longest) run
+ * four lanes each, one spatial axis per lane, so that they end sooner (the
+ * launch ends with them): code 0 = 256 (the default), 1 = none, 2 = 1024,
+ * 3 = 4096.  Changes which lanes integrate a trajectory, never a result.
+ * Ignored with AI_FP32_STAGES. */
 #define AI_WIDE(code) ((int32_t)(code) << 16)
 
 enum ai_rc {

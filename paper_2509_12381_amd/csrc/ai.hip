@@ -336,12 +336,9 @@ __device__ __forceinline__ Rot rot_small(double u) {
   s = fma(s, u2, -1.0 / 6.0);                            // -1/3!
   return {fma(c, u2, 1.0), fma(s * u2, u, u)};
 }
-// Sum and difference of two angles, and twice an angle.
+// Sum of two angles, and twice an angle.
 __device__ __forceinline__ Rot rot_add(Rot a, Rot b) {
   return {fma(a.c, b.c, -(a.s * b.s)), fma(a.s, b.c, a.c * b.s)};
-}
-__device__ __forceinline__ Rot rot_sub(Rot a, Rot b) {
-  return {fma(a.c, b.c, a.s * b.s), fma(a.s, b.c, -(a.c * b.s))};
 }
 __device__ __forceinline__ Rot rot_twice(Rot a) {
   const double s2 = a.s + a.s;
@@ -565,7 +562,8 @@ __device__ __forceinline__ void stage_phases(const Ctl& K, double cph, double sp
   // from h by the rounding of t + h, a stage-time shift no larger than the
   // rounding of t + c h itself).  The angles are built from theta = d/10 and
   // phi = d/9 (d = omega (t_new - t)): 2, 3, 8 and 10 theta by doubling and
-  // addition, 8/9 d = 10 theta - phi.  The stage-6 rotation also advances the
+  // addition; the phase at 8/9 d is the end phase (10 theta) turned back by
+  // phi.  The stage-6 rotation also advances the
   // phase on acceptance.  A lane whose step spans more than SMALL_ANGLE
   // radians evaluates each phase directly instead.
   const double tn = t + h;
@@ -574,14 +572,14 @@ __device__ __forceinline__ void stage_phases(const Ctl& K, double cph, double sp
   {
     const Rot r1 = rot_small(0.1 * d6), phi = rot_small((1.0 / 9.0) * d6);
     const Rot r2 = rot_twice(r1), r3 = rot_add(r2, r1), r4 = rot_twice(r2);
-    const Rot r8 = rot_twice(r4), r10 = rot_add(r8, r2), r89 = rot_sub(r10, phi);
+    const Rot r8 = rot_twice(r4), r10 = rot_add(r8, r2);
     const double C = cph, S = sph;
     cs2 = fma(C, r2.c, -(S * r2.s));
     cs3 = fma(C, r3.c, -(S * r3.s));
     cs4 = fma(C, r8.c, -(S * r8.s));
-    cs5 = fma(C, r89.c, -(S * r89.s));
     cs6 = fma(C, r10.c, -(S * r10.s));
     sn6 = fma(S, r10.c, C * r10.s);
+    cs5 = fma(cs6, phi.c, sn6 * phi.s);  // the end phase turned back by d/9
     if (!(fabs(d6) <= SMALL_ANGLE)) {
       cs2 = cos_rf(omega * fma(C2, h, t));
       cs3 = cos_rf(omega * fma(C3, h, t));
@@ -616,8 +614,11 @@ __device__ __forceinline__ void pick(double& na, double& da, double nb, double d
 // error below 2^-23) refined by one Newton step, r (1 + (1 - s r)), to a
 // relative error below 2^-46, times |e|.  The norm's largest ratio then
 // differs from the quotients' by at most that much (ties within it may pick
-// either component, which changes the norm by no more), far below the error
-// estimate's own rounding noise.  s = inf gives NaN, which only a non-finite
+// either component, which changes the norm by no more), so an accept/reject
+// decision differs from the exact division's only where err lies within
+// ~1e-14 of RelTol.  (The estimate alone, 2^-23, flipped such decisions: one
+// of 95 non-chaotic trajectories of a 10 uK ensemble then took another step
+// sequence and ended 5e-5 away.)  s = inf gives NaN, which only a non-finite
 // solution can produce (the attempt then ends as non-finite either way).
 __device__ __forceinline__ double ratio(double e, double s) {
   const double r = __builtin_amdgcn_rcp(s);
@@ -994,23 +995,34 @@ struct Derived {
   double lifetime, angle, transfer, dist, ke, rmin;
 };
 
-__device__ __forceinline__ Derived derive(double t_first, double t_last, double va0x, double va0y,
-                                          double va0z, double rmin2, double bounces,
-                                          const double* y, double m_atom, double half_mi) {
-  const double cx = fma(va0y, y[11], -(va0z * y[10]));
-  const double cy = fma(va0z, y[9], -(va0x * y[11]));
-  const double cz = fma(va0x, y[10], -(va0y * y[9]));
-  const double dot = fma(va0z, y[11], fma(va0y, y[10], va0x * y[9]));
-  const double dvx = y[9] - va0x, dvy = y[10] - va0y, dvz = y[11] - va0z;
-  const double dx = y[0] - y[6], dy = y[1] - y[7], dz = y[2] - y[8];
+// From the raw accumulators, the atom's initial and final velocity va0, va,
+// the ion's final velocity vi and the final separation d = x_ion - x_atom.
+__device__ __forceinline__ Derived derive_from(double t_first, double t_last, double va0x,
+                                               double va0y, double va0z, double rmin2,
+                                               double bounces, double vix, double viy, double viz,
+                                               double vax, double vay, double vaz, double dx,
+                                               double dy, double dz, double m_atom,
+                                               double half_mi) {
+  const double cx = fma(va0y, vaz, -(va0z * vay));
+  const double cy = fma(va0z, vax, -(va0x * vaz));
+  const double cz = fma(va0x, vay, -(va0y * vax));
+  const double dot = fma(va0z, vaz, fma(va0y, vay, va0x * vax));
+  const double dvx = vax - va0x, dvy = vay - va0y, dvz = vaz - va0z;
   Derived d;
   d.lifetime = bounces >= 2.0 ? t_last - t_first : 0.0;
   d.angle = atan2(sqrt(fma(cz, cz, fma(cy, cy, cx * cx))), dot);
   d.transfer = m_atom * sqrt(fma(dvz, dvz, fma(dvy, dvy, dvx * dvx)));
   d.dist = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
-  d.ke = half_mi * fma(y[5], y[5], fma(y[4], y[4], y[3] * y[3]));
+  d.ke = half_mi * fma(viz, viz, fma(viy, viy, vix * vix));
   d.rmin = sqrt(rmin2);
   return d;
+}
+
+__device__ __forceinline__ Derived derive(double t_first, double t_last, double va0x, double va0y,
+                                          double va0z, double rmin2, double bounces,
+                                          const double* y, double m_atom, double half_mi) {
+  return derive_from(t_first, t_last, va0x, va0y, va0z, rmin2, bounces, y[3], y[4], y[5], y[9],
+                     y[10], y[11], y[0] - y[6], y[1] - y[7], y[2] - y[8], m_atom, half_mi);
 }
 
 __device__ __forceinline__ void finalize_one(const Launch& P, const double* __restrict__ yf,
@@ -1566,6 +1578,15 @@ constexpr int TAIL_ROUNDS = 8;
 // iteration: busy lanes make attempts until enough lanes are free, ended
 // trajectories are stored, and free lanes start staged trajectories.
 __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
+  // the leading positions of a longest-first order: four lanes per
+  // trajectory, as in the plain kernel (these waves then leave)
+  if ((long long)blockIdx.x < P.wide_waves) {
+    const long long first = (long long)blockIdx.x * (WAVE / 4);
+    wave_priority_from_keys(P.key, first);
+    const long long g = first + (threadIdx.x >> 2);
+    if (g < P.wide) integrate_wide<Force>(P, (long long)P.order[g], (int)(threadIdx.x & 3));
+    return;
+  }
   __shared__ double stage_y[12][WAVE];  // staged initial states, component-major
   __shared__ long long stage_idx[WAVE];
   __shared__ float stage_key[WAVE];
@@ -1587,7 +1608,9 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
   const Ctl K = lane_ctl(P);
   const Force Fc = lane_force(P);
   Lane L;
-  long long idx = (long long)blockIdx.x * BLOCK + lane;
+  // statically assigned: the positions after the four-lane ones, a wave's worth each
+  const long long static_first = P.wide + ((long long)blockIdx.x - P.wide_waves) * BLOCK;
+  long long idx = static_first + lane;
   int busy = 0;                             // integrating, or ended and not yet stored
   bool critical = false;                    // wave-uniform
   bool drained = P.first_dynamic >= P.n;    // wave-uniform: no more claims succeed
@@ -1630,7 +1653,7 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_persistent_kernel(Launch P) {
     critical = frac >= 0.5f;
   };
 
-  if (P.key) set_priority(P.key[(long long)blockIdx.x * BLOCK]);  // the grid never exceeds n
+  if (P.key) set_priority(P.key[static_first]);  // the grid never exceeds the positions
   if (idx < P.n) {
     idx = P.order ? (long long)P.order[idx] : idx;
     double y[12];
@@ -1754,6 +1777,21 @@ __device__ __forceinline__ void store_through(double* p, double v) {
                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// A load that is not served from a stale cache line (system scope): the slab's
+// initial states were written by a copy engine, possibly over lines an earlier
+// request left in this die's L2.
+__device__ __forceinline__ double load_through(const double* p) {
+  return __longlong_as_double((long long)__hip_atomic_load(
+      (const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+}
+
+// Wait until this wave's memory operations have completed: its stores written
+// through above are then in memory.  (A release or acquire fence at system or
+// device scope would write back or invalidate the whole L2 of the die, at every
+// finished trajectory and every claim; the kernel needs neither, since the data
+// it shares bypasses the L2 both ways.)
+__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 __device__ __forceinline__ Force32 force32_of(const Force& F) {
   Force32 f;
   f.inv_mi = (float)F.inv_mi;
@@ -1766,6 +1804,18 @@ __device__ __forceinline__ Force32 force32_of(const Force& F) {
     f.kq[k] = (float)F.kq[k];
   }
   return f;
+}
+
+// The derived observables out of line, so that the temporaries of atan2 and
+// the square roots do not add to the registers the integration loop holds
+// (a call on the rare path where a lane ends a trajectory; inlined, it added
+// ~40 registers spilled to scratch).
+__device__ __attribute__((noinline)) Derived resident_derive(
+    double t_first, double t_last, double va0x, double va0y, double va0z, double rmin2,
+    double bounces, double vix, double viy, double viz, double vax, double vay, double vaz,
+    double dx, double dy, double dz, double m_atom, double half_mi) {
+  return derive_from(t_first, t_last, va0x, va0y, va0z, rmin2, bounces, vix, viy, viz, vax, vay,
+                     vaz, dx, dy, dz, m_atom, half_mi);
 }
 
 // The leader lane's claim: up to `want` trajectories of the oldest published
@@ -1819,11 +1869,18 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
   __shared__ int lane_slot[WAVE];
   __shared__ double lane_va0[3][WAVE], lane_m_atom[WAVE], lane_half_mi[WAVE];
   __shared__ long long claim_info[3];   // leader's claim broadcast: seq, first, count
+  // each lane's loop and force constants (its request's), read from LDS at
+  // every attempt rather than held in registers across the loop: they would
+  // add ~40 registers to the ones the loop carries, which the rare start and
+  // store paths then push into scratch
+  __shared__ Ctl lane_K[WAVE];
+  __shared__ Force lane_F[WAVE];
+  __shared__ double lane_near2[WAVE];
   const int lane = (int)threadIdx.x;    // BLOCK == WAVE
+  using LdsCtl = __attribute__((address_space(3))) Ctl*;
+  using LdsForce = __attribute__((address_space(3))) Force*;
+  using LdsDouble = __attribute__((address_space(3))) double*;
   Lane L;
-  Ctl K;
-  Force F;
-  double near2 = 0.0;
   int busy = 0;
   long long cur_seq = -1;               // wave-uniform: request in lds_desc
   long long cur_n = 0;
@@ -1840,9 +1897,36 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
     int since = 0;
     for (;;) {
       if (busy && L.status == 0) {
+        // opaque addresses: the loads stay inside the loop
+        LdsCtl kp = (LdsCtl)&lane_K[lane];
+        LdsForce fp = (LdsForce)&lane_F[lane];
+        LdsDouble np = (LdsDouble)&lane_near2[lane];
+        asm volatile("" : "+v"(kp), "+v"(fp), "+v"(np));
+        Ctl K;
+        K.tf = kp->tf;
+        K.hmax = kp->hmax;
+        K.rtol = kp->rtol;
+        K.inv_rtol = kp->inv_rtol;
+        K.thr = kp->thr;
+        K.vbound = kp->vbound;
+        K.r_exit2 = kp->r_exit2;
+        K.r_bounce2 = kp->r_bounce2;
+        K.omega = kp->omega;
+        K.max_steps = kp->max_steps;
+        K.exit_on = kp->exit_on;
+        Force F;
+        F.inv_mi = fp->inv_mi;
+        F.inv_ma = fp->inv_ma;
+        F.nCn = fp->nCn;
+        F.mCm = fp->mCm;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          F.ka[k] = fp->ka[k];
+          F.kq[k] = fp->kq[k];
+        }
         if (L.fresh) begin_step(K, L);
         const double dx = L.x[0] - L.x[3], dy = L.x[1] - L.x[4], dz = L.x[2] - L.x[5];
-        if (fma(dz, dz, fma(dy, dy, dx * dx)) < near2)
+        if (fma(dz, dz, fma(dy, dy, dx * dx)) < *np)
           attempt(F, K, L);
         else
           attempt32(force32_of(F), K, L);
@@ -1873,9 +1957,10 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
 #pragma unroll
         for (int c = 0; c < 12; ++c) store_through(yf + c * ld + i, y[c]);
         const double bounces = (double)L.bounces;
-        const Derived d = derive(L.t_first, L.t_last, lane_va0[0][lane], lane_va0[1][lane],
-                                 lane_va0[2][lane], L.rmin2, bounces, y, lane_m_atom[lane],
-                                 lane_half_mi[lane]);
+        const Derived d = resident_derive(
+            L.t_first, L.t_last, lane_va0[0][lane], lane_va0[1][lane], lane_va0[2][lane], L.rmin2,
+            bounces, y[3], y[4], y[5], y[9], y[10], y[11], y[0] - y[6], y[1] - y[7], y[2] - y[8],
+            lane_m_atom[lane], lane_half_mi[lane]);
         store_through(ob + AI_OBS_TEND * ld + i, L.t);
         store_through(ob + AI_OBS_STATUS * ld + i, (double)L.status);
         store_through(ob + AI_OBS_NSTEPS * ld + i, (double)L.nsteps);
@@ -1890,9 +1975,8 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
         store_through(ob + AI_OBS_RMIN * ld + i, d.rmin);
         store_through(ob + AI_OBS_HNEXT * ld + i, L.absh);
       }
-      // the stores above are complete and visible before any count that
-      // includes them (release at system scope)
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      // the stores above are in memory before any count that includes them
+      wait_memory();
       unsigned long long todo = ended;
       while (todo) {
         const int leader = __ffsll((long long)todo) - 1;
@@ -1901,10 +1985,10 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
         if (lane == leader) {
           const unsigned long long k = (unsigned long long)__popcll(group);
           const unsigned long long before = __hip_atomic_fetch_add(
-              (unsigned long long*)A.done_cnt + slot, k, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM);
+              (unsigned long long*)A.done_cnt + slot, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
           if (before + k == (unsigned long long)lane_target[lane])
             __hip_atomic_store((unsigned long long*)A.done_seq + slot,
-                               (unsigned long long)lane_seq[lane] + 1ull, __ATOMIC_RELEASE,
+                               (unsigned long long)lane_seq[lane] + 1ull, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_SYSTEM);
         }
         todo &= ~group;
@@ -1919,7 +2003,7 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
       if (freel == 0ull) break;
       if (lane == 0) {
         const unsigned long long pub = __hip_atomic_load((const unsigned long long*)A.pub,
-                                                         __ATOMIC_ACQUIRE,
+                                                         __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_SYSTEM);
         long long seq = -1, first = 0;
         int count = 0;
@@ -1933,9 +2017,8 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
         claim_info[2] = count;
       }
       __syncthreads();
-      // what the leader acquired (the request's initial states in the slab,
-      // copied there before it was published) is visible to every lane
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+      // the request's initial states, copied into the slab before it was
+      // published, are read below with loads that bypass stale cache lines
       const long long seq = claim_info[0], first = claim_info[1];
       const int count = (int)claim_info[2];
       __syncthreads();
@@ -1961,10 +2044,11 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
         const long long i = first + e;
         double y[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) y[c] = P.y0[c * P.ld + i];
-        K = lane_ctl(P);
-        F = lane_force(P);
-        near2 = lds_desc.fp32 ? P.near2 : INFINITY;
+        for (int c = 0; c < 12; ++c) y[c] = load_through(P.y0 + c * P.ld + i);
+        lane_K[lane] = lane_ctl(P);
+        const Force F = lane_force(P);
+        lane_F[lane] = F;
+        lane_near2[lane] = lds_desc.fp32 ? P.near2 : INFINITY;
         lane_yf[lane] = P.yf;
         lane_obs[lane] = P.obs;
         lane_ld[lane] = P.ld;
@@ -2653,10 +2737,19 @@ int integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t ld,
 
   const int refill_min = (kernel >> 8) & 0x7f;
   P.refill_min = refill_min > 0 ? refill_min : 1;
+  // with the schedule, the leading positions run four lanes each in waves of
+  // their own (as in the plain kernel); the other waves start a wave's worth
+  // of the following positions each and draw the rest from the queue
+  if (P.order) {
+    const long long width = wide_trajectories(kernel);
+    P.wide = n < width ? n : width;
+    P.wide_waves = (int)((P.wide + WAVE / 4 - 1) / (WAVE / 4));
+  }
   long long blocks = (long long)f->cus * f->persistent_blocks_per_cu;
-  const long long need = (n + BLOCK - 1) / BLOCK;
+  const long long need = P.wide_waves + (n - P.wide + BLOCK - 1) / BLOCK;
   if (blocks > need) blocks = need;
-  P.first_dynamic = blocks * BLOCK;
+  if (blocks < P.wide_waves) blocks = P.wide_waves;
+  P.first_dynamic = P.wide + (blocks - P.wide_waves) * BLOCK;
   unsigned long long* queue = (unsigned long long*)scratch_ptr;
   // the queue counter: from the static scratch, else stream-ordered (released
   // by free_queue)

@@ -361,10 +361,11 @@ def _four_lane_inputs(wl, oracle_full, n):
 
 @pytest.mark.parametrize("n", [1, 5, 16, 17, 255, 256, 257, 300])
 def test_four_lane_path_agrees_bitwise(ai, torch, oracle_full, n):
-    """The scheduled plain kernel integrates its leading 256 positions with four
-    lanes per trajectory (one axis each).  At sizes that fill the quads and the
-    waves raggedly, its results equal the unscheduled one-lane integration bit
-    for bit, also for bounces, complexes, a non-finite start and the step cap."""
+    """The scheduled plain and persistent kernels integrate their leading 256
+    positions with four lanes per trajectory (one axis each).  At sizes that
+    fill the quads and the waves raggedly, their results equal the unscheduled
+    one-lane integration bit for bit, also for bounces, complexes, a non-finite
+    start and the step cap."""
     import dataclasses
     wl = W.small_ensemble()
     y0 = _four_lane_inputs(wl, oracle_full, n)
@@ -372,11 +373,12 @@ def test_four_lane_path_agrees_bitwise(ai, torch, oracle_full, n):
     for cap in (None, 300):
         system = wl.system if cap is None else dataclasses.replace(wl.system, max_steps=cap)
         a = run_gpu(ai, torch, system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "plain", ld=ld)
-        b = run_gpu(ai, torch, system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "plain", ld=ld,
-                    schedule="longest-first")
-        np.testing.assert_array_equal(a[0], b[0])
-        np.testing.assert_array_equal(a[1], b[1])
-        assert np.all(b[0][:, n:] == -7.0) and np.all(b[1][:, n:] == -7.0)
+        for kernel in ("plain", "persistent"):
+            b = run_gpu(ai, torch, system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, kernel, ld=ld,
+                        schedule="longest-first")
+            np.testing.assert_array_equal(a[0], b[0])
+            np.testing.assert_array_equal(a[1], b[1])
+            assert np.all(b[0][:, n:] == -7.0) and np.all(b[1][:, n:] == -7.0)
         assert a[1][O["status"], 0] == W.ST_NONFINITE
         if cap is None and n >= 42:
             assert np.sum(a[1][O["bounces"], :n] >= 2) >= 1     # complexes among them
@@ -416,14 +418,22 @@ def queue_ensemble(ai, torch):
     return wl, lanes, wl.initial_states(3 * lanes + 5)
 
 
-@pytest.mark.parametrize("extra", [1, 7, 8, 31, 32, 33, 1000, "3x"])
+@pytest.mark.parametrize("extra", [1, 7, 8, 31, 32, 33, 1000, "3x", "s1", "s33"])
 def test_queue_chunks_agree_bitwise(ai, torch, queue_ensemble, extra):
     """Sizes just past the statically assigned lanes, around chunk boundaries
     and through the small chunks near the queue's end: the persistent kernel
     (refill thresholds 1 and 64, with and without the schedule) matches the
-    plain kernel bit for bit, and writes nothing past n."""
+    plain kernel bit for bit, and writes nothing past n.  With the schedule,
+    the first 16 waves take the 256 leading positions four lanes each and the
+    others a wave's worth each, so its static share ends 768 positions
+    earlier ("s" sizes)."""
     wl, lanes, y0all = queue_ensemble
-    n = 3 * lanes + 5 if extra == "3x" else lanes + extra
+    if extra == "3x":
+        n = 3 * lanes + 5
+    elif isinstance(extra, str):
+        n = lanes - 3 * 256 + int(extra[1:])
+    else:
+        n = lanes + extra
     y0 = y0all[:, :n]
     ld = n + 3
     a = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, "plain", ld=ld)
