@@ -1764,6 +1764,10 @@ static_assert(sizeof(ResidentDesc) <= sizeof(ai_resident_desc), "resident descri
 constexpr int RES_DESC_WORDS = (int)((sizeof(ResidentDesc) + 7) / 8);
 static_assert(RES_DESC_WORDS <= WAVE, "one word per lane");
 constexpr int RES_BACKOFF = 64;
+// Trajectories a wave claims at a time (fewer at a request's end); it keeps
+// the unstarted ones of a claim and hands them to its lanes as they free up,
+// so the claim word sees one compare-and-swap per chunk.
+constexpr int RES_CHUNK = 32;
 
 __device__ __forceinline__ unsigned long long load_system(const uint64_t* p) {
   return __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
@@ -1819,43 +1823,46 @@ __device__ __attribute__((noinline)) Derived resident_derive(
 }
 
 // The leader lane's claim: up to `want` trajectories of the oldest published
-// request with work left, as (request, first index, count); false if there
-// is none.  The claim word packs (request << 32 | claimed).  n_of(seq) gives
-// a request's size; it is only asked for the request the word names, which
-// still has unclaimed trajectories, so its descriptor is current.  Bounded: a
-// claim that keeps losing the race is given up (and retried later).
+// request with work left, as (request, first index, count); false if there is
+// none.  Each ring slot has a claim counter packing (request << 32 | claimed),
+// which the host sets to (request << 32) when it publishes the request there;
+// a claim is one fetch-and-add of `want` on the counter of the request the
+// current-request word names, so claims never retry against each other.  The
+// counter's old value says which request the trajectories belong to (and so
+// which descriptor: the ring slot's, copied before the counter was set) and
+// whether any were left; a claim that finds a request exhausted moves the
+// current-request word on (one compare-and-swap, if the next request is
+// published) and tries again.  Counts past a request's size are claims of
+// nothing.  n_of(seq) gives a request's size.  Bounded: gives up after a few
+// rounds (and is retried later).
 template <class SizeOf>
-__device__ bool claim(const ai_resident_args& A, unsigned long long pub, int want, long long& seq,
-                      long long& first, int& count, SizeOf n_of) {
-  unsigned long long h =
-      __hip_atomic_load((unsigned long long*)A.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (int tries = 0; tries < 256; ++tries) {
-    const unsigned long long s = h >> 32, k = h & 0xffffffffull;
+__device__ bool claim(const ai_resident_args& A, int want, long long& seq, long long& first,
+                      int& count, SizeOf n_of) {
+  for (int tries = 0; tries < 8; ++tries) {
+    const unsigned long long pub = load_system(A.pub);
+    unsigned long long s =
+        __hip_atomic_load((unsigned long long*)A.cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (s >= pub) return false;
-    const long long n = n_of((long long)s);
-    unsigned long long next;
-    long long take = 0;
-    if ((long long)k >= n) {
-      next = (s + 1) << 32;
-    } else {
-      take = n - (long long)k < want ? n - (long long)k : want;
-      // the claim that takes a request's last trajectories moves the word on
-      // to the next request, so the word never names a request whose
-      // trajectories are all claimed (and whose ring slot the server may
-      // reuse once they have finished)
-      next = (long long)k + take == n ? (s + 1) << 32 : h + (unsigned long long)take;
+    const unsigned long long v = __hip_atomic_fetch_add(
+        (unsigned long long*)A.claimed + s % (unsigned long long)A.ring, (unsigned long long)want,
+        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long sv = (long long)(v >> 32), k = (long long)(v & 0xffffffffull);
+    if (sv < (long long)s) return false;  // the slot not yet set for s (cannot happen)
+    const long long n = n_of(sv);
+    if (k < n) {
+      seq = sv;
+      first = k;
+      count = (int)(n - k < want ? n - k : want);
+      return true;
     }
-    if (__hip_atomic_compare_exchange_strong((unsigned long long*)A.head, &h, next,
-                                             __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT)) {
-      if (take > 0) {
-        seq = (long long)s;
-        first = (long long)k;
-        count = (int)take;
-        return true;
-      }
-      h = next;
-    }
+    // the request is exhausted (or its slot already holds a later one):
+    // move the current-request word past it
+    if (s + 1 < pub)
+      __hip_atomic_compare_exchange_strong((unsigned long long*)A.cur, &s, s + 1,
+                                           __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    else
+      return false;
   }
   return false;
 }
@@ -1884,6 +1891,7 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
   int busy = 0;
   long long cur_seq = -1;               // wave-uniform: request in lds_desc
   long long cur_n = 0;
+  long long st_next = 0, st_end = 0;    // wave-uniform: claimed, unstarted positions of cur_seq
   unsigned long long idle_since = 0;
   bool idle = false;
   int backoff = 0;                      // attempts before the next claim
@@ -1893,7 +1901,7 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
     // integrate until enough lanes are free to refill (a wave with nothing
     // left to run leaves at once); ended lanes wait, frozen, for their store
     // (after a claim found nothing, wait RES_BACKOFF attempts before asking
-    // again: each look at the request count is a round trip to host memory)
+    // again)
     int since = 0;
     for (;;) {
       if (busy && L.status == 0) {
@@ -2001,43 +2009,48 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
     for (;;) {
       const unsigned long long freel = __ballot(!busy);
       if (freel == 0ull) break;
-      if (lane == 0) {
-        const unsigned long long pub = __hip_atomic_load((const unsigned long long*)A.pub,
-                                                         __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_SYSTEM);
-        long long seq = -1, first = 0;
-        int count = 0;
-        const bool got = claim(A, pub, __popcll(freel), seq, first, count, [&](long long s) {
-          if (s == cur_seq) return cur_n;
-          const ResidentDesc* d = (const ResidentDesc*)&A.desc[s % A.ring];
-          return (long long)load_system((const uint64_t*)&d->P.n);
-        });
-        claim_info[0] = got ? seq : -1;
-        claim_info[1] = first;
-        claim_info[2] = count;
-      }
-      __syncthreads();
-      // the request's initial states, copied into the slab before it was
-      // published, are read below with loads that bypass stale cache lines
-      const long long seq = claim_info[0], first = claim_info[1];
-      const int count = (int)claim_info[2];
-      __syncthreads();
-      if (seq < 0) {
-        backoff = RES_BACKOFF;
-        break;
-      }
-      backoff = 0;
-      claimed_any = true;
-      if (seq != cur_seq) {
-        // the request's descriptor, one word per lane, from host memory
-        const uint64_t* src = A.desc[seq % A.ring].w;
-        if (lane < RES_DESC_WORDS) ((unsigned long long*)&lds_desc)[lane] = load_system(src + lane);
+      if (st_next >= st_end) {
+        if (lane == 0) {
+          long long seq = -1, first = 0;
+          int count = 0;
+          const bool got = claim(A, RES_CHUNK, seq, first, count, [&](long long s) {
+            if (s == cur_seq) return cur_n;
+            const ResidentDesc* d = (const ResidentDesc*)&A.desc[s % A.ring];
+            return (long long)load_system((const uint64_t*)&d->P.n);
+          });
+          claim_info[0] = got ? seq : -1;
+          claim_info[1] = first;
+          claim_info[2] = count;
+        }
         __syncthreads();
-        if (lane == 0) lds_S = start_const(lds_desc.P);
+        // the request's initial states, copied into the slab before it was
+        // published, are read below with loads that bypass stale cache lines
+        const long long seq = claim_info[0], first = claim_info[1];
+        const int count = (int)claim_info[2];
         __syncthreads();
-        cur_seq = seq;
-        cur_n = lds_desc.P.n;
+        if (seq < 0) {
+          backoff = RES_BACKOFF;
+          break;
+        }
+        backoff = 0;
+        claimed_any = true;
+        if (seq != cur_seq) {
+          // the request's descriptor, one word per lane, from the device ring
+          const uint64_t* src = A.desc[seq % A.ring].w;
+          if (lane < RES_DESC_WORDS) ((unsigned long long*)&lds_desc)[lane] = load_system(src + lane);
+          __syncthreads();
+          if (lane == 0) lds_S = start_const(lds_desc.P);
+          __syncthreads();
+          cur_seq = seq;
+          cur_n = lds_desc.P.n;
+        }
+        st_next = first;
+        st_end = first + count;
       }
+      const long long seq = cur_seq;
+      const long long first = st_next;
+      const long long count = st_end - st_next;
+      st_next += __popcll(freel) < count ? __popcll(freel) : count;
       const int e = (int)lanes_below(freel);
       if (!busy && e < count) {
         const Launch& P = lds_desc.P;

@@ -16,13 +16,16 @@ int ai_fail(int rc, const char* msg);
 
 // ---- Resident serving kernel (ai.hip) and its host runtime (server.hip) ----
 //
-// The host publishes requests in a ring of descriptors in host-coherent
-// (fine-grained) memory and counts them in *pub; the kernel's resident waves
-// claim trajectories of the oldest published request that has work left,
-// integrate them from the server's device slab into it, and signal a request's
-// completion by writing its number + 1 into done_seq[slot] (host-coherent).
-// Device memory holds the claim word (request << 32 | claimed) and, per ring
-// slot, the cumulative count of finished trajectories.
+// The host publishes requests by copies on one stream, in order: a request's
+// initial states into the server's device slab, its descriptor into a ring of
+// descriptors in device memory, then the new request count into a device
+// word; the kernel's resident waves claim trajectories of the oldest published
+// request that has work left, integrate them from the slab into it, and
+// signal a request's completion by writing its number + 1 into done_seq[slot]
+// (host-coherent memory, the only host memory the kernel touches).  Device
+// memory also holds the current-request word and, per ring slot, a claim
+// counter (request << 32 | claimed, set by the publication) and the
+// cumulative count of finished trajectories.
 
 #include <stdint.h>
 
@@ -32,11 +35,12 @@ struct ai_resident_desc {
 };
 
 struct ai_resident_args {
-  const ai_resident_desc* desc;  // host-coherent: ring of `ring` descriptors
-  const uint64_t* pub;           // host-coherent: requests published so far
-  const uint64_t* stop;          // host-coherent: nonzero: waves exit once idle
+  const ai_resident_desc* desc;  // device: ring of `ring` descriptors
+  const uint64_t* pub;           // device: requests published so far
+  const uint64_t* stop;          // device: nonzero: waves exit once idle
   uint64_t* done_seq;            // host-coherent: per slot, last completed request + 1
-  uint64_t* head;                // device: claim word, zero at the first launch
+  uint64_t* cur;                 // device: oldest request that may have work left (zero at first)
+  uint64_t* claimed;             // device: per slot, request << 32 | trajectories claimed
   uint64_t* done_cnt;            // device: per slot, finished trajectories (cumulative)
   int32_t ring;                  // descriptor slots
   int32_t refill_min;            // free lanes a busy wave gathers before refilling

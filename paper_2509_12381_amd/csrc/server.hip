@@ -48,12 +48,16 @@ struct Request {
   bool done = false;
   // resident mode
   size_t slab_off = 0, slab_len = 0;
+  bool staged = false;  // buffers in host memory: integrated from and into the slab
   uint64_t seq = 0;
   hipEvent_t copied_in = nullptr, copied_out = nullptr;
 };
 
-// Slab footprint of a request of n trajectories: initial states, final states
-// and observables, each plane rounded up to 256 bytes.
+// Footprint of a request of n trajectories: initial states, final states and
+// observables, each plane rounded up to 256 bytes.  Every admitted request
+// holds that much of the server's budget; one whose buffers are in host
+// memory is integrated from and into that region of the slab, one whose
+// buffers are device memory of the server's device in place.
 size_t plane_bytes(int64_t n) { return ((size_t)n * 8 + 255) & ~size_t(255); }
 size_t footprint(int64_t n) { return (12 + 12 + AI_NOBS) * plane_bytes(n); }
 
@@ -92,35 +96,19 @@ struct SlabSpace {
   }
 };
 
-using RequestPtr = std::shared_ptr<Request>;
-
-// The copy kind between the slab and a caller's buffer.  A copy within
-// device memory goes to a DMA engine: a copy kernel would need wave slots,
-// and the resident kernel holds all of them while it has work (idle waves
-// leave only after idle_ms), so such a copy could wait for a lull in the
-// stream.  Host buffers are copied as the runtime sees fit.
-hipMemcpyKind copy_kind(const void* user) {
+// Whether a buffer is device memory of the current device (else host memory).
+bool on_device(const void* p) {
   hipPointerAttribute_t attr;
-  if (hipPointerGetAttributes(&attr, user) != hipSuccess) {
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
     (void)hipGetLastError();
-    return hipMemcpyDefault;
+    return false;
   }
-  return attr.type == hipMemoryTypeDevice ? hipMemcpyDeviceToDeviceNoCU : hipMemcpyDefault;
+  int dev = -1;
+  return attr.type == hipMemoryTypeDevice && hipGetDevice(&dev) == hipSuccess &&
+         attr.device == dev;
 }
 
-// `planes` rows of `width` bytes between pitched buffers: one 2-D copy, or
-// plane by plane for the DMA engines' device-to-device kind.
-hipError_t copy_planes(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
-                       size_t planes, hipMemcpyKind kind, hipStream_t s) {
-  if (kind != hipMemcpyDeviceToDeviceNoCU)
-    return hipMemcpy2DAsync(dst, dpitch, src, spitch, width, planes, kind, s);
-  for (size_t c = 0; c < planes; ++c) {
-    const hipError_t e = hipMemcpyAsync((char*)dst + c * dpitch, (const char*)src + c * spitch,
-                                        width, kind, s);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
+using RequestPtr = std::shared_ptr<Request>;
 
 }  // namespace
 
@@ -138,11 +126,17 @@ struct ai_server {
   double idle_ms = 20.0;
   size_t slab_bytes = 0;
   char* slab = nullptr;                 // device
-  uint64_t* ctl = nullptr;              // host-coherent: pub, stop, done_seq[ring]
-  ai_resident_desc* desc = nullptr;     // host-coherent: ring of descriptors
-  uint64_t* dev_ctl = nullptr;          // the same two, as the device addresses them
-  ai_resident_desc* dev_desc = nullptr;
-  uint64_t* dev_words = nullptr;        // device: head, done_cnt[ring]
+  // host-coherent: [8, 8 + ring) completion words done_seq[slot] (the kernel
+  // writes them), [8 + ring, 8 + 2 ring) the request count and
+  // [8 + 2 ring, 8 + 3 ring) the claim counter each publication copies to the
+  // device, [1] the stop word's source
+  uint64_t* ctl = nullptr;
+  ai_resident_desc* desc = nullptr;     // pinned: descriptors, copied to dev_ring
+  uint64_t* dev_ctl = nullptr;          // ctl as the device addresses it
+  ai_resident_desc* dev_ring = nullptr; // device: ring of descriptors
+  uint64_t* dev_words = nullptr;        // device: cur, pub, stop, done_cnt[ring] from word 8,
+                                        // claimed[ring] after it
+  bool broken = false;                  // dispatcher: a publication failed; refuse the rest
   hipEvent_t kernel_done = nullptr;
   bool kernel_running = false;
   int64_t launches = 0;
@@ -284,17 +278,19 @@ void ai_server::finish(const RequestPtr& r, int rc, const std::string& error) {
 void ai_server::dispatch() {
   (void)hipSetDevice(device);
   hipStream_t kstream = streams[0], in_stream = streams[1], out_stream = streams[2];
-  uint64_t* pub = ctl;
-  uint64_t* stop_word = ctl + 1;
+  uint64_t* stop_src = ctl + 1;
   uint64_t* done_seq = ctl + 8;
+  uint64_t* pub_src = ctl + 8 + ring;
+  uint64_t* claim_src = ctl + 8 + 2 * (size_t)ring;
   std::deque<RequestPtr> staging, running, draining;
   ai_resident_args args{};
-  args.desc = dev_desc;
-  args.pub = dev_ctl;
-  args.stop = dev_ctl + 1;
+  args.desc = dev_ring;
+  args.pub = dev_words + 1;
+  args.stop = dev_words + 2;
   args.done_seq = dev_ctl + 8;
-  args.head = dev_words;
+  args.cur = dev_words;
   args.done_cnt = dev_words + 8;
+  args.claimed = dev_words + 8 + ring;
   args.ring = ring;
   args.refill_min = refill_min;
   args.idle_ticks = (int64_t)(idle_ms * 1e5);  // 100 MHz clock
@@ -329,24 +325,56 @@ void ai_server::dispatch() {
           draining.empty() && stopping)
         break;
     }
+    // publication, in request order on the copy stream: the initial states
+    // into the slab (host-memory requests), the descriptor into the device
+    // ring, the slot's claim counter (request << 32), then the new
+    // request count into the device word the kernel reads; the kernel sees a
+    // request only once all of it is in device memory and never reads host
+    // memory for it
     for (const RequestPtr& r : admit) {
       const ai_batch_item& it = r->item;
       const size_t pb = plane_bytes(it.n);
       double* y0s = (double*)(slab + r->slab_off);
+      const uint32_t slot = (uint32_t)(r->seq % ring);
+      if (broken) {
+        finish(r, AI_EHIP, "an earlier publication failed");
+        continue;
+      }
+      slot_total[slot] += (uint64_t)it.n;
+      if (r->staged)
+        ai_resident_describe(&it, r->kernel, y0s, y0s + 12 * pb / 8, y0s + 24 * pb / 8,
+                             (int64_t)(pb / 8), r->seq, slot_total[slot], &desc[slot]);
+      else
+        ai_resident_describe(&it, r->kernel, const_cast<double*>(it.y0), it.final_state, it.obs,
+                             it.ld, r->seq, slot_total[slot], &desc[slot]);
+      pub_src[slot] = r->seq + 1;
+      claim_src[slot] = r->seq << 32;
       hipError_t e = hipEventCreateWithFlags(&r->copied_in, hipEventDisableTiming);
+      if (e == hipSuccess && r->staged)
+        e = hipMemcpy2DAsync(y0s, pb, it.y0, (size_t)it.ld * 8, (size_t)it.n * 8, 12,
+                             hipMemcpyDefault, in_stream);
       if (e == hipSuccess)
-        e = copy_planes(y0s, pb, it.y0, (size_t)it.ld * 8, (size_t)it.n * 8, 12,
-                        copy_kind(it.y0), in_stream);
+        e = hipMemcpyAsync(dev_ring + slot, desc + slot, sizeof(ai_resident_desc),
+                           hipMemcpyHostToDevice, in_stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(dev_words + 8 + ring + slot, claim_src + slot, sizeof(uint64_t),
+                           hipMemcpyHostToDevice, in_stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(dev_words + 1, pub_src + slot, sizeof(uint64_t),
+                           hipMemcpyHostToDevice, in_stream);
       if (e == hipSuccess) e = hipEventRecord(r->copied_in, in_stream);
       if (e != hipSuccess) {
-        finish(r, AI_EHIP, hip_error(e, "copy in"));
+        // a request count that never arrives would stall every later request:
+        // the server refuses the rest
+        broken = true;
+        (void)hipStreamSynchronize(in_stream);
+        finish(r, AI_EHIP, hip_error(e, "publish"));
         continue;
       }
       staging.push_back(r);
       progress = true;
     }
-    // publish, in request order, the requests whose initial states are in
-    // the slab
+    // published requests (their copies have completed), in order
     while (!staging.empty()) {
       const RequestPtr r = staging.front();
       const hipError_t q = hipEventQuery(r->copied_in);
@@ -354,18 +382,11 @@ void ai_server::dispatch() {
       staging.pop_front();
       progress = true;
       if (q != hipSuccess) {
-        finish(r, AI_EHIP, hip_error(q, "copy in"));
+        broken = true;
+        finish(r, AI_EHIP, hip_error(q, "publish"));
         continue;
       }
       const ai_batch_item& it = r->item;
-      const size_t pb = plane_bytes(it.n);
-      double* y0s = (double*)(slab + r->slab_off);
-      const uint32_t slot = (uint32_t)(r->seq % ring);
-      slot_total[slot] += (uint64_t)it.n;
-      ai_resident_describe(&it, r->kernel, y0s, y0s + 12 * pb / 8, y0s + 24 * pb / 8,
-                           (int64_t)(pb / 8), r->seq, slot_total[slot], &desc[slot]);
-      // descriptor before the count that publishes it
-      __atomic_store_n(pub, r->seq + 1, __ATOMIC_RELEASE);
       in_flight_traj += it.n;
       r->info.start_s = now_s();
       r->info.batch_size = (int32_t)(running.size() + 1);
@@ -417,16 +438,20 @@ void ai_server::dispatch() {
       it = running.erase(it);
       progress = true;
       in_flight_traj -= r->item.n;
+      if (!r->staged) {  // the results are in the caller's buffers
+        finish(r, AI_OK, "");
+        continue;
+      }
       const ai_batch_item& itm = r->item;
       const size_t pb = plane_bytes(itm.n);
       const char* base = slab + r->slab_off;
       hipError_t e = hipEventCreateWithFlags(&r->copied_out, hipEventDisableTiming);
       if (e == hipSuccess)
-        e = copy_planes(itm.final_state, (size_t)itm.ld * 8, base + 12 * pb, pb,
-                        (size_t)itm.n * 8, 12, copy_kind(itm.final_state), out_stream);
+        e = hipMemcpy2DAsync(itm.final_state, (size_t)itm.ld * 8, base + 12 * pb, pb,
+                             (size_t)itm.n * 8, 12, hipMemcpyDefault, out_stream);
       if (e == hipSuccess)
-        e = copy_planes(itm.obs, (size_t)itm.ld * 8, base + 24 * pb, pb, (size_t)itm.n * 8,
-                        AI_NOBS, copy_kind(itm.obs), out_stream);
+        e = hipMemcpy2DAsync(itm.obs, (size_t)itm.ld * 8, base + 24 * pb, pb, (size_t)itm.n * 8,
+                             AI_NOBS, hipMemcpyDefault, out_stream);
       if (e == hipSuccess) e = hipEventRecord(r->copied_out, out_stream);
       if (e != hipSuccess) {
         (void)hipStreamSynchronize(out_stream);  // the slab space is not reused under a copy
@@ -452,8 +477,12 @@ void ai_server::dispatch() {
       work.wait_for(lock, std::chrono::microseconds(100));
     }
   }
-  // everything is served: the waves exit once idle
-  __atomic_store_n(stop_word, (uint64_t)1, __ATOMIC_RELEASE);
+  // everything is served: the waves exit once idle (at the latest after
+  // idle_ms, should the stop word not arrive)
+  *stop_src = 1;
+  if (hipMemcpyAsync(dev_words + 2, stop_src, sizeof(uint64_t), hipMemcpyHostToDevice,
+                     in_stream) == hipSuccess)
+    (void)hipStreamSynchronize(in_stream);
   if (kernel_running) (void)hipEventSynchronize(kernel_done);
   kernel_running = false;
 }
@@ -467,7 +496,7 @@ int ai_server::start_resident(const ai_server_config& c) {
   slot_busy.assign(ring, 0);
   space.reset(slab_bytes);
   hipError_t e;
-  const size_t ctl_bytes = sizeof(uint64_t) * (8 + (size_t)ring);
+  const size_t ctl_bytes = sizeof(uint64_t) * (8 + 3 * (size_t)ring);
   if ((e = hipHostMalloc((void**)&ctl, ctl_bytes, hipHostMallocCoherent | hipHostMallocMapped)) !=
           hipSuccess ||
       (e = hipHostMalloc((void**)&desc, sizeof(ai_resident_desc) * ring,
@@ -477,11 +506,11 @@ int ai_server::start_resident(const ai_server_config& c) {
   }
   std::memset(ctl, 0, ctl_bytes);
   std::memset(desc, 0, sizeof(ai_resident_desc) * ring);
-  if ((e = hipHostGetDevicePointer((void**)&dev_ctl, ctl, 0)) != hipSuccess ||
-      (e = hipHostGetDevicePointer((void**)&dev_desc, desc, 0)) != hipSuccess)
+  if ((e = hipHostGetDevicePointer((void**)&dev_ctl, ctl, 0)) != hipSuccess)
     return ai_fail(AI_EHIP, hipGetErrorString(e));
-  const size_t dev_bytes = sizeof(uint64_t) * (8 + (size_t)ring);
+  const size_t dev_bytes = sizeof(uint64_t) * (8 + 2 * (size_t)ring);
   if ((e = hipMalloc((void**)&dev_words, dev_bytes)) != hipSuccess ||
+      (e = hipMalloc((void**)&dev_ring, sizeof(ai_resident_desc) * ring)) != hipSuccess ||
       (e = hipMalloc((void**)&slab, slab_bytes)) != hipSuccess) {
     (void)hipGetLastError();
     return ai_fail(AI_ENOMEM, "server slab");
@@ -504,10 +533,12 @@ void ai_server::release_resident() {
   if (kernel_done) (void)hipEventDestroy(kernel_done);
   kernel_done = nullptr;
   if (slab) (void)hipFree(slab);
+  if (dev_ring) (void)hipFree(dev_ring);
   if (dev_words) (void)hipFree(dev_words);
   if (desc) (void)hipHostFree(desc);
   if (ctl) (void)hipHostFree(ctl);
   slab = nullptr;
+  dev_ring = nullptr;
   dev_words = nullptr;
   desc = nullptr;
   ctl = nullptr;
@@ -613,6 +644,8 @@ int ai_server_submit(ai_server* srv, const ai_batch_item* item, int32_t kernel,
   auto r = std::make_shared<Request>();
   r->item = *item;
   r->kernel = kernel;
+  r->staged = resident && item->n > 0 &&
+              !(on_device(item->y0) && on_device(item->final_state) && on_device(item->obs));
   r->base_rc = rc;
   r->info.submit_s = now_s();
   {

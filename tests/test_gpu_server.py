@@ -211,9 +211,10 @@ def test_resident_alone_equals_in_mix(ai, torch):
 
 
 def test_resident_admission_by_footprint(ai, torch):
-    """A slab that holds two of the requests at a time: the others wait in
-    arrival order until earlier ones have been copied out, and all complete
-    correctly; a request larger than the slab is refused at submission."""
+    """A budget (slab) that holds the footprint of two of the requests at a
+    time: the others wait in arrival order until earlier ones have completed,
+    and all complete correctly; a request larger than the budget is refused at
+    submission."""
     wl = W.small_ensemble()
     y = wl.initial_states(6 * 512)
     reqs = [_request(torch, wl, y[:, 512 * k:512 * (k + 1)]) for k in range(6)]
