@@ -285,33 +285,43 @@ def serve_stream(binding, W, torch, reqs, srv, pace: bool) -> dict:
     return rec
 
 
-def serving(binding, W, torch, count: int, saturate: int, launches_count: int,
-            plain_traj_per_s: float) -> dict:
+def serving(binding, W, torch, count: int, saturate: int, resident_paced: int,
+            plain_traj_per_s: float, plain_steps_per_s: float) -> dict:
     """The serving configuration: the Poisson stream (200 requests/s, seed 2;
-    sizes, tolerances, precision, temperature and q per request) served by the
-    resident kernel (continuous batching, admission by footprint into a 4 GiB
-    slab); the first `saturate` requests again, submitted at once (the
-    sustained rate); and the first `launches_count` of the stream served by
-    batched launches for comparison."""
+    sizes, tolerances, precision, temperature and q per request), paced,
+    served by batched launches (three workers, longest-first schedule); the
+    first `saturate` requests again, submitted at once, served by the resident
+    kernel (continuous batching, admission by footprint, 4 GiB budget): the
+    sustained rate; and, if asked, the first `resident_paced` requests of the
+    stream paced through the resident kernel."""
     stream, reqs = serving_requests(W, torch, count, W.SERVING_RATE_HZ)
     progress(f"serving: {len(reqs)} requests prepared")
-    out = {"workload": f"poisson-{W.SERVING_RATE_HZ:g}rps", "seed": W.SERVING_SEED,
-           "mode": "resident", "slab_bytes": 4 << 30}
-    with binding.Server(mode="resident") as srv:
+    out = {"workload": f"poisson-{W.SERVING_RATE_HZ:g}rps", "seed": W.SERVING_SEED}
+    with binding.Server(schedule="longest-first") as srv:
         out["paced"] = serve_stream(binding, W, torch, reqs, srv, pace=True)
+        out["paced"]["mode"] = "launches"
         progress(f"serving: paced stream, p50 {out['paced']['latency_ms']['p50']:.1f} ms, "
                  f"p99 {out['paced']['latency_ms']['p99']:.1f} ms")
-        if saturate:
-            sat = serve_stream(binding, W, torch, reqs[:saturate], srv, pace=False)
-            sat["vs_plain_kernel"] = sat["trajectories_per_s"] / plain_traj_per_s
-            out["saturated"] = sat
-            progress(f"serving: saturated, {sat['trajectories_per_s']:.3g} trajectories/s")
-    if launches_count:
-        with binding.Server(schedule="longest-first") as srv:
-            out["launch_mode_paced"] = serve_stream(binding, W, torch, reqs[:launches_count], srv,
-                                                    pace=True)
-            progress("serving: launch mode done")
+    if saturate or resident_paced:
+        with binding.Server(mode="resident") as srv:
+            if saturate:
+                sat = serve_stream(binding, W, torch, reqs[:saturate], srv, pace=False)
+                sat["mode"] = "resident"
+                sat["slab_bytes"] = 4 << 30
+                sat["vs_plain_kernel"] = sat["trajectories_per_s"] / plain_traj_per_s
+                # the stream's trajectories cost more on average (RelTol down
+                # to 1e-10, cold atoms), so accepted steps/s compare the work
+                # rates
+                sat["steps_vs_plain_kernel"] = sat["accepted_steps_per_s"] / plain_steps_per_s
+                out["saturated"] = sat
+                progress(f"serving: saturated, {sat['trajectories_per_s']:.3g} trajectories/s")
+            if resident_paced:
+                rp = serve_stream(binding, W, torch, reqs[:resident_paced], srv, pace=True)
+                rp["mode"] = "resident"
+                out["resident_paced"] = rp
+                progress("serving: resident paced done")
     out["plain_kernel_trajectories_per_s"] = plain_traj_per_s
+    out["plain_kernel_accepted_steps_per_s"] = plain_steps_per_s
     del reqs
     torch.cuda.empty_cache()
     return out
@@ -474,11 +484,13 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true",
                     help="skip timing the batched 64-ensemble grid")
     ap.add_argument("--serving-requests", type=int, default=2000,
-                    help="requests of the serving stream to run (0: skip)")
+                    help="requests of the serving stream to run, paced, by batched launches "
+                         "(0: skip serving)")
     ap.add_argument("--serving-saturate", type=int, default=1000,
-                    help="requests of the stream to submit at once for the sustained rate")
-    ap.add_argument("--serving-launches", type=int, default=400,
-                    help="requests of the stream to serve by batched launches for comparison")
+                    help="requests of the stream the resident kernel serves submitted at once "
+                         "(the sustained rate)")
+    ap.add_argument("--serving-resident-paced", type=int, default=0,
+                    help="requests of the stream to serve paced by the resident kernel")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="trajectories the oracle baseline integrates (default: the whole ensemble)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -629,8 +641,8 @@ def main() -> int:
     if args.serving_requests > 0 and args.n is None:
         served = serving(binding, W, torch, args.serving_requests,
                          min(args.serving_saturate, args.serving_requests),
-                         min(args.serving_launches, args.serving_requests),
-                         wl.n * args.steps / (total_ms / 1e3))
+                         min(args.serving_resident_paced, args.serving_requests),
+                         wl.n * args.steps / (total_ms / 1e3), value)
         progress("serving done")
 
     cpu = None
