@@ -92,8 +92,9 @@ __host__ __device__ constexpr long long wide_trajectories(int32_t kernel) {
 // constants are held in scalar registers, the loop's other constants in
 // vector registers (Ctl below).
 struct Launch {
-  double inv_mi, inv_ma;     // 1/m_ion, 1/m_atom
-  double nCn, mCm;           // n Cn and m Cm; for n=4, m=8 (dV/dr)/r = s^3 (4 C4 - 8 C8 s^2), s = 1/r^2
+  double mr;                 // m_atom / m_ion: F_ion = -mr F_atom - kappa(t) x_ion
+  double nCa, mCa;           // n Cn / m_atom and m Cm / m_atom: F_atom = g_a d with, for n=4, m=8,
+                             // g_a = ((dV/dr)/r) / m_atom = s^3 (nCa - mCa s^2), s = 1/r^2
   int pot_n, pot_m;          // the exponents n < m of V(r) = -Cn/r^n + Cm/r^m
   double ka[3], kq[3];       // kappa_k(t) = ka_k + kq_k cos(omega t) = (a_k + 2 q_k cos) omega^2/4
   double omega;
@@ -164,15 +165,14 @@ __device__ __forceinline__ T in_vgpr(T x) {
 // registers as well: fma(kq, cos, ka) with both in scalar registers needs a
 // copy of one of them first (an instruction reads one scalar operand).
 struct Force {
-  double inv_mi, inv_ma, nCn, mCm, ka[3], kq[3];
+  double mr, nCa, mCa, ka[3], kq[3];
 };
 
 __device__ __forceinline__ Force lane_force(const Launch& P) {
   Force f;
-  f.inv_mi = P.inv_mi;
-  f.inv_ma = P.inv_ma;
-  f.nCn = P.nCn;
-  f.mCm = P.mCm;
+  f.mr = P.mr;
+  f.nCa = P.nCa;
+  f.mCa = P.mCa;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     f.ka[k] = in_vgpr(P.ka[k]);
@@ -181,20 +181,19 @@ __device__ __forceinline__ Force lane_force(const Launch& P) {
   return f;
 }
 
-// The force constants of a potential with other exponents: g = (dV/dr)/r =
-// n Cn r^-(n+2) - m Cm r^-(m+2), powers of s = 1/r^2 (times sqrt(s) = 1/r
-// for an odd exponent).
+// The force constants of a potential with other exponents: g_a = (dV/dr)/r
+// / m_atom = (n Cn r^-(n+2) - m Cm r^-(m+2)) / m_atom, powers of s = 1/r^2
+// (times sqrt(s) = 1/r for an odd exponent).
 struct ForceNM {
-  double inv_mi, inv_ma, nCn, mCm, ka[3], kq[3];
+  double mr, nCa, mCa, ka[3], kq[3];
   int en, em;  // n + 2 and m + 2
 };
 
 __device__ __forceinline__ ForceNM lane_force_nm(const Launch& P) {
   ForceNM f;
-  f.inv_mi = P.inv_mi;
-  f.inv_ma = P.inv_ma;
-  f.nCn = P.nCn;
-  f.mCm = P.mCm;
+  f.mr = P.mr;
+  f.nCa = P.nCa;
+  f.mCa = P.mCa;
   f.en = P.pot_n + 2;
   f.em = P.pot_m + 2;
 #pragma unroll
@@ -213,15 +212,14 @@ __device__ __forceinline__ ForceNM lane_force_of(const Launch& P, const ForceNM*
 // The force constants in single precision, for the single-precision-stage
 // variant.
 struct Force32 {
-  float inv_mi, inv_ma, nCn, mCm, ka[3], kq[3];
+  float mr, nCa, mCa, ka[3], kq[3];
 };
 
 __device__ __forceinline__ Force32 lane_force32(const Launch& P) {
   Force32 f;
-  f.inv_mi = (float)P.inv_mi;
-  f.inv_ma = (float)P.inv_ma;
-  f.nCn = (float)P.nCn;
-  f.mCm = (float)P.mCm;
+  f.mr = (float)P.mr;
+  f.nCa = (float)P.nCa;
+  f.mCa = (float)P.mCa;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     f.ka[k] = in_vgpr((float)P.ka[k]);
@@ -381,11 +379,12 @@ __device__ __forceinline__ double inv_fifth_root(double q) {
   return fma(-0.2 * q, w3 * w3, 1.2 * w);
 }
 
-// g = (dV/dr)/r of V(r) = -Cn/r^n + Cm/r^m (Sec. 2.1; general n, m in Sec.
-// 4.1) from s = 1/r^2: for n = 4, m = 8, s^3 (4 C4 - 8 C8 s^2).
+// g_a = (dV/dr)/(r m_atom) of V(r) = -Cn/r^n + Cm/r^m (Sec. 2.1; general n, m
+// in Sec. 4.1) from s = 1/r^2: for n = 4, m = 8, s^3 (4 C4 - 8 C8 s^2) / m_atom
+// with the constants divided by m_atom on the host.
 __device__ __forceinline__ double force_g(const Force& P, double s) {
   const double s2 = s * s;
-  return (s2 * s) * fma(-P.mCm, s2, P.nCn);
+  return (s2 * s) * fma(-P.mCa, s2, P.nCa);
 }
 
 // r^-k = s^(k/2) for an exponent k the same across the launch: binary powers
@@ -401,13 +400,15 @@ __device__ __forceinline__ double inv_rpow(double s, double rinv, int k) {
 
 __device__ __forceinline__ double force_g(const ForceNM& P, double s) {
   const double rinv = ((P.en | P.em) & 1) ? sqrt(s) : 0.0;
-  return fma(P.nCn, inv_rpow(s, rinv, P.en), -P.mCm * inv_rpow(s, rinv, P.em));
+  return fma(P.nCa, inv_rpow(s, rinv, P.en), -P.mCa * inv_rpow(s, rinv, P.em));
 }
 
 // Accelerations F(t, X) of Sec. 2.1 for V(r) = -C4/r^4 + C8/r^8:
 // F_ion = -(g/m_ion) d - kappa(t) x_ion, F_atom = (g/m_atom) d with
-// d = x_ion - x_atom and g = (dV/dr)/r.  cosrf = cos(omega t).  Returns r^2
-// and d.
+// d = x_ion - x_atom and g = (dV/dr)/r, formed as F_atom = g_a d and F_ion =
+// -(m_atom/m_ion) F_atom - kappa(t) x_ion (g_a = g/m_atom): the ion's
+// interaction term is the atom's times the mass ratio, which saves a product
+// per stage.  cosrf = cos(omega t).  Returns r^2 and d.
 template <class C>
 __device__ __forceinline__ double accel(const C& P, double cosrf, const double* X,
                                         double* F, double& dx, double& dy, double& dz) {
@@ -416,16 +417,16 @@ __device__ __forceinline__ double accel(const C& P, double cosrf, const double* 
   dz = X[2] - X[5];
   const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
   const double s = recip(r2);
-  const double g = force_g(P, s);
-  const double gi = g * P.inv_mi, ga = g * P.inv_ma;
-  // -(gi d + kappa x) written as (-gi) d + kappa (-x): the same value (the
-  // rounding is symmetric), with the negations as free operand modifiers
-  F[0] = fma(-gi, dx, fma(P.kq[0], cosrf, P.ka[0]) * -X[0]);
-  F[1] = fma(-gi, dy, fma(P.kq[1], cosrf, P.ka[1]) * -X[1]);
-  F[2] = fma(-gi, dz, fma(P.kq[2], cosrf, P.ka[2]) * -X[2]);
+  const double ga = force_g(P, s);
   F[3] = ga * dx;
   F[4] = ga * dy;
   F[5] = ga * dz;
+  // -(mr F_atom + kappa x) written as (-mr) F_atom + kappa (-x): the same
+  // value (the rounding is symmetric), with the negations as free operand
+  // modifiers
+  F[0] = fma(-P.mr, F[3], fma(P.kq[0], cosrf, P.ka[0]) * -X[0]);
+  F[1] = fma(-P.mr, F[4], fma(P.kq[1], cosrf, P.ka[1]) * -X[1]);
+  F[2] = fma(-P.mr, F[5], fma(P.kq[2], cosrf, P.ka[2]) * -X[2]);
   return r2;
 }
 
@@ -450,12 +451,11 @@ __device__ __forceinline__ float accel32(const Force32& P, float cosrf, const fl
   const float r2 = fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0]));
   const float s = recipf(r2);
   const float s2 = s * s;
-  const float g = (s2 * s) * fmaf(-P.mCm, s2, P.nCn);
-  const float gi = g * P.inv_mi, ga = g * P.inv_ma;
+  const float ga = (s2 * s) * fmaf(-P.mCa, s2, P.nCa);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    F[k] = -fmaf(gi, d[k], fmaf(P.kq[k], cosrf, P.ka[k]) * xi[k]);
     F[3 + k] = ga * d[k];
+    F[k] = -fmaf(P.mr, F[3 + k], fmaf(P.kq[k], cosrf, P.ka[k]) * xi[k]);
   }
   return r2;
 }
@@ -632,23 +632,20 @@ __device__ __forceinline__ double ratio(double e, double s) {
 // the position half's against the velocity half's).  The position half is
 // reduced before the last force evaluation, which keeps few of its values
 // live across it.  half_norm() reduces one half: e the error components, y
-// and yn the solution before and after; m receives the half's largest ratio;
-// returns whether an e is NaN (the maximum instructions drop NaN operands).
+// and yn the solution before and after; m receives the half's largest ratio.
+// The maximum instructions drop NaN operands; a NaN or infinite error
+// component comes with a non-finite new state, which conclude() catches.
 template <class RE>
-__device__ __forceinline__ bool half_norm(const Ctl& K, const RE* e, const double* y,
+__device__ __forceinline__ void half_norm(const Ctl& K, const RE* e, const double* y,
                                           const double* yn, double& m) {
   double ax[3];
-  bool nan_seen = false;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const double n0 = (double)e[k], n1 = (double)e[3 + k];
-    const double r0 = ratio(n0, max_abs(max_abs(y[k], yn[k]), K.thr));
-    const double r1 = ratio(n1, max_abs(max_abs(y[3 + k], yn[3 + k]), K.thr));
-    nan_seen = nan_seen || (n0 != n0) || (n1 != n1);
+    const double r0 = ratio((double)e[k], max_abs(max_abs(y[k], yn[k]), K.thr));
+    const double r1 = ratio((double)e[3 + k], max_abs(max_abs(y[3 + k], yn[3 + k]), K.thr));
     ax[k] = vmax(r0, r1);
   }
   m = vmax(vmax(ax[0], ax[1]), ax[2]);
-  return nan_seen;
 }
 
 // The error norm's largest ratio given the position half's, mx: mx against
@@ -658,15 +655,13 @@ __device__ __forceinline__ bool half_norm(const Ctl& K, const RE* e, const doubl
 // itself, and the velocity half's scales and reciprocals are not formed (for
 // thermal collisions the velocity scales sit at the floor AbsTol/RelTol, far
 // above |v|, and the position half decides every step).  The result is the
-// same either way.  nan_v: whether an e is NaN.
+// same either way.
 template <class RE>
 __device__ __forceinline__ double with_velocity_half(const Ctl& K, const RE* e, const double* v,
-                                                     const double* vn, double mx, bool& nan_v) {
+                                                     const double* vn, double mx) {
   double a[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) a[c] = (double)e[c];
-  nan_v = (a[0] != a[0]) || (a[3] != a[3]) || (a[1] != a[1]) || (a[4] != a[4]) ||
-          (a[2] != a[2]) || (a[5] != a[5]);
   const double big = max_abs(max_abs(max_abs(a[0], a[3]), max_abs(a[1], a[4])), max_abs(a[2], a[5]));
   if (big * K.vbound <= mx) return mx;
   double mv;
@@ -679,11 +674,22 @@ __device__ __forceinline__ double with_velocity_half(const Ctl& K, const RE* e, 
 // (the phase is rotated here), and the observables and exits are updated from
 // w() = d . (v_ion - v_atom) and r2n = |d|^2 at tnew; ion_distance() gives
 // |x_ion| at tnew for the first bounce.
+//
+// The attempt ends the trajectory as non-finite when an error component is
+// NaN or infinite, tested without looking at each of the twelve components:
+// the first-stage force is finite (the previous attempt would have ended
+// otherwise), stages 3-6 enter the new velocity with nonzero weights and
+// stage 2 enters the positions of stages 4-6, so a non-finite force of stages
+// 2-6 (the only way the components without stage 7 can be non-finite) makes
+// the new velocity, and with it w(), non-finite.  Stage 7's force, from the
+// new position, is NaN only if that position is or r2n is 0, and infinite
+// otherwise, which makes err infinite.  Hence the test on err, w and r2n.
 template <class LN, class Advance, class W, class IonDistance>
 __device__ __forceinline__ void conclude(const Ctl& K, LN& L, double t, double h, double tnew,
                                          double err, double cs6, double sn6, double r2n,
                                          Advance advance, W w_of, IonDistance ion_distance) {
-  if (!isfinite(err)) {
+  const double w = w_of();
+  if (!isfinite(err) || !isfinite(w) || !(r2n > 0.0)) {
     L.status = AI_ST_NONFINITE;
     return;
   }
@@ -713,7 +719,6 @@ __device__ __forceinline__ void conclude(const Ctl& K, LN& L, double t, double h
   L.fresh = true;
 
   // observables: closest approach = sign change of r r' from - to +
-  const double w = w_of();
   if (L.w_prev < 0.0 && w >= 0.0) {
     L.approached = true;
     if (r2n < K.r_bounce2) {
@@ -824,14 +829,13 @@ __device__ __forceinline__ void attempt(const F& P, const Ctl& K, Lane& L) {
   // error norm (order in half_norm()): the position half, stage 7, the
   // velocity half
   double mx;
-  const bool nan_x = half_norm(K, ex, x, xn, mx);
+  half_norm(K, ex, x, xn, mx);
   const double r2n = accel(P, cos7, xn, F7, dx, dy, dz);
   double ev7[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) ev7[c] = fma(E7, F7[c], ev[c]);
-  bool nan_v;
-  const double m = with_velocity_half(K, ev7, v, vn, mx, nan_v);
-  const double err = (nan_x || nan_v) ? __builtin_nan("") : h * m;
+  const double m = with_velocity_half(K, ev7, v, vn, mx);
+  const double err = h * m;
   conclude_lane(K, L, t, h, tnew, err, xn, vn, F7, cs6, sn6, dx, dy, dz, r2n);
 }
 
@@ -934,21 +938,23 @@ __device__ __forceinline__ void attempt32(const Force32& P, const Ctl& K, Lane& 
   // error norm in double, as in attempt(): the position half, stage 7 at tnew
   // from the new double state, the velocity half
   double mx;
-  const bool nan_x = half_norm(K, ex, x, xn, mx);
+  half_norm(K, ex, x, xn, mx);
   const double cos7 = L.done ? cos_rf(K.omega * tnew) : cs6;
   const double dx = xn[0] - xn[3], dy = xn[1] - xn[4], dz = xn[2] - xn[5];
+  float r2f;
   {
     const float dn[3] = {(float)dx, (float)dy, (float)dz};
     const float xin[3] = {(float)xn[0], (float)xn[1], (float)xn[2]};
-    accel32(P, (float)cos7, dn, xin, F7);
+    r2f = accel32(P, (float)cos7, dn, xin, F7);
   }
   const double r2n = fma(dz, dz, fma(dy, dy, dx * dx));
   float ev7[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) ev7[c] = fmaf(E7f, F7[c], ev[c]);
-  bool nan_v;
-  const double m = with_velocity_half(K, ev7, v, vn, mx, nan_v);
-  const double err = (nan_x || nan_v) ? __builtin_nan("") : h * m;
+  const double m = with_velocity_half(K, ev7, v, vn, mx);
+  // stage 7's single-precision force is not finite also when the separation's
+  // square underflows in single precision (r2f = 0 with r2n > 0)
+  const double err = (r2f > 0.0f) ? h * m : __builtin_nan("");
   conclude_lane(K, L, t, h, tnew, err, xn, vn, F7, cs6, sn6, dx, dy, dz, r2n);
 }
 
@@ -1207,10 +1213,9 @@ __device__ __forceinline__ double accel_wide(const F& P, double ka, double kq, d
   dz = from_quad_lane<2>(d);
   const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
   const double s = recip(r2);
-  const double g = force_g(P, s);
-  const double gi = g * P.inv_mi, ga = g * P.inv_ma;
-  Fi = -fma(gi, d, fma(kq, cosrf, ka) * Xi);
+  const double ga = force_g(P, s);
   Fa = ga * d;
+  Fi = -fma(P.mr, Fa, fma(kq, cosrf, ka) * Xi);
   return r2;
 }
 
@@ -1268,7 +1273,6 @@ __device__ __forceinline__ void attempt_wide(const F& P, double ka, double kq, c
   }
   // error norm as in half_norm(): this axis's ion and atom ratios on this
   // lane, the axes across the quad
-  int nan_here = (exi != exi) | (exa != exa);
   double mx = vmax(ratio(exi, max_abs(max_abs(xi, xni), K.thr)),
                    ratio(exa, max_abs(max_abs(xa, xna), K.thr)));
   {
@@ -1280,7 +1284,6 @@ __device__ __forceinline__ void attempt_wide(const F& P, double ka, double kq, c
   const double r2n = accel_wide(P, ka, kq, cos7, xni, xna, F7i, F7a, dx, dy, dz);
 
   const double e7i = fma(E7, F7i, evi), e7a = fma(E7, F7a, eva);
-  nan_here |= (e7i != e7i) | (e7a != e7a);
   // the velocity half as in with_velocity_half(): skipped when each axis's
   // bound max(|e|) vbound is at most mx (decided per quad, so that the quad's
   // lanes stay together for the exchanges below)
@@ -1294,9 +1297,7 @@ __device__ __forceinline__ void attempt_wide(const F& P, double ka, double kq, c
     mv = vmax(vmax(from_quad_lane<0>(mv), my), mz);
     m = vmax(mx, mv);
   }
-  const int nan_seen =
-      from_quad_lane<0>(nan_here) | from_quad_lane<1>(nan_here) | from_quad_lane<2>(nan_here);
-  const double err = nan_seen ? __builtin_nan("") : h * m;
+  const double err = h * m;
 
   conclude(
       K, L, t, h, tnew, err, cs6, sn6, r2n,
@@ -1798,10 +1799,9 @@ __device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)
 
 __device__ __forceinline__ Force32 force32_of(const Force& F) {
   Force32 f;
-  f.inv_mi = (float)F.inv_mi;
-  f.inv_ma = (float)F.inv_ma;
-  f.nCn = (float)F.nCn;
-  f.mCm = (float)F.mCm;
+  f.mr = (float)F.mr;
+  f.nCa = (float)F.nCa;
+  f.mCa = (float)F.mCa;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     f.ka[k] = (float)F.ka[k];
@@ -1923,10 +1923,9 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
         K.max_steps = kp->max_steps;
         K.exit_on = kp->exit_on;
         Force F;
-        F.inv_mi = fp->inv_mi;
-        F.inv_ma = fp->inv_ma;
-        F.nCn = fp->nCn;
-        F.mCm = fp->mCm;
+        F.mr = fp->mr;
+        F.nCa = fp->nCa;
+        F.mCa = fp->mCa;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           F.ka[k] = fp->ka[k];
@@ -2292,10 +2291,9 @@ Launch launch_constants(const ai_params* p, int64_t n, int64_t ld, double t0, do
                         double rtol, double atol) {
   Launch P;
   const double w2 = p->omega_rf * p->omega_rf / 4.0;
-  P.inv_mi = 1.0 / p->m_ion;
-  P.inv_ma = 1.0 / p->m_atom;
-  P.nCn = p->n * p->Cn;
-  P.mCm = p->m * p->Cm;
+  P.mr = p->m_atom / p->m_ion;
+  P.nCa = (p->n * p->Cn) / p->m_atom;
+  P.mCa = (p->m * p->Cm) / p->m_atom;
   P.pot_n = p->n;
   P.pot_m = p->m;
   for (int k = 0; k < 3; ++k) {
