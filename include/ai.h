@@ -318,7 +318,10 @@ int ai_trace(const ai_params *p, const double *y0, double t0, double tmax, doubl
  * submitted and served in arrival order.  A request's results are bitwise
  * those of ai_integrate on it alone, whatever it shares the GPU with.  The
  * caller owns every buffer and keeps it allocated until ai_server_wait has
- * returned the request's completion.  Two modes:
+ * returned the request's completion.  A request's initial states must be in
+ * its buffers when it is submitted (the server's streams and kernel do not
+ * wait for work on other streams: synchronize whatever produced them first).
+ * Two modes:
  *
  * AI_SERVE_RESIDENT (continuous batching): a resident kernel stays on the GPU
  * while requests flow.  The server owns a slab of device memory (slab_bytes)

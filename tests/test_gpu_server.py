@@ -32,6 +32,9 @@ def _request(torch, wl, y0, t0=None, tmax=None, rtol=None, atol=None, ld=None):
     d = torch.from_numpy(y0p).cuda()
     fin = torch.full((12, ld), -7.0, dtype=torch.float64, device="cuda")
     obs = torch.full((13, ld), -7.0, dtype=torch.float64, device="cuda")
+    # the server's streams do not wait for torch's: the buffers are filled
+    # before the request can be submitted
+    torch.cuda.synchronize()
     return dict(item=(wl.system, d, fin, obs, wl.t0 if t0 is None else t0,
                       wl.tmax if tmax is None else tmax, wl.rtol if rtol is None else rtol,
                       wl.atol if atol is None else atol, n),
@@ -67,6 +70,7 @@ def _mix(torch):
 
 def test_server_alone_equals_in_mix(ai, torch):
     reqs = _mix(torch)
+    torch.cuda.synchronize()        # inputs and padding in place before submission
     with ai.Server(schedule="longest-first") as srv:
         tickets = [srv.submit(r["item"]) for r in reqs]
         infos = [srv.wait(t) for t in tickets]
@@ -94,6 +98,7 @@ def test_server_requests_that_run_alone(ai, torch):
     reqs = [_request(torch, wl, y[:, :300]), _request(torch, wl, y[:, 300:700]),
             _request(torch, wl, y[:, 700:900]), _request(torch, wl612, y[:, 900:])]
     precisions = ["fp64", "fp32-stages", "fp64", "fp64"]
+    torch.cuda.synchronize()
     with ai.Server(workers=1) as srv:
         tickets = [srv.submit(r["item"], p) for r, p in zip(reqs, precisions)]
         infos = [srv.wait(t) for t in tickets]
@@ -113,6 +118,7 @@ def test_server_launch_cap_and_close_finishes_queued_work(ai, torch):
     y = wl.initial_states()
     reqs = [_request(torch, wl, y[:, i:i + 256]) for i in range(0, 1024, 256)]
     big = _request(torch, wl, y)
+    torch.cuda.synchronize()
     srv = ai.Server(max_batch=512, workers=1)
     tickets = [srv.submit(r["item"]) for r in reqs + [big]]
     infos = [srv.wait(t) for t in tickets[:2]]
