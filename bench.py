@@ -43,12 +43,45 @@ def progress(msg: str) -> None:
     print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
+def strip_comments(src: str) -> str:
+    """C/C++ source without its comments (string and character literals kept),
+    each comment replaced by one space."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+            out.append(" ")
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return "".join(out)
+
+
 def source_digest() -> str:
+    """Digest of the kernel sources' tokens (comments and layout left out): the
+    profiles are taken on code, and a change of documentation does not make
+    them stale."""
+    import re
+    token = re.compile(r'"(?:\\.|[^"\\])*"|\'(?:\\.|[^\'\\])*\'|[^\s"\']+')
     h = hashlib.sha256()
     for p in ("paper_2509_12381_amd/csrc/ai.hip", "paper_2509_12381_amd/csrc/schedule.hip",
               "paper_2509_12381_amd/csrc/schedule.h", "include/ai.h"):
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            # the tokens, so that layout and comments do not count
+            h.update(" ".join(token.findall(strip_comments(f.read()))).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 
