@@ -259,6 +259,15 @@ __device__ __forceinline__ double recip(double a) {
   return fma(r, fma(e, e, e), r);
 }
 
+// 1/a for the force: the hardware estimate r (|1 - a r| at most 2^-24.4 over
+// 2^24 random doubles of exponents -60..60 on gfx950) and one Newton step,
+// r (1 + e), which leaves a relative error of about e^2 <= 2^-48.7 (10 ulp):
+// far below the solution's own tolerance, and one FMA shorter than recip().
+__device__ __forceinline__ double recip_force(double a) {
+  const double r = __builtin_amdgcn_rcp(a);
+  return fma(r, fma(-a, r, 1.0), r);
+}
+
 // Taylor polynomials of cos and sin of a small angle u (|u| <= pi/4 on every
 // call), truncated after u^16 and u^17 (remainders below 3e-18).
 __device__ __forceinline__ double cos_poly(double u2) {
@@ -416,7 +425,7 @@ __device__ __forceinline__ double accel(const C& P, double cosrf, const double* 
   dy = X[1] - X[4];
   dz = X[2] - X[5];
   const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-  const double s = recip(r2);
+  const double s = recip_force(r2);
   const double ga = force_g(P, s);
   F[3] = ga * dx;
   F[4] = ga * dy;
@@ -1212,7 +1221,7 @@ __device__ __forceinline__ double accel_wide(const F& P, double ka, double kq, d
   dy = from_quad_lane<1>(d);
   dz = from_quad_lane<2>(d);
   const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-  const double s = recip(r2);
+  const double s = recip_force(r2);
   const double ga = force_g(P, s);
   Fa = ga * d;
   Fi = -fma(P.mr, Fa, fma(kq, cosrf, ka) * Xi);
