@@ -20,7 +20,8 @@ for a 1-ulp relative change of y0, N its number of accepted steps (rounding
 differences enter at every step and add up like a random walk).  A flyby
 moves by ~1e-12; a hard inner bounce in the C4/C8 well, whose depth is ~1e6
 times the collision energy, amplifies rounding by ~1e8 and is excluded from
-the 1e-6 bar (it is still checked at 1e-4, which catches wrong physics).  Chaotic trajectories can
+the 1e-6 bar (it is held to a bar scaled by its own sensitivity, 20 times it
+within [1e-6, 1e-4], which catches wrong physics).  Chaotic trajectories can
 legitimately differ between two correct FP64 implementations (round-off is
 amplified; Sec. 4.2 reports the same between CPU and GPU), so for the full
 ensemble the bar is statistical: complex probability within 3 sigma
@@ -92,15 +93,36 @@ def _dump(tag, **arrays):
         np.savez_compressed(os.path.join(d, f"{tag}.npz"), **arrays)
 
 
-def non_chaotic(aio, system, y0, t0, tmax, rtol, atol, ofin, oob):
-    """Direct trajectories (bounces <= 1, escaped or timed out) whose oracle
-    end state is insensitive to a 1-ulp perturbation of y0 (see module
-    docstring)."""
+def direct_classes(aio, system, y0, t0, tmax, rtol, atol, ofin, oob):
+    """(non-chaotic, direct, sensitivity): direct trajectories (bounces <= 1,
+    escaped or timed out), those among them whose oracle end state is
+    insensitive to a 1-ulp perturbation of y0 (see module docstring), and each
+    trajectory's sensitivity: the block-relative move of the oracle's aligned
+    end state under that perturbation times sqrt(accepted steps)."""
     pfin, pob, _ = run_oracle(aio, system, y0 * (1.0 + 2.0**-52), t0, tmax, rtol, atol)
     moved = S.block_relative_difference(aligned_oracle_state(aio, system, ofin, oob, pob), pfin)
     direct = (oob[O["bounces"]] <= 1) & np.isin(oob[O["status"]], (W.ST_ESCAPED, W.ST_TMAX))
-    calm = moved * np.sqrt(np.maximum(oob[O["nsteps"]], 1.0)) <= 1e-7
-    return direct & calm, direct
+    sens = moved * np.sqrt(np.maximum(oob[O["nsteps"]], 1.0))
+    return direct & (sens <= 1e-7), direct, sens
+
+
+def non_chaotic(aio, system, y0, t0, tmax, rtol, atol, ofin, oob):
+    """(non-chaotic, direct) of direct_classes()."""
+    calm, direct, _ = direct_classes(aio, system, y0, t0, tmax, rtol, atol, ofin, oob)
+    return calm, direct
+
+
+# Direct trajectories that are not non-chaotic (a hard bounce in the well) are
+# held to a bar scaled by their own sensitivity: two correct FP64 runs differ
+# by rounding at every step, which such a trajectory amplifies as it amplifies
+# the 1-ulp change of y0.  Measured on the 1,024-trajectory ensemble at RelTol
+# 1e-8 and 1e-10, the GPU-oracle difference is at most 1.9 times the
+# sensitivity (median 0.03-0.05); the bar allows 20 times, within [1e-6, 1e-4].
+SENSITIVITY_FACTOR = 20.0
+
+
+def sensitivity_bar(sens):
+    return np.clip(SENSITIVITY_FACTOR * sens, 1e-6, 1e-4)
 
 
 def _report(tag, aio, system, gob, oob, gfin, ofin, direct):
@@ -174,7 +196,8 @@ def test_small_ensemble_parity(ai, torch, aio, rtol, atol):
     gfin, gob, grc = run_gpu(ai, torch, wl.system, y0, wl.t0, wl.tmax, rtol, atol)
     ofin, oob, orc = run_oracle(aio, wl.system, y0, wl.t0, wl.tmax, rtol, atol)
     assert grc == orc == 0
-    calm, direct = non_chaotic(aio, wl.system, y0, wl.t0, wl.tmax, rtol, atol, ofin, oob)
+    calm, direct, sens = direct_classes(aio, wl.system, y0, wl.t0, wl.tmax, rtol, atol, ofin,
+                                        oob)
     assert calm.mean() > 0.95
     rel, raw, same = _report(f"1k rtol={rtol}", aio, wl.system, gob, oob, gfin, ofin, calm)
     assert rel.max() <= 1e-6
@@ -182,7 +205,12 @@ def test_small_ensemble_parity(ai, torch, aio, rtol, atol):
     assert same >= 0.99
     loose, _, _ = _report(f"1k rtol={rtol} all direct", aio, wl.system, gob, oob, gfin, ofin,
                           direct)
-    assert loose.max() <= 1e-4
+    bar = sensitivity_bar(sens[direct])
+    print(f"[1k rtol={rtol} all direct] largest difference / sensitivity "
+          f"{(loose / np.maximum(sens[direct], 1e-300)).max():.2f}, tightest bar on a "
+          f"sensitive one {bar[sens[direct] > 1e-7].min() if (sens[direct] > 1e-7).any() else 0:.1e}",
+          flush=True)
+    assert np.all(loose <= bar)
     assert (gob[O["status"]] == oob[O["status"]]).mean() >= 0.99
     # every observable plane on every non-chaotic direct trajectory
     al = aligned_oracle_state(aio, wl.system, ofin, oob, gob)
@@ -306,7 +334,8 @@ for a 1-ulp relative change of y0, N its number of accepted steps (rounding
 differences enter at every step and add up like a random walk).  A flyby
 moves by ~1e-12; a hard inner bounce in the C4/C8 well, whose depth is ~1e6
 times the collision energy, amplifies rounding by ~1e8 and is excluded from
-the 1e-6 bar (it is still checked at 1e-4, which catches wrong physics)."""
+the 1e-6 bar (it is held to a bar scaled by its own sensitivity, 20 times it
+within [1e-6, 1e-4], which catches wrong physics)."""
     import dataclasses
     wl = W.small_ensemble()
     system = dataclasses.replace(wl.system, r_exit=0.0)
@@ -315,14 +344,17 @@ the 1e-6 bar (it is still checked at 1e-4, which catches wrong physics)."""
     gfin, gob, _ = run_gpu(ai, torch, system, y0, 0.0, tmax, 1e-10, 1e-12, "persistent")
     ofin, oob, _ = run_oracle(aio, system, y0, 0.0, tmax, 1e-10, 1e-12)
     assert np.all(gob[O["status"]] == W.ST_TMAX) and np.all(gob[O["tend"]] == tmax)
-    calm, direct = non_chaotic(aio, system, y0, 0.0, tmax, 1e-10, 1e-12, ofin, oob)
+    calm, direct, sens = direct_classes(aio, system, y0, 0.0, tmax, 1e-10, 1e-12, ofin, oob)
     rel = S.block_relative_difference(gfin[:, calm], ofin[:, calm])
     loose = S.block_relative_difference(gfin[:, direct], ofin[:, direct])
     same = (gob[O["nsteps"], calm] == oob[O["nsteps"], calm]).mean()
     print(f"[fixed tmax] non-chaotic={calm.sum()} max block-rel={rel.max():.3e} "
-          f"all direct={loose.max():.3e} same nsteps={same:.4f}", flush=True)
+          f"all direct={loose.max():.3e} largest difference / sensitivity "
+          f"{(loose / np.maximum(sens[direct], 1e-300)).max():.2f} same nsteps={same:.4f}",
+          flush=True)
     assert calm.mean() > 0.95
-    assert rel.max() <= 1e-6 and same >= 0.99 and loose.max() <= 1e-4
+    assert rel.max() <= 1e-6 and same >= 0.99
+    assert np.all(loose <= sensitivity_bar(sens[direct]))
 
 
 @pytest.mark.parametrize("kernel,schedule,refill", [
