@@ -325,8 +325,9 @@ def serving(binding, W, torch, count: int, saturate: int, resident_paced: int,
     served by batched launches (three workers, longest-first schedule); the
     first `saturate` requests again, submitted at once, served by the resident
     kernel (continuous batching, admission by footprint, 4 GiB budget): the
-    sustained rate; and, if asked, the first `resident_paced` requests of the
-    stream paced through the resident kernel."""
+    sustained rate; and the first `resident_paced` requests of the stream
+    paced through the resident kernel (idle_ms 500, so that its waves stay
+    through the stream's quiet spells)."""
     stream, reqs = serving_requests(W, torch, count, W.SERVING_RATE_HZ)
     progress(f"serving: {len(reqs)} requests prepared")
     out = {"workload": f"poisson-{W.SERVING_RATE_HZ:g}rps", "seed": W.SERVING_SEED}
@@ -335,24 +336,27 @@ def serving(binding, W, torch, count: int, saturate: int, resident_paced: int,
         out["paced"]["mode"] = "launches"
         progress(f"serving: paced stream, p50 {out['paced']['latency_ms']['p50']:.1f} ms, "
                  f"p99 {out['paced']['latency_ms']['p99']:.1f} ms")
-    if saturate or resident_paced:
+    if saturate:
         with binding.Server(mode="resident") as srv:
-            if saturate:
-                sat = serve_stream(binding, W, torch, reqs[:saturate], srv, pace=False)
-                sat["mode"] = "resident"
-                sat["slab_bytes"] = 4 << 30
-                sat["vs_plain_kernel"] = sat["trajectories_per_s"] / plain_traj_per_s
-                # the stream's trajectories cost more on average (RelTol down
-                # to 1e-10, cold atoms), so accepted steps/s compare the work
-                # rates
-                sat["steps_vs_plain_kernel"] = sat["accepted_steps_per_s"] / plain_steps_per_s
-                out["saturated"] = sat
-                progress(f"serving: saturated, {sat['trajectories_per_s']:.3g} trajectories/s")
-            if resident_paced:
-                rp = serve_stream(binding, W, torch, reqs[:resident_paced], srv, pace=True)
-                rp["mode"] = "resident"
-                out["resident_paced"] = rp
-                progress("serving: resident paced done")
+            sat = serve_stream(binding, W, torch, reqs[:saturate], srv, pace=False)
+        sat["mode"] = "resident"
+        sat["slab_bytes"] = 4 << 30
+        sat["vs_plain_kernel"] = sat["trajectories_per_s"] / plain_traj_per_s
+        # the stream's trajectories cost more on average (RelTol down to 1e-10,
+        # cold atoms), so accepted steps/s compare the work rates
+        sat["steps_vs_plain_kernel"] = sat["accepted_steps_per_s"] / plain_steps_per_s
+        out["saturated"] = sat
+        progress(f"serving: saturated, {sat['trajectories_per_s']:.3g} trajectories/s")
+    if resident_paced:
+        # waves that stay through the stream's quiet spells: each leaves after
+        # idle_ms without work of its own (the default 20 ms lets most leave)
+        idle = 500.0
+        with binding.Server(mode="resident", idle_ms=idle) as srv:
+            rp = serve_stream(binding, W, torch, reqs[:resident_paced], srv, pace=True)
+        rp["mode"] = "resident"
+        rp["idle_ms"] = idle
+        out["resident_paced"] = rp
+        progress(f"serving: resident paced, p50 {rp['latency_ms']['p50']:.1f} ms")
     out["plain_kernel_trajectories_per_s"] = plain_traj_per_s
     out["plain_kernel_accepted_steps_per_s"] = plain_steps_per_s
     del reqs
@@ -522,8 +526,9 @@ def main() -> int:
     ap.add_argument("--serving-saturate", type=int, default=1000,
                     help="requests of the stream the resident kernel serves submitted at once "
                          "(the sustained rate)")
-    ap.add_argument("--serving-resident-paced", type=int, default=0,
-                    help="requests of the stream to serve paced by the resident kernel")
+    ap.add_argument("--serving-resident-paced", type=int, default=400,
+                    help="requests of the stream to serve paced by the resident kernel "
+                         "(0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="trajectories the oracle baseline integrates (default: the whole ensemble)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,

@@ -1842,8 +1842,9 @@ __device__ __attribute__((noinline)) Derived resident_derive(
 // whether any were left; a claim that finds a request exhausted moves the
 // current-request word on (one compare-and-swap, if the next request is
 // published) and tries again.  Counts past a request's size are claims of
-// nothing.  n_of(seq) gives a request's size.  Bounded: gives up after a few
-// rounds (and is retried later).
+// nothing; a claim looks at the counter before adding to it, so only claims
+// racing at a request's end add past its size.  n_of(seq) gives a request's
+// size.  Bounded: gives up after a few rounds (and is retried later).
 template <class SizeOf>
 __device__ bool claim(const ai_resident_args& A, int want, long long& seq, long long& first,
                       int& count, SizeOf n_of) {
@@ -1852,9 +1853,26 @@ __device__ bool claim(const ai_resident_args& A, int want, long long& seq, long 
     unsigned long long s =
         __hip_atomic_load((unsigned long long*)A.cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (s >= pub) return false;
-    const unsigned long long v = __hip_atomic_fetch_add(
-        (unsigned long long*)A.claimed + s % (unsigned long long)A.ring, (unsigned long long)want,
-        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long* counter =
+        (unsigned long long*)A.claimed + s % (unsigned long long)A.ring;
+    // a look first: idle waves polling an exhausted request must not keep
+    // adding to its counter (2,000 waves adding 32 every look would carry the
+    // 32-bit claimed count into the request number within seconds, and the
+    // counter would then name a request it does not hold)
+    const unsigned long long seen =
+        __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((long long)(seen >> 32) == (long long)s &&
+        (long long)(seen & 0xffffffffull) >= n_of((long long)s)) {
+      if (s + 1 < pub) {
+        __hip_atomic_compare_exchange_strong((unsigned long long*)A.cur, &s, s + 1,
+                                             __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        continue;
+      }
+      return false;
+    }
+    const unsigned long long v = __hip_atomic_fetch_add(counter, (unsigned long long)want,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const long long sv = (long long)(v >> 32), k = (long long)(v & 0xffffffffull);
     if (sv < (long long)s) return false;  // the slot not yet set for s (cannot happen)
     const long long n = n_of(sv);
@@ -2092,7 +2110,8 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
       continue;
     }
     // nothing to run: stop if asked, or after idle_ticks without work; else
-    // wait a little and look again
+    // wait ~100 us and look again (each look is a few loads of the request
+    // words by each of ~2,000 waves)
     const unsigned long long now = __builtin_amdgcn_s_memrealtime();
     if (claimed_any || !idle) {
       idle = true;
@@ -2102,7 +2121,7 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
     if (lane == 0) stop = load_system(A.stop) != 0ull;
     if (__shfl(stop, 0, WAVE)) break;
     if (now - idle_since > (unsigned long long)A.idle_ticks) break;
-    for (int k = 0; k < 6; ++k) __builtin_amdgcn_s_sleep(127);
+    for (int k = 0; k < 30; ++k) __builtin_amdgcn_s_sleep(127);
   }
 }
 
