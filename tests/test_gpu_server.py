@@ -313,6 +313,28 @@ def test_resident_keeps_its_waves_while_any_has_work(ai, torch):
     assert t_mixed <= 3.0 * t_alone + 0.02
 
 
+def test_resident_claim_counter_survives_a_long_idle_spell(ai, torch):
+    """Regression: idle waves used to add to the last request's claim counter
+    at every look, so a kernel idle for a few seconds carried the 32-bit
+    claimed count into the request number (about 2,000 waves adding 32 every
+    ~100 us reach 2^32 in ~7 s), and a request published afterwards was served
+    from a counter naming a request it did not hold.  A request after an
+    8.5-second idle spell must still equal ai_integrate on it alone."""
+    import time
+    wl = W.small_ensemble()
+    y = wl.initial_states(384)
+    a, b = _request(torch, wl, y[:, :128]), _request(torch, wl, y[:, 128:])
+    with ai.Server(mode="resident", idle_ms=9000.0) as srv:
+        ia = srv.wait(srv.submit(a["item"]), timeout=60.0)
+        time.sleep(8.5)                  # the waves stay, idle, looking for work
+        ib = srv.wait(srv.submit(b["item"]), timeout=60.0)
+    assert ia["rc"] == ib["rc"] == 0
+    for r in (a, b):
+        fin, obs = _alone(ai, torch, r)
+        np.testing.assert_array_equal(r["fin"].cpu().numpy(), fin)
+        np.testing.assert_array_equal(r["obs"].cpu().numpy(), obs)
+
+
 def test_resident_stream_against_oracle(ai, torch, aio):
     """A mixed stream as the serving configuration draws it (RelTol 1e-6, 1e-8
     and 1e-10, double and single-precision-stage requests, temperature and q
