@@ -160,7 +160,8 @@ int ai_integrate(const ai_params *p, const double *y0, int64_t n, int64_t ld, do
  * AI_SCHEDULE_LONGEST_FIRST enqueues two kernels and nothing else (no
  * allocation, no memset), so that call may be captured in a HIP graph and
  * replayed; the schedule and the persistent kernel allocate stream-ordered
- * memory and the schedule's sort clears buffers, so those are not for capture. */
+ * memory here, so for capture use ai_integrate_static_async, whose scheduled
+ * plain call enqueues kernels only. */
 int ai_integrate_async(const ai_params *p, const double *y0, int64_t n, int64_t ld, double t0,
                        double tmax, double rtol, double atol, double *final_state, double *obs,
                        int32_t kernel, void *stream);
@@ -176,8 +177,9 @@ int ai_integrate_async(const ai_params *p, const double *y0, int64_t n, int64_t 
  * device's scratch and it keeps the last call's contents (the queue counter
  * is cleared by a kernel at the start of each persistent call), so calls
  * whose work overlaps on one device, from any stream or thread, race: the
- * caller orders them.  The schedule's sort clears buffers with memsets, so
- * only unscheduled calls are for graph capture. */
+ * caller orders them.  Its plain kernel calls, scheduled or not, enqueue
+ * kernels only (the schedule's counting sort writes every word it reads), so
+ * they may be captured in a HIP graph and replayed. */
 #define AI_STATIC_SCRATCH_BYTES (32ull << 20)
 #define AI_STATIC_MAX_SCHEDULED (1 << 20)
 int ai_integrate_static_async(const ai_params *p, const double *y0, int64_t n, int64_t ld,

@@ -4,8 +4,7 @@
 
 Each source is compiled to an object under _build/ and the objects are linked
 into libai.so.  --cached recompiles only objects older than their sources
-(the scheduling unit instantiates rocPRIM's radix sort and takes about a
-minute); --remarks prints the compiler's per-kernel resource usage (VGPRs,
+(the kernel unit takes about a minute); --remarks prints the compiler's per-kernel resource usage (VGPRs,
 AGPRs, scratch spills, occupancy).
 """
 from __future__ import annotations

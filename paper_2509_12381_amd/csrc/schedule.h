@@ -82,7 +82,7 @@ ai_order_model ai_make_order_model(const double a[3], const double q[3], double 
 // predicted costs in the same (decreasing) order in *key; both live inside
 // *workspace, which the caller releases with hipFreeAsync on the same stream
 // once the consumer has been enqueued.  The keys are the costs' codes
-// (AI_ORDER_CODES levels up to horizon x rate), equal codes in index order.
+// (AI_ORDER_CODES levels up to horizon x rate), equal codes in no fixed order.
 // Needs n < 2^32.  With ext (device memory of ext_bytes, at least
 // ai_order_workspace_bytes(n), 256-byte aligned) the work uses that buffer
 // instead, allocates nothing and leaves *workspace NULL; the buffer must stay

@@ -7,8 +7,6 @@
 // not depend on it.
 #include "schedule.h"
 
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -272,27 +270,157 @@ constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 namespace {
 
-// Workspace for n keys: the cost kernel's output, the sorted copy, and the
-// radix sort's scratch; `launch` enqueues the cost kernel into key_in/idx_in.
-// The keys have AI_ORDER_CODE_BITS significant bits, which is all the sort
-// looks at.
-// rocPRIM's radix sort with the onesweep algorithm from 4,096 items up (its
-// default sorts up to 2^20 items by merging, about twenty passes; onesweep
-// needs a histogram and one pass per 8 key bits).
-using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
-                                              rocprim::default_config, 4096>;
+// ---- Counting sort of the cost codes, descending ----
+//
+// The codes have AI_ORDER_CODE_BITS bits, so one counting pass orders them:
+// the keys are cut into tiles (one block each); a first kernel counts each
+// tile's codes in LDS; an exclusive scan over the counts, taken code by code
+// from the largest and tile by tile within a code, gives every (code, tile)
+// pair its first output position; a scatter kernel hands out positions within
+// a pair by LDS atomics.  Equal codes therefore come out in no fixed order,
+// which changes nothing but which lane integrates which trajectory.  Every
+// word of the workspace that is read is written first by these kernels, so
+// the sort needs no memset (and a stream capture records kernels only).
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_MAX_TILES = 1024;  // counts stay at most 16 MiB
+constexpr int SORT_ROW_THREADS = 256;
+constexpr int SORT_BASE_THREADS = 1024;
+static_assert(AI_ORDER_CODES % SORT_BASE_THREADS == 0, "rows per thread of the base scan");
+static_assert(SORT_MAX_TILES % SORT_ROW_THREADS == 0, "tiles per thread of the row scan");
 
-// Bytes of the workspace for n keys (the four arrays and the sort's scratch),
-// or 0 if rocPRIM cannot size it.
-size_t workspace_bytes(int64_t n, size_t* temp_out, hipStream_t stream) {
-  size_t temp_bytes = 0;
-  if (rocprim::radix_sort_pairs_desc<SortConfig>(nullptr, temp_bytes, (unsigned*)nullptr,
-                                                 (unsigned*)nullptr, (unsigned*)nullptr,
-                                                 (unsigned*)nullptr, (unsigned)n, 0,
-                                                 AI_ORDER_CODE_BITS, stream) != hipSuccess)
-    return 0;
-  if (temp_out) *temp_out = temp_bytes;
-  return 4 * align256(sizeof(unsigned) * (size_t)n) + align256(temp_bytes);
+struct SortLayout {
+  int tiles;     // blocks of the count and scatter kernels
+  int64_t tile;  // keys per tile, a multiple of SORT_THREADS
+};
+
+SortLayout sort_layout(int64_t n) {
+  int64_t tiles = (n + 4095) / 4096;
+  tiles = tiles < 1 ? 1 : (tiles > SORT_MAX_TILES ? SORT_MAX_TILES : tiles);
+  int64_t tile = (n + tiles - 1) / tiles;
+  tile = (tile + SORT_THREADS - 1) / SORT_THREADS * SORT_THREADS;
+  SortLayout L;
+  L.tile = tile;
+  L.tiles = (int)((n + tile - 1) / tile);
+  return L;
+}
+
+// Row r of the counts holds code AI_ORDER_CODES - 1 - r, so that rows in
+// increasing order are codes in decreasing order.
+__device__ __forceinline__ unsigned code_row(unsigned key) {
+  return AI_ORDER_CODES - 1u - (key < AI_ORDER_CODES ? key : AI_ORDER_CODES - 1u);
+}
+
+// counts[r * tiles + t]: keys of tile t in row r.
+__global__ __launch_bounds__(SORT_THREADS) void ai_sort_count_kernel(
+    const unsigned* __restrict__ key, long long n, long long tile, int tiles,
+    unsigned* __restrict__ counts) {
+  __shared__ unsigned h[AI_ORDER_CODES];
+  for (int r = threadIdx.x; r < (int)AI_ORDER_CODES; r += SORT_THREADS) h[r] = 0u;
+  __syncthreads();
+  const long long begin = (long long)blockIdx.x * tile;
+  const long long end = begin + tile < n ? begin + tile : n;
+  for (long long i = begin + threadIdx.x; i < end; i += SORT_THREADS)
+    atomicAdd(&h[code_row(key[i])], 1u);
+  __syncthreads();
+  for (int r = threadIdx.x; r < (int)AI_ORDER_CODES; r += SORT_THREADS)
+    counts[(long long)r * tiles + blockIdx.x] = h[r];
+}
+
+// Inclusive scan of one value per thread over a block of THREADS threads
+// (Hillis-Steele in LDS); `total` receives the block's sum.
+template <int THREADS>
+__device__ __forceinline__ unsigned block_inclusive_scan(unsigned v, unsigned* lds,
+                                                         unsigned& total) {
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  for (int d = 1; d < THREADS; d <<= 1) {
+    const unsigned add = threadIdx.x >= (unsigned)d ? lds[threadIdx.x - d] : 0u;
+    __syncthreads();
+    lds[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const unsigned r = lds[threadIdx.x];
+  total = lds[THREADS - 1];
+  __syncthreads();
+  return r;
+}
+
+// One block per row: the row's counts become offsets within the row
+// (exclusive scan over the tiles); row_total[r] receives the row's sum.
+__global__ __launch_bounds__(SORT_ROW_THREADS) void ai_sort_row_kernel(
+    unsigned* __restrict__ counts, int tiles, unsigned* __restrict__ row_total) {
+  __shared__ unsigned lds[SORT_ROW_THREADS];
+  unsigned* row = counts + (long long)blockIdx.x * tiles;
+  const int per = (tiles + SORT_ROW_THREADS - 1) / SORT_ROW_THREADS;  // at most 4
+  const int first = threadIdx.x * per;
+  unsigned local[SORT_MAX_TILES / SORT_ROW_THREADS];
+  unsigned sum = 0u;
+#pragma unroll
+  for (int j = 0; j < SORT_MAX_TILES / SORT_ROW_THREADS; ++j) {
+    const int t = first + j;
+    local[j] = (j < per && t < tiles) ? row[t] : 0u;
+    sum += local[j];
+  }
+  unsigned total = 0u;
+  unsigned run = block_inclusive_scan<SORT_ROW_THREADS>(sum, lds, total) - sum;
+#pragma unroll
+  for (int j = 0; j < SORT_MAX_TILES / SORT_ROW_THREADS; ++j) {
+    const int t = first + j;
+    if (j < per && t < tiles) row[t] = run;
+    run += local[j];
+  }
+  if (threadIdx.x == 0) row_total[blockIdx.x] = total;
+}
+
+// One block: row_base[r] = the sum of the rows before r.
+__global__ __launch_bounds__(SORT_BASE_THREADS) void ai_sort_base_kernel(
+    const unsigned* __restrict__ row_total, unsigned* __restrict__ row_base) {
+  __shared__ unsigned lds[SORT_BASE_THREADS];
+  constexpr int PER = AI_ORDER_CODES / SORT_BASE_THREADS;
+  unsigned local[PER];
+  unsigned sum = 0u;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    local[j] = row_total[threadIdx.x * PER + j];
+    sum += local[j];
+  }
+  unsigned total = 0u;
+  unsigned run = block_inclusive_scan<SORT_BASE_THREADS>(sum, lds, total) - sum;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    row_base[threadIdx.x * PER + j] = run;
+    run += local[j];
+  }
+}
+
+// Every key of tile t to its position: its row's base, the tile's offset in
+// the row, and a rank among the tile's keys of that row.
+__global__ __launch_bounds__(SORT_THREADS) void ai_sort_scatter_kernel(
+    const unsigned* __restrict__ key_in, const unsigned* __restrict__ idx_in, long long n,
+    long long tile, int tiles, const unsigned* __restrict__ offsets,
+    const unsigned* __restrict__ row_base, unsigned* __restrict__ key_out,
+    unsigned* __restrict__ idx_out) {
+  __shared__ unsigned cursor[AI_ORDER_CODES];
+  for (int r = threadIdx.x; r < (int)AI_ORDER_CODES; r += SORT_THREADS)
+    cursor[r] = row_base[r] + offsets[(long long)r * tiles + blockIdx.x];
+  __syncthreads();
+  const long long begin = (long long)blockIdx.x * tile;
+  const long long end = begin + tile < n ? begin + tile : n;
+  for (long long i = begin + threadIdx.x; i < end; i += SORT_THREADS) {
+    const unsigned k = key_in[i];
+    const unsigned pos = atomicAdd(&cursor[code_row(k)], 1u);
+    key_out[pos] = k;
+    idx_out[pos] = idx_in[i];
+  }
+}
+
+// Workspace for n keys: the cost kernel's output, the sorted copy, and the
+// counting sort's counts and row sums.
+size_t workspace_bytes(int64_t n) {
+  const SortLayout L = sort_layout(n);
+  return 4 * align256(sizeof(unsigned) * (size_t)n) +
+         align256(sizeof(unsigned) * (size_t)AI_ORDER_CODES * (size_t)L.tiles) +
+         2 * align256(sizeof(unsigned) * (size_t)AI_ORDER_CODES);
 }
 
 // ext: a caller's workspace of ext_bytes (nothing is allocated, *workspace
@@ -305,11 +433,11 @@ hipError_t sort_by_key(int64_t n, unsigned** order, unsigned** key, void** works
   *key = nullptr;
   *workspace = nullptr;
   if (n <= 0 || n > 0xffffffffLL) return hipErrorInvalidValue;
-  const unsigned size = (unsigned)n;
-  size_t temp_bytes = 0;
-  const size_t total = workspace_bytes(n, &temp_bytes, stream);
-  if (total == 0) return hipErrorInvalidValue;
+  const SortLayout L = sort_layout(n);
+  const size_t total = workspace_bytes(n);
   const size_t ubytes = align256(sizeof(unsigned) * (size_t)n);
+  const size_t cbytes = align256(sizeof(unsigned) * (size_t)AI_ORDER_CODES * (size_t)L.tiles);
+  const size_t rbytes = align256(sizeof(unsigned) * (size_t)AI_ORDER_CODES);
   hipError_t e = hipSuccess;
   char* base = ext;
   if (ext) {
@@ -321,11 +449,22 @@ hipError_t sort_by_key(int64_t n, unsigned** order, unsigned** key, void** works
   unsigned* key_out = (unsigned*)(base + ubytes);
   unsigned* idx_in = (unsigned*)(base + 2 * ubytes);
   unsigned* idx_out = (unsigned*)(base + 3 * ubytes);
-  void* temp = base + 4 * ubytes;
+  unsigned* counts = (unsigned*)(base + 4 * ubytes);
+  unsigned* row_total = (unsigned*)(base + 4 * ubytes + cbytes);
+  unsigned* row_base = (unsigned*)(base + 4 * ubytes + cbytes + rbytes);
   launch(key_in, idx_in);
-  if ((e = hipGetLastError()) == hipSuccess)
-    e = rocprim::radix_sort_pairs_desc<SortConfig>(temp, temp_bytes, key_in, key_out, idx_in,
-                                                   idx_out, size, 0, AI_ORDER_CODE_BITS, stream);
+  if ((e = hipGetLastError()) == hipSuccess) {
+    hipLaunchKernelGGL(ai_sort_count_kernel, dim3(L.tiles), dim3(SORT_THREADS), 0, stream,
+                       key_in, (long long)n, (long long)L.tile, L.tiles, counts);
+    hipLaunchKernelGGL(ai_sort_row_kernel, dim3(AI_ORDER_CODES), dim3(SORT_ROW_THREADS), 0,
+                       stream, counts, L.tiles, row_total);
+    hipLaunchKernelGGL(ai_sort_base_kernel, dim3(1), dim3(SORT_BASE_THREADS), 0, stream,
+                       row_total, row_base);
+    hipLaunchKernelGGL(ai_sort_scatter_kernel, dim3(L.tiles), dim3(SORT_THREADS), 0, stream,
+                       key_in, idx_in, (long long)n, (long long)L.tile, L.tiles, counts,
+                       row_base, key_out, idx_out);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) {
     if (!ext) (void)hipFreeAsync(base, stream);
     return e;
@@ -460,8 +599,8 @@ ai_order_model ai_make_order_model(const double a[3], const double q[3], double 
   return m;
 }
 
-size_t ai_order_workspace_bytes(int64_t n, hipStream_t stream) {
-  return n > 0 && n <= 0xffffffffLL ? workspace_bytes(n, nullptr, stream) : 0;
+size_t ai_order_workspace_bytes(int64_t n, hipStream_t) {
+  return n > 0 && n <= 0xffffffffLL ? workspace_bytes(n) : 0;
 }
 
 hipError_t ai_longest_first_order(const double* y0, int64_t n, int64_t ld,

@@ -1071,6 +1071,38 @@ def test_unscheduled_plain_call_replays_from_a_graph(ai, torch):
         np.testing.assert_array_equal(obs.cpu().numpy(), ref_o)
 
 
+def test_scheduled_static_call_replays_from_a_graph(ai, torch):
+    """With its workspace in the library's static scratch, the scheduled call
+    enqueues kernels only (the cost key, the counting sort's four kernels, the
+    integration and the finalize; no allocation, no memset), so it can be
+    captured in a HIP graph: every replay, with eager work between them, gives
+    the eager result."""
+    wl = W.small_ensemble()
+    y0 = torch.from_numpy(wl.initial_states()).cuda()
+    fin = torch.empty_like(y0)
+    obs = torch.empty((13, wl.n), dtype=torch.float64, device="cuda")
+    ai.ai_integrate(wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, fin, obs, "plain",
+                    schedule="longest-first")
+    torch.cuda.synchronize()
+    ref_f, ref_o = fin.cpu().numpy(), obs.cpu().numpy()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ai.ai_integrate_static_async(wl.system, y0, wl.t0, wl.tmax, wl.rtol, wl.atol, fin,
+                                         obs, "plain", schedule="longest-first", stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        fin.fill_(-1.0)
+        obs.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(fin.cpu().numpy(), ref_f)
+        np.testing.assert_array_equal(obs.cpu().numpy(), ref_o)
+
+
 def test_trace_refine_follows_closed_form(ai, torch):
     """refine = 4 (ode45's default number of output points per step): with the
     atom-ion interaction off and a static harmonic trap, the ion oscillates as
