@@ -969,7 +969,8 @@ __device__ __forceinline__ void attempt32(const Force32& P, const Ctl& K, Lane& 
 
 // End of trajectory idx: store the final state and the raw accumulators.
 // Derived observables are formed afterwards by ai_finalize_kernel from these
-// planes, so the integration loops carry no atan2 or square roots; until then
+// planes (the plain kernels form them at the end instead: finish_derived),
+// so the integration loops carry no atan2 or square roots; until then
 // the lifetime, angle, transfer, dist, ke and rmin planes hold t_first,
 // t_last, the atom's initial velocity (3 planes) and rmin^2.
 // va0 is the atom's initial velocity (kept by the caller: final_state may be
@@ -1124,11 +1125,58 @@ __device__ __forceinline__ float wave_uniform(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// One trajectory per lane; the grid covers n.  Lane g integrates trajectory
-// order[g] (g itself when order is null); with the schedule's keys the wave
-// takes the priority of its first (longest) trajectory.
-// Trajectory idx of the ensemble P, start to end, by one lane.
-template <class R, class F = Force>
+// The derived observables out of line, for the resident kernel, where a
+// lane ends trajectories inside its loop: inlined there, the temporaries of
+// atan2 and the square roots added ~40 registers spilled to scratch.
+__device__ __attribute__((noinline)) Derived derive_at_end(
+    double t_first, double t_last, double va0x, double va0y, double va0z, double rmin2,
+    double bounces, double vix, double viy, double viz, double vax, double vay, double vaz,
+    double dx, double dy, double dz, double m_atom, double half_mi) {
+  return derive_from(t_first, t_last, va0x, va0y, va0z, rmin2, bounces, vix, viy, viz, vax, vay,
+                     vaz, dx, dy, dz, m_atom, half_mi);
+}
+
+// finish() with the derived observables formed here, from the same values
+// ai_finalize_kernel would read back (so the results are bitwise the same),
+// instead of by that kernel afterwards.  Called after the integration loop,
+// inline: the loop's registers are free by then.
+template <class R>
+__device__ __forceinline__ void finish_derived(const Launch& P, const LaneT<R>& L, long long idx,
+                                               double va0x, double va0y, double va0z) {
+  const Derived d = derive_from(L.t_first, L.t_last, va0x, va0y, va0z, L.rmin2,
+                                  (double)L.bounces, L.v[0], L.v[1], L.v[2], L.v[3], L.v[4],
+                                  L.v[5], L.x[0] - L.x[3], L.x[1] - L.x[4], L.x[2] - L.x[5],
+                                  P.m_atom, P.half_mi);
+  const long long ld = P.ld;
+  double o[AI_NOBS];
+  o[AI_OBS_TEND] = L.t;
+  o[AI_OBS_STATUS] = (double)L.status;
+  o[AI_OBS_NSTEPS] = (double)L.nsteps;
+  o[AI_OBS_NFAILED] = (double)L.nfailed;
+  o[AI_OBS_BOUNCES] = (double)L.bounces;
+  o[AI_OBS_LIFETIME] = d.lifetime;
+  o[AI_OBS_ANGLE] = d.angle;
+  o[AI_OBS_TRANSFER] = d.transfer;
+  o[AI_OBS_POSITION] = L.position;
+  o[AI_OBS_DIST] = d.dist;
+  o[AI_OBS_KE] = d.ke;
+  o[AI_OBS_RMIN] = d.rmin;
+  o[AI_OBS_HNEXT] = L.absh;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    P.yf[k * ld + idx] = L.x[k];
+    P.yf[(3 + k) * ld + idx] = L.v[k];
+    P.yf[(6 + k) * ld + idx] = L.x[3 + k];
+    P.yf[(9 + k) * ld + idx] = L.v[3 + k];
+  }
+#pragma unroll
+  for (int c = 0; c < AI_NOBS; ++c) P.obs[c * ld + idx] = o[c];
+}
+
+// Trajectory idx of the ensemble P, start to end, by one lane.  DERIVE: form
+// the derived observables here (finish_derived) rather than leave the raw
+// accumulators for ai_finalize_kernel (finish).
+template <class R, class F = Force, bool DERIVE = false>
 __device__ __forceinline__ void integrate_one(const Launch& P, long long idx) {
   const Ctl K = lane_ctl(P);
   const F Fc = lane_force_of(P, (const F*)nullptr);
@@ -1160,7 +1208,10 @@ __device__ __forceinline__ void integrate_one(const Launch& P, long long idx) {
   }
   // the initial atom velocity is read before final_state (possibly y0) is written
   const double* va0 = P.y0 + 9 * P.ld + idx;
-  finish(P.yf, P.obs, P.ld, L, idx, va0[0], va0[P.ld], va0[2 * P.ld]);
+  if constexpr (DERIVE)
+    finish_derived(P, L, idx, va0[0], va0[P.ld], va0[2 * P.ld]);
+  else
+    finish(P.yf, P.obs, P.ld, L, idx, va0[0], va0[P.ld], va0[2 * P.ld]);
 }
 
 // ---- Four lanes per trajectory ----
@@ -1333,8 +1384,9 @@ __device__ __forceinline__ void attempt_wide(const F& P, double ka, double kq, c
 
 // Trajectory idx by the four lanes of a quad; this lane holds axis ax and, if
 // it is the quad's lane q < 3, stores that axis's final state (q = 0 also the
-// observables).  The start is the one-lane start on every lane.
-template <class F>
+// observables, with DERIVE the derived ones as finish_derived forms them).
+// The start is the one-lane start on every lane.
+template <class F, bool DERIVE = false>
 __device__ __forceinline__ void integrate_wide(const Launch& P, long long idx, int q) {
   const int ax = q < 3 ? q : 2;
   const Ctl K = lane_ctl(P);
@@ -1384,6 +1436,21 @@ __device__ __forceinline__ void integrate_wide(const Launch& P, long long idx, i
     P.yf[(6 + ax) * ld + idx] = W.xa;
     P.yf[(9 + ax) * ld + idx] = W.va;
   }
+  // DERIVE: lane q = 0 gathers the other axes' final values from lanes 1
+  // and 2 of its quad and forms the derived observables (as finish_derived)
+  double vi[3], va[3], d[3];
+  if constexpr (DERIVE) {
+    const double dq = W.xi - W.xa;
+    vi[0] = from_quad_lane<0>(W.vi);
+    vi[1] = from_quad_lane<1>(W.vi);
+    vi[2] = from_quad_lane<2>(W.vi);
+    va[0] = from_quad_lane<0>(W.va);
+    va[1] = from_quad_lane<1>(W.va);
+    va[2] = from_quad_lane<2>(W.va);
+    d[0] = from_quad_lane<0>(dq);
+    d[1] = from_quad_lane<1>(dq);
+    d[2] = from_quad_lane<2>(dq);
+  }
   if (q == 0) {
     double o[AI_NOBS];
     o[AI_OBS_TEND] = W.t;
@@ -1399,6 +1466,17 @@ __device__ __forceinline__ void integrate_wide(const Launch& P, long long idx, i
     o[AI_OBS_KE] = y[11];
     o[AI_OBS_RMIN] = W.rmin2;
     o[AI_OBS_HNEXT] = W.absh;
+    if constexpr (DERIVE) {
+      const Derived dv = derive_from(W.t_first, W.t_last, y[9], y[10], y[11], W.rmin2,
+                                       (double)W.bounces, vi[0], vi[1], vi[2], va[0], va[1], va[2],
+                                       d[0], d[1], d[2], P.m_atom, P.half_mi);
+      o[AI_OBS_LIFETIME] = dv.lifetime;
+      o[AI_OBS_ANGLE] = dv.angle;
+      o[AI_OBS_TRANSFER] = dv.transfer;
+      o[AI_OBS_DIST] = dv.dist;
+      o[AI_OBS_KE] = dv.ke;
+      o[AI_OBS_RMIN] = dv.rmin;
+    }
 #pragma unroll
     for (int c = 0; c < AI_NOBS; ++c) P.obs[c * ld + idx] = o[c];
   }
@@ -1426,7 +1504,7 @@ __device__ __forceinline__ void plain_body(const Launch& P) {
       wave_priority_from_keys(P.key, first);
       const long long g = first + (threadIdx.x >> 2);
       if (g >= P.wide) return;
-      integrate_wide<F>(P, (long long)P.order[g], (int)(threadIdx.x & 3));
+      integrate_wide<F, true>(P, (long long)P.order[g], (int)(threadIdx.x & 3));
       return;
     }
   }
@@ -1434,7 +1512,7 @@ __device__ __forceinline__ void plain_body(const Launch& P) {
   wave_priority_from_keys(P.key, first);
   const long long g = first + threadIdx.x;
   if (g >= P.n) return;
-  integrate_one<R, F>(P, P.order ? (long long)P.order[g] : g);
+  integrate_one<R, F, true>(P, P.order ? (long long)P.order[g] : g);
 }
 
 __global__ __launch_bounds__(BLOCK) void ai_plain_kernel(Launch P) { plain_body<double>(P); }
@@ -1819,18 +1897,6 @@ __device__ __forceinline__ Force32 force32_of(const Force& F) {
   return f;
 }
 
-// The derived observables out of line, so that the temporaries of atan2 and
-// the square roots do not add to the registers the integration loop holds
-// (a call on the rare path where a lane ends a trajectory; inlined, it added
-// ~40 registers spilled to scratch).
-__device__ __attribute__((noinline)) Derived resident_derive(
-    double t_first, double t_last, double va0x, double va0y, double va0z, double rmin2,
-    double bounces, double vix, double viy, double viz, double vax, double vay, double vaz,
-    double dx, double dy, double dz, double m_atom, double half_mi) {
-  return derive_from(t_first, t_last, va0x, va0y, va0z, rmin2, bounces, vix, viy, viz, vax, vay,
-                     vaz, dx, dy, dz, m_atom, half_mi);
-}
-
 // The leader lane's claim: up to `want` trajectories of the oldest published
 // request with work left, as (request, first index, count); false if there is
 // none.  Each ring slot has a claim counter packing (request << 32 | claimed),
@@ -1991,7 +2057,7 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
 #pragma unroll
         for (int c = 0; c < 12; ++c) store_through(yf + c * ld + i, y[c]);
         const double bounces = (double)L.bounces;
-        const Derived d = resident_derive(
+        const Derived d = derive_at_end(
             L.t_first, L.t_last, lane_va0[0][lane], lane_va0[1][lane], lane_va0[2][lane], L.rmin2,
             bounces, y[3], y[4], y[5], y[9], y[10], y[11], y[0] - y[6], y[1] - y[7], y[2] - y[8],
             lane_m_atom[lane], lane_half_mi[lane]);
@@ -2771,7 +2837,9 @@ int integrate_async(const ai_params* p, const double* y0, int64_t n, int64_t ld,
       release();
       return rc;
     }
-    return conclude();
+    // the plain kernels store the derived observables themselves
+    const int rrc = release();
+    return rrc != AI_OK ? rrc : warn;
   }
 
   const int refill_min = (kernel >> 8) & 0x7f;

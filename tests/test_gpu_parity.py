@@ -1073,8 +1073,8 @@ def test_unscheduled_plain_call_replays_from_a_graph(ai, torch):
 
 def test_scheduled_static_call_replays_from_a_graph(ai, torch):
     """With its workspace in the library's static scratch, the scheduled call
-    enqueues kernels only (the cost key, the counting sort's four kernels, the
-    integration and the finalize; no allocation, no memset), so it can be
+    enqueues kernels only (the cost key, the counting sort's four kernels and
+    the integration kernel; no allocation, no memset), so it can be
     captured in a HIP graph: every replay, with eager work between them, gives
     the eager result."""
     wl = W.small_ensemble()
