@@ -157,7 +157,7 @@ int ai_integrate(const ai_params *p, const double *y0, int64_t n, int64_t ld, do
  * on the stream has completed; the library keeps no pointer after that.
  * The persistent kernel takes an 8-byte queue counter from the stream-ordered
  * allocator for the duration of the call.  The plain kernel without
- * AI_SCHEDULE_LONGEST_FIRST enqueues two kernels and nothing else (no
+ * AI_SCHEDULE_LONGEST_FIRST enqueues its one kernel and nothing else (no
  * allocation, no memset), so that call may be captured in a HIP graph and
  * replayed; the schedule and the persistent kernel allocate stream-ordered
  * memory here, so for capture use ai_integrate_static_async, whose scheduled

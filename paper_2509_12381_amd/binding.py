@@ -395,7 +395,7 @@ def ai_batch_plan_destroy(plan):
 
 class BatchPlan:
     """ai_batch_plan: a batch (batch_items tuples) prepared once; launch()
-    enqueues only its two kernels (capturable in a HIP graph).  The tensors of
+    enqueues only its one kernel (capturable in a HIP graph).  The tensors of
     the items must stay alive while the plan is used."""
 
     def __init__(self, items, schedule="longest-first"):

@@ -1098,13 +1098,6 @@ __device__ __forceinline__ int batch_entry(const BatchEntry* E, int count, long 
   return lo;
 }
 
-__global__ __launch_bounds__(256) void ai_finalize_batch_kernel(BatchLaunch B) {
-  const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (j >= B.total) return;
-  const BatchEntry& E = B.entries[batch_entry(B.entries, B.count, j)];
-  finalize_one(E.P, E.P.yf, E.P.obs, j - E.offset);
-}
-
 // Wave priority from the predicted duration of the wave's longest trajectory
 // relative to the longest in the ensemble (both from the longest-first
 // schedule).  The longest trajectories set the end of the launch; while they
@@ -1620,7 +1613,8 @@ __global__ __launch_bounds__(BLOCK) void ai_plain_nm_kernel(Launch P) {
 // ensemble's constants, buffers and tolerances.
 // The grid is laid out as the plain kernel's: B.wide_waves waves of four-lane
 // trajectories (positions 0 .. B.wide - 1 of the order), then one trajectory
-// per lane.
+// per lane; as there, the derived observables are formed at each
+// trajectory's end.
 __global__ __launch_bounds__(BLOCK) void ai_plain_batch_kernel(BatchLaunch B) {
   const long long w = blockIdx.x;
   if (w < B.wide_waves) {
@@ -1630,7 +1624,7 @@ __global__ __launch_bounds__(BLOCK) void ai_plain_batch_kernel(BatchLaunch B) {
     if (g >= B.wide) return;
     const long long j = (long long)B.order[g];
     const BatchEntry& E = B.entries[batch_entry(B.entries, B.count, j)];
-    integrate_wide<Force>(E.P, j - E.offset, (int)(threadIdx.x & 3));
+    integrate_wide<Force, true>(E.P, j - E.offset, (int)(threadIdx.x & 3));
     return;
   }
   const long long first = B.wide + (w - B.wide_waves) * BLOCK;
@@ -1639,7 +1633,7 @@ __global__ __launch_bounds__(BLOCK) void ai_plain_batch_kernel(BatchLaunch B) {
   if (g >= B.total) return;
   const long long j = B.order ? (long long)B.order[g] : g;
   const BatchEntry& E = B.entries[batch_entry(B.entries, B.count, j)];
-  integrate_one<double>(E.P, j - E.offset);
+  integrate_one<double, Force, true>(E.P, j - E.offset);
 }
 
 __global__ void ai_queue_reset_kernel(unsigned long long* queue) { *queue = 0ull; }
@@ -3173,13 +3167,13 @@ int ai_integrate_batch_async(const ai_batch_item* items, int32_t count, int32_t 
   char* table = nullptr;
   if ((e = hipMallocAsync((void**)&table, tbytes, s)) != hipSuccess) {
     (void)hipGetLastError();
-    pinned_release(stage, s, false);
+    (void)pinned_release(stage, s, false);  // nothing was copied: cannot fail
     return fail(AI_ENOMEM, "hipMallocAsync(batch table): %s", hipGetErrorString(e));
   }
   if ((e = hipMemcpyAsync(table, stage->host, tbytes, hipMemcpyHostToDevice, s)) !=
       hipSuccess) {
     (void)hipGetLastError();
-    pinned_release(stage, s, false);
+    (void)pinned_release(stage, s, false);  // nothing was copied: cannot fail
     (void)hipFreeAsync(table, s);
     return hip_fail(e, "hipMemcpyAsync(batch table)");
   }
@@ -3230,12 +3224,6 @@ int ai_integrate_batch_async(const ai_batch_item* items, int32_t count, int32_t 
   if ((trc = time_mark(kernel, false, s)) != AI_OK) {
     release();
     return trc;
-  }
-  hipLaunchKernelGGL(ai_finalize_batch_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
-                     0, s, B);
-  if ((e = hipGetLastError()) != hipSuccess) {
-    release();
-    return hip_fail(e, "launch(finalize batch)");
   }
   const int rc = release();
   return rc != AI_OK ? rc : warn;
@@ -3346,9 +3334,6 @@ int ai_batch_plan_launch(const ai_batch_plan* pl, void* stream) {
   hipLaunchKernelGGL(ai_plain_batch_kernel, dim3(batch_blocks(B)), dim3(BLOCK), 0, s, B);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "launch(plan)");
-  hipLaunchKernelGGL(ai_finalize_batch_kernel, dim3((unsigned)((B.total + 255) / 256)), dim3(256),
-                     0, s, B);
-  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "launch(plan finalize)");
   return pl->warn;
 }
 

@@ -876,7 +876,7 @@ def test_batch_plan_matches_batched_call(ai, torch, schedule):
 
 
 def test_batch_plan_replays_from_a_graph(ai, torch):
-    """A plan's launch enqueues two kernels and nothing else, so it can be
+    """A plan's launch enqueues one kernel and nothing else, so it can be
     captured in a HIP graph: every replay, with eager work between them, gives
     the batched call's result, also after new initial states are written into
     the items' buffers (the order computed at creation affects only the time)."""
@@ -1043,7 +1043,7 @@ def test_trace_path_conserves_energy_trap_off(ai, torch, aio):
 
 
 def test_unscheduled_plain_call_replays_from_a_graph(ai, torch):
-    """The plain kernel without the schedule enqueues two kernels and nothing
+    """The plain kernel without the schedule enqueues one kernel and nothing
     else (no allocation, no memset), so a caller may capture the call in a HIP
     graph: every replay, with eager work between them, gives the eager result."""
     wl = W.small_ensemble()
