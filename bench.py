@@ -730,10 +730,13 @@ def main() -> int:
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic, "kernel": KERNEL_SYMBOL[args.kernel],
                      "flop_per_launch": flop, "kernel_ms": kernel_ms, "call_ms": call_ms,
+                     "kernel_ms_each": [round(x, 4) for x in reversed(kernel_ms_each)],
+                     "call_ms_each": [round(x, 4) for x in per_ms],
                      "what": "achieved: algorithmic FLOPs (the 12-component Dormand-Prince "
                              "attempt, 922 per attempt) over kernel_ms, the integration kernel "
-                             "alone (AI_TIME_KERNEL events on the launch stream); call_ms: the "
-                             "whole call with the schedule and the observables",
+                             "alone (AI_TIME_KERNEL events on the launch stream), the mean of "
+                             "kernel_ms_each (the timed calls in order); call_ms: the whole "
+                             "call with the schedule, the mean of call_ms_each",
                      **(counter_rate or {"counter_tflops": None})},
         "ensemble": ensemble_statistics(W, stats, ob, wl.tmax),
         "kernel_info": info,
