@@ -2,11 +2,14 @@
 // points of ai.h; host code only).
 //
 // Resident mode (continuous batching): one dispatcher thread admits requests
-// in arrival order into the server's device slab by footprint, copies their
-// initial states in on a stream of its own, publishes each to the resident
-// kernel (ai.hip) through a ring of descriptors in host-coherent memory, keeps
-// the kernel running (relaunching it after it has exited for lack of work),
-// watches the completion words the kernel writes, copies results out on a
+// in arrival order by footprint against the server's device slab, copies the
+// initial states of requests whose buffers are host memory into the slab on a
+// stream of its own (device buffers are integrated in place), publishes each
+// request to the resident kernel (ai.hip) by copying its descriptor from a
+// pinned staging ring into a ring of descriptors in device memory and then the
+// new request count into a device word, keeps the kernel running (relaunching
+// it after it has exited for lack of work), watches the completion words the
+// kernel writes into host-coherent memory, copies staged results out on a
 // second stream and frees the slab space.
 //
 // Launch mode: each of the server's workers owns a stream and a thread.  A
