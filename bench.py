@@ -324,8 +324,10 @@ def serving(binding, W, torch, count: int, saturate: int, resident_paced: int,
     sizes, tolerances, precision, temperature and q per request), paced,
     served by batched launches (three workers, longest-first schedule); the
     first `saturate` requests again, submitted at once, served by the resident
-    kernel (continuous batching, admission by footprint, 4 GiB budget): the
-    sustained rate; and the first `resident_paced` requests of the stream
+    kernel (continuous batching, admission by footprint, a budget that holds
+    them all): the
+    sustained rate, and once more through batched launches for comparison;
+    and the first `resident_paced` requests of the stream
     paced through the resident kernel (idle_ms 500, so that its waves stay
     through the stream's quiet spells)."""
     stream, reqs = serving_requests(W, torch, count, W.SERVING_RATE_HZ)
@@ -337,16 +339,30 @@ def serving(binding, W, torch, count: int, saturate: int, resident_paced: int,
         progress(f"serving: paced stream, p50 {out['paced']['latency_ms']['p50']:.1f} ms, "
                  f"p99 {out['paced']['latency_ms']['p99']:.1f} ms")
     if saturate:
-        with binding.Server(mode="resident") as srv:
+        # a budget that admits every request at once (their footprints; the
+        # buffers are device memory, integrated in place)
+        need = sum(37 * ((8 * r.n + 255) // 256 * 256) for r, *_ in reqs[:saturate])
+        slab = max(4 << 30, (need + (1 << 30) - 1) >> 30 << 30)
+        with binding.Server(mode="resident", slab_bytes=slab) as srv:
             sat = serve_stream(binding, W, torch, reqs[:saturate], srv, pace=False)
         sat["mode"] = "resident"
-        sat["slab_bytes"] = 4 << 30
+        sat["slab_bytes"] = slab
         sat["vs_plain_kernel"] = sat["trajectories_per_s"] / plain_traj_per_s
         # the stream's trajectories cost more on average (RelTol down to 1e-10,
         # cold atoms), so accepted steps/s compare the work rates
         sat["steps_vs_plain_kernel"] = sat["accepted_steps_per_s"] / plain_steps_per_s
         out["saturated"] = sat
         progress(f"serving: saturated, {sat['trajectories_per_s']:.3g} trajectories/s")
+        # the same requests at once through batched launches: per launch the
+        # longest-first order across its requests, and one precision per launch
+        with binding.Server(schedule="longest-first") as srv:
+            satl = serve_stream(binding, W, torch, reqs[:saturate], srv, pace=False)
+        satl["mode"] = "launches"
+        satl["vs_plain_kernel"] = satl["trajectories_per_s"] / plain_traj_per_s
+        satl["steps_vs_plain_kernel"] = satl["accepted_steps_per_s"] / plain_steps_per_s
+        out["saturated_launches"] = satl
+        progress(f"serving: saturated through launches, {satl['trajectories_per_s']:.3g} "
+                 f"trajectories/s")
     if resident_paced:
         # waves that stay through the stream's quiet spells: each leaves after
         # idle_ms without work of its own (the default 20 ms lets most leave)

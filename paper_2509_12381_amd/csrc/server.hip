@@ -378,6 +378,7 @@ void ai_server::dispatch() {
       progress = true;
     }
     // published requests (their copies have completed), in order
+    std::vector<RequestPtr> fresh;
     while (!staging.empty()) {
       const RequestPtr r = staging.front();
       const hipError_t q = hipEventQuery(r->copied_in);
@@ -395,41 +396,33 @@ void ai_server::dispatch() {
       r->info.batch_size = (int32_t)(running.size() + 1);
       r->info.batch_trajectories = in_flight_traj;
       running.push_back(r);
-      // the kernel must be running while published requests are unfinished
-      if (kernel_running && hipEventQuery(kernel_done) != hipErrorNotReady) kernel_running = false;
-      if (!kernel_running) {
-        int64_t waves = 0;
-        const int lrc = ai_resident_launch(&args, kstream, &waves);
-        hipError_t e = lrc == AI_OK ? hipEventRecord(kernel_done, kstream) : hipSuccess;
-        if (lrc != AI_OK || e != hipSuccess) {
-          const std::string why = lrc != AI_OK ? std::string(ai_last_error())
-                                               : hip_error(e, "hipEventRecord");
-          for (const RequestPtr& x : running) finish(x, AI_EHIP, why);
-          running.clear();
-          in_flight_traj = 0;
-          continue;
-        }
-        kernel_running = true;
-        launches += 1;
-      }
-      r->info.batch_id = launches - 1;
+      fresh.push_back(r);
     }
-    // a kernel that ran out of work and exited while requests were published
-    // is started again
-    if (!running.empty() && kernel_running && hipEventQuery(kernel_done) != hipErrorNotReady) {
+    // the kernel runs while published requests are unfinished.  Its waves
+    // hold every compute unit while they live, and the runtime runs the
+    // publication copies as kernels, so a launch waits until every
+    // publication enqueued so far has completed: it then starts with all of
+    // them in view instead of holding the rest back until its waves leave
+    if (kernel_running && hipEventQuery(kernel_done) != hipErrorNotReady) kernel_running = false;
+    if (!running.empty() && !kernel_running && staging.empty()) {
       int64_t waves = 0;
       const int lrc = ai_resident_launch(&args, kstream, &waves);
-      if (lrc == AI_OK && hipEventRecord(kernel_done, kstream) == hipSuccess) {
-        launches += 1;
-        progress = true;
-      } else {
-        const std::string why = ai_last_error();
+      const hipError_t e = lrc == AI_OK ? hipEventRecord(kernel_done, kstream) : hipSuccess;
+      if (lrc != AI_OK || e != hipSuccess) {
+        const std::string why = lrc != AI_OK ? std::string(ai_last_error())
+                                             : hip_error(e, "hipEventRecord");
         for (const RequestPtr& x : running) finish(x, AI_EHIP, why);
         running.clear();
+        fresh.clear();
         in_flight_traj = 0;
-        kernel_running = false;
+      } else {
+        kernel_running = true;
+        launches += 1;
+        progress = true;
       }
     }
+    // the launch that serves them: the running one, else the next
+    for (const RequestPtr& r : fresh) r->info.batch_id = kernel_running ? launches - 1 : launches;
     // completed requests: results out to the caller's buffers
     for (auto it = running.begin(); it != running.end();) {
       const RequestPtr r = *it;
