@@ -970,10 +970,9 @@ __device__ __forceinline__ void attempt32(const Force32& P, const Ctl& K, Lane& 
 // End of trajectory idx: store the final state and the raw accumulators.
 // Derived observables are formed afterwards by ai_finalize_kernel from these
 // planes (the plain and batched kernels form them at the end instead:
-// finish_derived),
-// so the integration loops carry no atan2 or square roots; until then
-// the lifetime, angle, transfer, dist, ke and rmin planes hold t_first,
-// t_last, the atom's initial velocity (3 planes) and rmin^2.
+// finish_derived), so the integration loops carry no atan2 or square roots;
+// until then the lifetime, angle, transfer, dist, ke and rmin planes hold
+// t_first, t_last, the atom's initial velocity (3 planes) and rmin^2.
 // va0 is the atom's initial velocity (kept by the caller: final_state may be
 // the y0 buffer itself).
 template <class R>
