@@ -1850,6 +1850,12 @@ constexpr int RES_BACKOFF = 64;
 // the unstarted ones of a claim and hands them to its lanes as they free up,
 // so the claim word sees one compare-and-swap per chunk.
 constexpr int RES_CHUNK = 32;
+// How far past the oldest request with work left a wave looks for a request
+// of its own precision, and how many of its lanes must be running for it to
+// look only for that precision (see claim()).
+constexpr int RES_CLASS_WINDOW = 16;
+constexpr int RES_CLASS_KEEP = 32;
+static_assert(offsetof(ResidentDesc, fp32) % 8 == 0, "precision flag in a word of its own");
 
 __device__ __forceinline__ unsigned long long load_system(const uint64_t* p) {
   return __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
@@ -1905,9 +1911,50 @@ __device__ __forceinline__ Force32 force32_of(const Force& F) {
 // nothing; a claim looks at the counter before adding to it, so only claims
 // racing at a request's end add past its size.  n_of(seq) gives a request's
 // size.  Bounded: gives up after a few rounds (and is retried later).
-template <class SizeOf>
-__device__ bool claim(const ai_resident_args& A, int want, long long& seq, long long& first,
-                      int& count, SizeOf n_of) {
+//
+// Precision: a lane runs the double or the single-precision-stage attempt as
+// its request asks, so a wave holding lanes of both kinds issues both every
+// iteration.  A wave with at least RES_CLASS_KEEP lanes running requests of
+// one kind (cls: 0 double, 1 single-precision stages; -1 for any other wave)
+// therefore claims only requests of that kind: when the oldest request with
+// work left is of the other kind it takes the next one of its own kind within
+// RES_CLASS_WINDOW requests (claim_ahead), or nothing.  A wave with fewer
+// running lanes (one kept alive by a few long trajectories, say) takes the
+// oldest request whatever its kind, so mixing costs a wave at most half its
+// issue slots and the oldest request always has waves that take it.
+// cls_of(seq) gives a request's kind.
+template <class SizeOf, class ClassOf>
+__device__ bool claim_ahead(const ai_resident_args& A, int want, int cls, unsigned long long s,
+                            unsigned long long pub, long long& seq, long long& first, int& count,
+                            SizeOf n_of, ClassOf cls_of) {
+  const unsigned long long reach =
+      (unsigned long long)(RES_CLASS_WINDOW < A.ring - 1 ? RES_CLASS_WINDOW : A.ring - 1);
+  const unsigned long long end = s + 1 + reach < pub ? s + 1 + reach : pub;
+  for (unsigned long long t = s + 1; t < end; ++t) {
+    unsigned long long* counter = (unsigned long long*)A.claimed + t % (unsigned long long)A.ring;
+    const unsigned long long seen =
+        __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the slot holds request t (its descriptor was copied before its counter
+    // was set), of this kind, with trajectories left
+    if ((long long)(seen >> 32) != (long long)t || cls_of((long long)t) != cls) continue;
+    const long long n = n_of((long long)t);
+    if ((long long)(seen & 0xffffffffull) >= n) continue;
+    const unsigned long long v = __hip_atomic_fetch_add(counter, (unsigned long long)want,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long sv = (long long)(v >> 32), k = (long long)(v & 0xffffffffull);
+    if (sv == (long long)t && k < n) {
+      seq = sv;
+      first = k;
+      count = (int)(n - k < want ? n - k : want);
+      return true;
+    }
+  }
+  return false;
+}
+
+template <class SizeOf, class ClassOf>
+__device__ bool claim(const ai_resident_args& A, int want, int cls, long long& seq,
+                      long long& first, int& count, SizeOf n_of, ClassOf cls_of) {
   for (int tries = 0; tries < 8; ++tries) {
     const unsigned long long pub = load_system(A.pub);
     unsigned long long s =
@@ -1931,6 +1978,8 @@ __device__ bool claim(const ai_resident_args& A, int want, long long& seq, long 
       }
       return false;
     }
+    if (cls >= 0 && (long long)(seen >> 32) == (long long)s && cls_of((long long)s) != cls)
+      return claim_ahead(A, want, cls, s, pub, seq, first, count, n_of, cls_of);
     const unsigned long long v = __hip_atomic_fetch_add(counter, (unsigned long long)want,
                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const long long sv = (long long)(v >> 32), k = (long long)(v & 0xffffffffull);
@@ -1982,6 +2031,7 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
   unsigned long long idle_since = 0;
   bool idle = false;
   int backoff = 0;                      // attempts before the next claim
+  int wave_cls = -1;                    // wave-uniform: kind of the running lanes' requests
   const int refill_min = A.refill_min;
 
   for (;;) {
@@ -2096,14 +2146,21 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
       const unsigned long long freel = __ballot(!busy);
       if (freel == 0ull) break;
       if (st_next >= st_end) {
+        const int cls = __popcll(__ballot(busy)) >= RES_CLASS_KEEP ? wave_cls : -1;
         if (lane == 0) {
           long long seq = -1, first = 0;
           int count = 0;
-          const bool got = claim(A, RES_CHUNK, seq, first, count, [&](long long s) {
-            if (s == cur_seq) return cur_n;
-            const ResidentDesc* d = (const ResidentDesc*)&A.desc[s % A.ring];
-            return (long long)load_system((const uint64_t*)&d->P.n);
-          });
+          const bool got = claim(
+              A, RES_CHUNK, cls, seq, first, count,
+              [&](long long s) {
+                if (s == cur_seq) return cur_n;
+                const ResidentDesc* d = (const ResidentDesc*)&A.desc[s % A.ring];
+                return (long long)load_system((const uint64_t*)&d->P.n);
+              },
+              [&](long long s) {
+                const ResidentDesc* d = (const ResidentDesc*)&A.desc[s % A.ring];
+                return (load_system((const uint64_t*)&d->fp32) & 0xffffffffull) != 0ull ? 1 : 0;
+              });
           claim_info[0] = got ? seq : -1;
           claim_info[1] = first;
           claim_info[2] = count;
@@ -2130,6 +2187,7 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
           cur_seq = seq;
           cur_n = lds_desc.P.n;
         }
+        wave_cls = lds_desc.fp32 ? 1 : 0;
         st_next = first;
         st_end = first + count;
       }
