@@ -2198,7 +2198,14 @@ __global__ __launch_bounds__(BLOCK, 2) void ai_resident_kernel(ai_resident_args 
       const int e = (int)lanes_below(freel);
       if (!busy && e < count) {
         const Launch& P = lds_desc.P;
-        const long long i = first + e;
+        // with the request's order (longest predicted first), position
+        // first + e holds trajectory order[first + e]; written by the order's
+        // kernels before the request was published, read past any line an
+        // earlier request left in this die's L2
+        const long long i =
+            P.order ? (long long)__hip_atomic_load(P.order + first + e, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_SYSTEM)
+                    : first + e;
         double y[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) y[c] = load_through(P.y0 + c * P.ld + i);
@@ -2665,7 +2672,7 @@ int ai_check_request(const ai_batch_item* item, int32_t kernel, bool host_ok) {
 
 void ai_resident_describe(const ai_batch_item* it, int32_t kernel, double* y0s, double* fins,
                           double* obss, int64_t ld, uint64_t seq, uint64_t done_target,
-                          ai_resident_desc* out) {
+                          const unsigned* order, ai_resident_desc* out) {
   std::memset(out, 0, sizeof *out);
   ResidentDesc d;
   std::memset(&d, 0, sizeof d);
@@ -2675,10 +2682,30 @@ void ai_resident_describe(const ai_batch_item* it, int32_t kernel, double* y0s, 
   d.P.y0 = y0s;
   d.P.yf = fins;
   d.P.obs = obss;
+  d.P.order = order;
   d.seq = (long long)seq;
   d.target = (long long)done_target;
   d.fp32 = (kernel & AI_FP32_STAGES) ? 1 : 0;
   std::memcpy(out, &d, sizeof d);
+}
+
+int ai_resident_order(const ai_batch_item* it, const double* y0, int64_t ld, hipStream_t s,
+                      const unsigned** order, void** ws) {
+  *order = nullptr;
+  *ws = nullptr;
+  const double rtol = it->rtol < 100.0 * 2.220446049250313e-16 ? 100.0 * 2.220446049250313e-16
+                                                                : it->rtol;
+  unsigned* o = nullptr;
+  unsigned* key = nullptr;
+  const hipError_t e = ai_longest_first_order(
+      y0, it->n, ld, order_model(&it->params, it->t0, it->tmax, rtol, false), &o, &key, ws, s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? fail(AI_ENOMEM, "request order: %s", hipGetErrorString(e))
+                                    : hip_fail(e, "request order");
+  }
+  *order = o;
+  return AI_OK;
 }
 
 int ai_resident_launch(const ai_resident_args* a, hipStream_t s, int64_t* waves) {

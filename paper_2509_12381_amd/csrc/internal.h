@@ -53,7 +53,20 @@ struct ai_resident_args {
 // AI_KERNEL_PLAIN, optionally | AI_FP32_STAGES.
 void ai_resident_describe(const ai_batch_item* item, int32_t kernel, double* y0s, double* fins,
                           double* obss, int64_t ld, uint64_t seq, uint64_t done_target,
-                          ai_resident_desc* out);
+                          const unsigned* order, ai_resident_desc* out);
+
+// Requests of at least this many trajectories, published while the resident
+// kernel is not running, are taken longest predicted first (the order of the
+// single-ensemble schedule); others in index order.
+constexpr int64_t AI_RESIDENT_ORDER_MIN = 4096;
+
+// Enqueue on s the longest-first order of the item's trajectories, whose
+// initial states are at y0 (planes of ld): *order receives the permutation
+// (device memory, valid once the work on s has run) and *ws the allocation
+// that holds it, to be released with hipFreeAsync once the request has
+// completed.  AI_OK or a negative ai_rc.
+int ai_resident_order(const ai_batch_item* item, const double* y0, int64_t ld, hipStream_t s,
+                      const unsigned** order, void** ws);
 
 // Launch the resident kernel on s with one wave per resident slot of the
 // device; *waves receives the grid size.  AI_OK or a negative ai_rc.

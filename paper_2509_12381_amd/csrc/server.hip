@@ -54,6 +54,7 @@ struct Request {
   bool staged = false;  // buffers in host memory: integrated from and into the slab
   uint64_t seq = 0;
   hipEvent_t copied_in = nullptr, copied_out = nullptr;
+  void* order_ws = nullptr;  // the request's longest-first order (stream-ordered allocation)
 };
 
 // Footprint of a request of n trajectories: initial states, final states and
@@ -260,6 +261,10 @@ void ai_server::finish(const RequestPtr& r, int rc, const std::string& error) {
   if (r->copied_in) (void)hipEventDestroy(r->copied_in);
   if (r->copied_out) (void)hipEventDestroy(r->copied_out);
   r->copied_in = r->copied_out = nullptr;
+  // the kernel reads a request's order only before its last trajectory is
+  // counted done, so it is released once the completion has been seen
+  if (r->order_ws) (void)hipFreeAsync(r->order_ws, streams[2]);
+  r->order_ws = nullptr;
   const double end = now_s();
   std::lock_guard<std::mutex> lock(mu);
   if (r->slab_len) {
@@ -298,6 +303,13 @@ void ai_server::dispatch() {
   args.refill_min = refill_min;
   args.idle_ticks = (int64_t)(idle_ms * 1e5);  // 100 MHz clock
   int64_t in_flight_traj = 0;
+  // a burst of submissions is published whole before a launch: the kernel is
+  // launched once no request has been admitted for LAUNCH_QUIET_S, once the
+  // first published request has waited LAUNCH_WAIT_S, or at once when queued
+  // requests cannot be admitted (the budget or the ring is full)
+  constexpr double LAUNCH_QUIET_S = 1e-3, LAUNCH_WAIT_S = 0.05;
+  double last_admit_s = 0.0, waiting_since_s = -1.0;
+  bool admission_blocked = false;
 
   auto hip_error = [](hipError_t e, const char* what) {
     (void)hipGetLastError();
@@ -324,16 +336,22 @@ void ai_server::dispatch() {
         admit.push_back(r);
         queue.pop_front();
       }
+      admission_blocked = !queue.empty();
       if (admit.empty() && queue.empty() && staging.empty() && running.empty() &&
           draining.empty() && stopping)
         break;
     }
+    if (!admit.empty()) last_admit_s = now_s();
     // publication, in request order on the copy stream: the initial states
     // into the slab (host-memory requests), the descriptor into the device
     // ring, the slot's claim counter (request << 32), then the new
     // request count into the device word the kernel reads; the kernel sees a
     // request only once all of it is in device memory and never reads host
     // memory for it
+    // the order's kernels, like the copies, wait for compute units while the
+    // kernel's waves live: a request published to a running kernel is taken
+    // in index order, one published while it is down longest first
+    const bool kernel_alive = kernel_running && hipEventQuery(kernel_done) == hipErrorNotReady;
     for (const RequestPtr& r : admit) {
       const ai_batch_item& it = r->item;
       const size_t pb = plane_bytes(it.n);
@@ -344,18 +362,31 @@ void ai_server::dispatch() {
         continue;
       }
       slot_total[slot] += (uint64_t)it.n;
-      if (r->staged)
-        ai_resident_describe(&it, r->kernel, y0s, y0s + 12 * pb / 8, y0s + 24 * pb / 8,
-                             (int64_t)(pb / 8), r->seq, slot_total[slot], &desc[slot]);
-      else
-        ai_resident_describe(&it, r->kernel, const_cast<double*>(it.y0), it.final_state, it.obs,
-                             it.ld, r->seq, slot_total[slot], &desc[slot]);
       pub_src[slot] = r->seq + 1;
       claim_src[slot] = r->seq << 32;
       hipError_t e = hipEventCreateWithFlags(&r->copied_in, hipEventDisableTiming);
       if (e == hipSuccess && r->staged)
         e = hipMemcpy2DAsync(y0s, pb, it.y0, (size_t)it.ld * 8, (size_t)it.n * 8, 12,
                              hipMemcpyDefault, in_stream);
+      // a large request's trajectories are taken longest predicted first: its
+      // order is computed on the copy stream from the initial states the
+      // kernel will read, before the descriptor that points to it
+      const double* y0_dev = r->staged ? y0s : it.y0;
+      const int64_t ld_dev = r->staged ? (int64_t)(pb / 8) : it.ld;
+      const unsigned* order = nullptr;
+      if (e == hipSuccess && it.n >= AI_RESIDENT_ORDER_MIN && !kernel_alive &&
+          ai_resident_order(&it, y0_dev, ld_dev, in_stream, &order, &r->order_ws) != AI_OK) {
+        broken = true;
+        (void)hipStreamSynchronize(in_stream);
+        finish(r, AI_EHIP, ai_last_error());
+        continue;
+      }
+      if (r->staged)
+        ai_resident_describe(&it, r->kernel, y0s, y0s + 12 * pb / 8, y0s + 24 * pb / 8,
+                             (int64_t)(pb / 8), r->seq, slot_total[slot], order, &desc[slot]);
+      else
+        ai_resident_describe(&it, r->kernel, const_cast<double*>(it.y0), it.final_state, it.obs,
+                             it.ld, r->seq, slot_total[slot], order, &desc[slot]);
       if (e == hipSuccess)
         e = hipMemcpyAsync(dev_ring + slot, desc + slot, sizeof(ai_resident_desc),
                            hipMemcpyHostToDevice, in_stream);
@@ -404,7 +435,15 @@ void ai_server::dispatch() {
     // publication enqueued so far has completed: it then starts with all of
     // them in view instead of holding the rest back until its waves leave
     if (kernel_running && hipEventQuery(kernel_done) != hipErrorNotReady) kernel_running = false;
+    bool launch_now = false;
     if (!running.empty() && !kernel_running && staging.empty()) {
+      const double t = now_s();
+      if (waiting_since_s < 0.0) waiting_since_s = t;
+      launch_now = admission_blocked || t - last_admit_s >= LAUNCH_QUIET_S ||
+                   t - waiting_since_s >= LAUNCH_WAIT_S;
+    }
+    if (launch_now) {
+      waiting_since_s = -1.0;
       int64_t waves = 0;
       const int lrc = ai_resident_launch(&args, kstream, &waves);
       const hipError_t e = lrc == AI_OK ? hipEventRecord(kernel_done, kstream) : hipSuccess;
